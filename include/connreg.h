@@ -1,0 +1,216 @@
+/* connreg.h -- C ABI of libconnreg, the MI355X (gfx950) solver for spatial
+ * connectome regression by the greedy rank-one ALS + Galerkin method of
+ * Kuerschner, Dolgov, Harris & Benner, "Greedy low-rank algorithm for
+ * spatial connectome regression".
+ *
+ * Problem (eq. obj_fun without the sign constraint):
+ *     min_W 1/2 ||P_Omega(W X - Y)||_F^2 + lambda/2 ||L_y W + W L_x^T||_F^2
+ * with normal equation (eq. multitermSylv)
+ *     A(W) = lambda (W L_x^2 + 2 L_y W L_x + L_y^2 W)
+ *            + sum_a diag(Omega_a) W X_a X_a^T  =  D = (Omega o Y) X^T.
+ * W (n_y x n_x) is never formed: it is kept as W = U Z V^T.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are column-major with an explicit leading dimension (ld >= rows).
+ *  - Pointers marked [dev] are device pointers (HIP global memory, e.g. torch
+ *    tensors); [host] are host pointers.  The caller owns every array it
+ *    passes; the library never frees caller memory.  The problem handle owns
+ *    copies of the problem data and its workspace (allocated at create or on
+ *    first use, freed at destroy).
+ *  - Work is enqueued on the handle's stream.  Entry points that return host
+ *    scalars (norms, statistics) synchronise that stream before returning.
+ *  - Return values: CR_OK = 0; negative = hard error, outputs undefined, a
+ *    message is available from cr_last_error(); positive = soft status,
+ *    outputs valid (a cap was hit, or a breakdown ended the greedy loop).
+ *  - One handle per stream; a handle is not thread-safe.
+ */
+#ifndef CONNREG_H
+#define CONNREG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CR_OK = 0,
+  CR_EINVAL = -1,      /* invalid argument (sizes, layout, non-Laplacian input) */
+  CR_ENOMEM = -2,      /* device allocation failed                              */
+  CR_EHIP = -3,        /* a HIP runtime call failed                             */
+  CR_ENONFINITE = -4,  /* NaN/Inf met in inputs or iterates                     */
+  CR_NOTCONV = 1,      /* an inner or outer iteration cap was hit               */
+  CR_BREAKDOWN = 2,    /* new ALS vector lies in span(U) or span(V): stopped    */
+  CR_PC_FALLBACK = 3   /* the learned preconditioner was replaced by Jacobi     */
+} cr_status;
+
+typedef enum {
+  CR_PREC_FP64 = 0,    /* every vector, product and reduction in FP64            */
+  CR_PREC_MIXED = 1    /* FP32 vectors/products with FP64 reductions, FP64
+                          Galerkin solve, residual and stopping test             */
+} cr_precision;
+
+/* Graph Laplacian L = Deg - Adj of a voxel face-adjacency graph, CSR, [host].
+ * Must be symmetric with off-diagonal entries -1, diagonal = number of
+ * off-diagonal entries in the row, at most 8 neighbours per voxel; anything
+ * else is rejected with CR_EINVAL (the paper's L_x, L_y are such graph
+ * Laplacians: section on the mathematical formulation). */
+typedef struct {
+  int64_t n;
+  const int32_t* rowptr;   /* n+1 */
+  const int32_t* colidx;   /* rowptr[n] */
+  const double* val;       /* rowptr[n] */
+} cr_csr;
+
+typedef struct {
+  cr_csr Ly;               /* target Laplacian, n_y x n_y                      */
+  cr_csr Lx;               /* source Laplacian, n_x x n_x                      */
+  int64_t n_inj;           /* number of injections                             */
+  const double* X;  int64_t ldx;    /* [dev] n_x x n_inj injection densities   */
+  const double* Y;  int64_t ldy;    /* [dev] n_y x n_inj target densities      */
+  const uint8_t* Omega; int64_t ldo;/* [dev] n_y x n_inj, 1 = observed (the
+                                       paper's convention, not the stored 1-Omega) */
+  double lambda;           /* operator lambda (lambda = lambda_bar n_inj / n_x
+                              is the caller's choice)                          */
+} cr_problem_desc;
+
+typedef struct cr_problem cr_problem;
+
+/* Copies the Laplacians (host) and X, Y, Omega (device) into handle-owned
+ * device storage: an ELL neighbour table per Laplacian, Omega as a bitmask
+ * plus per-injection lists of unobserved voxels, Omega o Y and X in the
+ * working precision.  `hip_stream` is a hipStream_t (NULL = default stream).
+ * Errors: CR_EINVAL for bad sizes or a non-graph-Laplacian, CR_ENOMEM, CR_EHIP. */
+cr_status cr_problem_create(const cr_problem_desc* desc, cr_precision prec, void* hip_stream,
+                            cr_problem** out);
+void cr_problem_destroy(cr_problem* p);
+
+/* ||D||_F = ||(Omega o Y) X^T||_F (FP64; synchronises). */
+cr_status cr_rhs_norm(cr_problem* p, double* out);
+
+/* Factored application of the operator of eq. multitermSylv to W = U Z V^T,
+ * U [dev] n_y x r, Z [dev] r x r, V [dev] n_x x r.  Outputs [dev]:
+ *   F (n_y x (2r + n_inj), ldf) = [ L_y U | L_y^2 U | Omega o (U Z H) ],
+ *   G (n_x x 2r, ldg)           = [ L_x V | L_x^2 V ],      H = V^T X,
+ * so that, with L_x symmetric,
+ *   A(U Z V^T) = lambda (U Z G_2^T + 2 F_1 Z G_1^T + F_2 Z V^T) + F_3 X^T.
+ * r = 0 is allowed (F = [0 columns | Omega o 0]).  Asynchronous.
+ * _f32: the same in FP32 storage (accumulation in FP32 for the products,
+ * FP64 for H); requires a handle created with CR_PREC_MIXED or FP64 (both
+ * keep FP32 copies of X). */
+cr_status cr_op_apply(cr_problem* p, int64_t r, const double* U, int64_t ldu, const double* Z,
+                      int64_t ldz, const double* V, int64_t ldv, double* F, int64_t ldf,
+                      double* G, int64_t ldg);
+cr_status cr_op_apply_f32(cr_problem* p, int64_t r, const float* U, int64_t ldu, const float* Z,
+                          int64_t ldz, const float* V, int64_t ldv, float* F, int64_t ldf,
+                          float* G, int64_t ldg);
+
+/* Solver options (Algorithm 1 and its sub-solvers).  Obtain defaults from
+ * cr_solve_opts_default() and override fields. */
+typedef struct {
+  int32_t max_rank;        /* Algorithm 1 rank cap r                                  */
+  double tau_dW;           /* stop when delta W <= tau_dW (0 = off)                   */
+  double tau_res;          /* stop when ||D - A(W)||_F / ||D||_F <= tau_res (0 = off) */
+  double als_delta;        /* ALS stop: | ||u_hat||/||v_hat|| - 1 | <= als_delta (0.1) */
+  int32_t als_max_sweeps;  /* ALS sweep cap (10)                                      */
+  int32_t als_fixed_sweeps;/* > 0: exactly this many sweeps (lockstep comparisons)    */
+  double pcg_rtol;         /* inner PCG relative residual (1e-8)                      */
+  int32_t pcg_maxit;       /* inner PCG iteration cap (5000)                          */
+  double galerkin_rtol;    /* projected CG tolerance; <= 0: tau/2 (tau = tau_res, else tau_dW) */
+  int32_t galerkin_maxit;  /* projected CG cap; <= 0: 50 r + 200                      */
+  uint64_t seed;           /* SplitMix64 seed of the initial ALS vectors              */
+  double orth_tol;         /* breakdown when ||x_perp|| <= orth_tol ||x|| (1e-10)      */
+  int32_t pcg_vpt;         /* voxels per thread in the PCG kernel (0 = auto)          */
+  int32_t verbose;         /* 1: one line per rank on stderr                          */
+} cr_solve_opts;
+
+void cr_solve_opts_default(cr_solve_opts* o);
+
+typedef struct {
+  int32_t sweeps;          /* ALS sweeps done                               */
+  double delta;            /* last | ||u_hat||/||v_hat|| - 1 |              */
+  double unorm, vnorm;     /* last ||u_hat||, ||v_hat||                     */
+  int32_t pcg_iters_u;     /* total PCG iterations, u-systems               */
+  int32_t pcg_iters_v;     /* total PCG iterations, v-systems               */
+  int32_t pcg_notconv;     /* number of inner solves that hit pcg_maxit     */
+} cr_als_stats;
+
+/* One rank-1 ALS update (eqs. ALS_linsys and ALS_linsys_v, the inner loop of
+ * Algorithm 1) for the residual R = D - A(U Z V^T) of the current iterate
+ * (r >= 0 columns; U, V orthonormal is not required here).
+ * v_io [dev] n_x: in = initial vector (normalised internally), out = unit v.
+ * u_out [dev] n_y: out = unit u.  Inner systems are solved by Jacobi PCG.
+ * Synchronises (reads the sweep test).  Soft status CR_NOTCONV when an inner
+ * solve hit its cap. */
+cr_status cr_als_step(cr_problem* p, int64_t r, const double* U, int64_t ldu, const double* Z,
+                      int64_t ldz, const double* V, int64_t ldv, double* v_io, double* u_out,
+                      const cr_solve_opts* opts, cr_als_stats* stats);
+
+/* Galerkin refinement (eq. Proj_Sylv): assembles U^T diag(Omega_a) U,
+ * V^T X, U^T L_y U, U^T L_y^2 U, V^T L_x V, V^T L_x^2 V, U^T (Omega o Y) from
+ * U [dev] n_y x r and V [dev] n_x x r (orthonormal columns expected), then
+ * solves the projected equation for Z by matrix-valued CG in FP64 from the
+ * warm start Z_io [dev] r x r (ldz) until
+ *   ||U^T D V - A_p(Z)||_F <= rtol ||U^T D V||_F   or maxit iterations.
+ * Z_io out = solution.  iters_out [host] may be NULL.  Synchronises.
+ * Soft status CR_NOTCONV when maxit was hit. */
+cr_status cr_galerkin_project(cr_problem* p, int64_t r, const double* U, int64_t ldu,
+                              const double* V, int64_t ldv, double* Z_io, int64_t ldz,
+                              double rtol, int32_t maxit, int32_t* iters_out);
+
+/* FP64 residual norm ||D - A(U Z V^T)||_F and its value relative to ||D||_F
+ * (the outer stopping test), from the factored residual R = F_R G_R^T with
+ * F_R = [Omega o (Y - U Z H) | U | L_y U | L_y^2 U] and
+ * G_R = [X | -lambda L_x^2 V Z^T | -2 lambda L_x V Z^T | -lambda V Z^T]
+ * via ||R||_F^2 = trace((F_R^T F_R)(G_R^T G_R)).  The Gram form loses about
+ * half the digits: its absolute error is near sqrt(eps) ||F_R|| ||G_R||.
+ * abs_out / rel_out [host].  Synchronises. */
+cr_status cr_residual_norm(cr_problem* p, int64_t r, const double* U, int64_t ldu, const double* Z,
+                           int64_t ldz, const double* V, int64_t ldv, double* abs_out,
+                           double* rel_out);
+
+typedef struct {
+  int32_t rank;            /* rank j just completed                         */
+  double relres;           /* ||D - A(W_j)||_F / ||D||_F                    */
+  double dW;               /* ||W_j - W_{j-1}||_F / ||W_j||_F               */
+  double energy;           /* 1/2 <W,A(W)> - <W,D>                          */
+  int32_t sweeps;          /* ALS sweeps                                    */
+  int32_t pcg_iters;       /* PCG iterations of this rank (u and v)         */
+  int32_t galerkin_iters;  /* projected CG iterations                       */
+  double seconds;          /* wall time since the solve started             */
+} cr_rank_info;
+
+typedef struct {
+  int32_t rank;            /* final rank                                    */
+  double relres, dW;       /* at the final rank                             */
+  int64_t pcg_iters;       /* total PCG iterations                          */
+  int64_t galerkin_iters;  /* total projected CG iterations                 */
+  int32_t pcg_notconv;     /* inner solves that hit their cap               */
+  double seconds;          /* wall time of the call                         */
+} cr_solve_stats;
+
+typedef void (*cr_rank_cb)(const cr_rank_info* info, void* user);
+
+/* Algorithm 1 (greedy rank-1 ALS + Galerkin) with outer stop on rank,
+ * delta W and the relative residual.  U [dev] n_y x max_rank (ld n_y),
+ * V [dev] n_x x max_rank (ld n_x), Z [dev] max_rank x max_rank (ld max_rank);
+ * on return the leading rank columns hold orthonormal bases and the core.
+ * *rank_io [host]: in = rank to resume from (0 = start from W = 0; otherwise
+ * U, V, Z hold a previous result whose U, V are orthonormal), out = final
+ * rank.  cb (may be NULL) is called after every rank.  Synchronises.
+ * Soft statuses: CR_BREAKDOWN (new direction in the span of the basis),
+ * CR_NOTCONV (max_rank reached with a tolerance set and not met). */
+cr_status cr_greedy_solve(cr_problem* p, const cr_solve_opts* opts, double* U, double* V,
+                          double* Z, int64_t* rank_io, cr_solve_stats* stats, cr_rank_cb cb,
+                          void* user);
+
+/* Message of the last hard error on this thread ("" if none). */
+const char* cr_last_error(void);
+
+/* Library version string. */
+const char* cr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CONNREG_H */

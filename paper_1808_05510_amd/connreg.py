@@ -1,0 +1,294 @@
+"""Python binding of libconnreg (ctypes).  Argument marshalling only: every
+step of the solver runs in the HIP library; torch supplies device memory and
+the stream.  Loading fails loudly when the library has not been built.
+
+Matrices cross the boundary column-major: a column-major n x k matrix is a
+torch tensor of shape (n, k) with strides (1, ld).  ``colmajor`` makes one.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_uint64, c_void_p
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libconnreg.so")
+
+CR_OK, CR_EINVAL, CR_ENOMEM, CR_EHIP, CR_ENONFINITE = 0, -1, -2, -3, -4
+CR_NOTCONV, CR_BREAKDOWN, CR_PC_FALLBACK = 1, 2, 3
+STATUS_NAMES = {0: "ok", -1: "einval", -2: "enomem", -3: "ehip", -4: "enonfinite",
+                1: "notconv", 2: "breakdown", 3: "pc_fallback"}
+PREC = {"fp64": 0, "mixed": 1}
+
+EXPORTS = ["cr_problem_create", "cr_problem_destroy", "cr_rhs_norm", "cr_op_apply",
+           "cr_op_apply_f32", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
+           "cr_residual_norm", "cr_greedy_solve", "cr_last_error", "cr_version"]
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("rowptr", c_void_p), ("colidx", c_void_p), ("val", c_void_p)]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("Ly", CSR), ("Lx", CSR), ("n_inj", c_int64),
+                ("X", c_void_p), ("ldx", c_int64), ("Y", c_void_p), ("ldy", c_int64),
+                ("Omega", c_void_p), ("ldo", c_int64), ("lambda_", c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("max_rank", c_int32), ("tau_dW", c_double), ("tau_res", c_double),
+                ("als_delta", c_double), ("als_max_sweeps", c_int32),
+                ("als_fixed_sweeps", c_int32), ("pcg_rtol", c_double), ("pcg_maxit", c_int32),
+                ("galerkin_rtol", c_double), ("galerkin_maxit", c_int32), ("seed", c_uint64),
+                ("orth_tol", c_double), ("pcg_vpt", c_int32), ("verbose", c_int32)]
+
+
+class ALSStats(ctypes.Structure):
+    _fields_ = [("sweeps", c_int32), ("delta", c_double), ("unorm", c_double),
+                ("vnorm", c_double), ("pcg_iters_u", c_int32), ("pcg_iters_v", c_int32),
+                ("pcg_notconv", c_int32)]
+
+
+class RankInfo(ctypes.Structure):
+    _fields_ = [("rank", c_int32), ("relres", c_double), ("dW", c_double), ("energy", c_double),
+                ("sweeps", c_int32), ("pcg_iters", c_int32), ("galerkin_iters", c_int32),
+                ("seconds", c_double)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("rank", c_int32), ("relres", c_double), ("dW", c_double),
+                ("pcg_iters", c_int64), ("galerkin_iters", c_int64), ("pcg_notconv", c_int32),
+                ("seconds", c_double)]
+
+
+RANK_CB = ctypes.CFUNCTYPE(None, POINTER(RankInfo), c_void_p)
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libconnreg.so (raises when it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(hipcc, gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(path)
+    P = c_void_p
+    L.cr_problem_create.argtypes = [POINTER(ProblemDesc), ctypes.c_int, P, POINTER(P)]
+    L.cr_problem_destroy.argtypes = [P]
+    L.cr_problem_destroy.restype = None
+    L.cr_rhs_norm.argtypes = [P, POINTER(c_double)]
+    L.cr_op_apply.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, c_int64, P,
+                              c_int64]
+    L.cr_op_apply_f32.argtypes = L.cr_op_apply.argtypes
+    L.cr_solve_opts_default.argtypes = [POINTER(SolveOpts)]
+    L.cr_solve_opts_default.restype = None
+    L.cr_als_step.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, P,
+                              POINTER(SolveOpts), POINTER(ALSStats)]
+    L.cr_galerkin_project.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, c_double,
+                                      c_int32, POINTER(c_int32)]
+    L.cr_residual_norm.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64,
+                                   POINTER(c_double), POINTER(c_double)]
+    L.cr_greedy_solve.argtypes = [P, POINTER(SolveOpts), P, P, P, POINTER(c_int64),
+                                  POINTER(SolveStats), RANK_CB, P]
+    L.cr_last_error.restype = ctypes.c_char_p
+    L.cr_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        L[name].restype = L[name].restype if name in (
+            "cr_problem_destroy", "cr_solve_opts_default", "cr_last_error", "cr_version") \
+            else ctypes.c_int
+    _lib = L
+    return L
+
+
+class ConnRegError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status):
+    if status < 0:
+        raise ConnRegError(status, load().cr_last_error().decode())
+    return status
+
+
+def colmajor(a, device="cuda:0", dtype=torch.float64) -> torch.Tensor:
+    """(n, k) tensor with column-major storage (strides (1, n))."""
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    a = np.asarray(a)
+    if a.ndim == 1:
+        a = a[:, None]
+    return torch.tensor(np.ascontiguousarray(a.T)).to(device=device, dtype=dtype).T
+
+
+def empty_colmajor(n, k, device="cuda:0", dtype=torch.float64) -> torch.Tensor:
+    return torch.empty((k, n), device=device, dtype=dtype).T
+
+
+def zeros_colmajor(n, k, device="cuda:0", dtype=torch.float64) -> torch.Tensor:
+    return torch.zeros((k, n), device=device, dtype=dtype).T
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() == 1 or t.shape[1] == 0:
+        return max(t.shape[0], 1)
+    if t.stride(0) != 1 and t.shape[0] > 1:
+        raise ValueError("matrix must be column-major (stride(0) == 1)")
+    return max(t.stride(1), t.shape[0]) if t.shape[1] > 1 else t.shape[0]
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load().cr_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """A problem handle on one device (see include/connreg.h)."""
+
+    def __init__(self, data: dict, precision: str = "fp64", device: str = "cuda:0",
+                 lam: float | None = None, stream: torch.cuda.Stream | None = None):
+        L = load()
+        self.device = torch.device(device)
+        self.precision = precision
+        with torch.cuda.device(self.device):
+            self.stream = stream or torch.cuda.current_stream(self.device)
+        self._host = {}
+        for k in ("Ly", "Lx"):
+            self._host[k] = (np.ascontiguousarray(data[k + "_rowptr"], np.int32),
+                             np.ascontiguousarray(data[k + "_colidx"], np.int32),
+                             np.ascontiguousarray(data[k + "_val"], np.float64))
+        self.n_y = self._host["Ly"][0].size - 1
+        self.n_x = self._host["Lx"][0].size - 1
+        self.n_inj = int(np.asarray(data["X"]).shape[1])
+        self.lam = float(data["lam"] if lam is None else lam)
+        X = colmajor(data["X"], self.device)
+        Y = colmajor(data["Y"], self.device)
+        Om = colmajor(np.asarray(data["Omega"], np.uint8), self.device, torch.uint8)
+
+        def csr(k):
+            rp, ci, v = self._host[k]
+            return CSR(rp.size - 1, rp.ctypes.data, ci.ctypes.data, v.ctypes.data)
+
+        d = ProblemDesc(csr("Ly"), csr("Lx"), self.n_inj, X.data_ptr(), _ld(X), Y.data_ptr(),
+                        _ld(Y), Om.data_ptr(), _ld(Om), self.lam)
+        h = c_void_p()
+        torch.cuda.synchronize(self.device)
+        _check(L.cr_problem_create(ctypes.byref(d), PREC[precision],
+                                   c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self._dtype = torch.float64
+
+    # -------------------------------------------------------------- helpers
+    def close(self):
+        if getattr(self, "h", None):
+            load().cr_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _col(self, a, dtype=torch.float64):
+        if isinstance(a, torch.Tensor) and a.device == self.device and a.dtype == dtype and \
+                (a.dim() == 1 or a.stride(0) == 1):
+            return a
+        return colmajor(a, self.device, dtype)
+
+    def rhs_norm(self) -> float:
+        out = c_double()
+        _check(load().cr_rhs_norm(self.h, ctypes.byref(out)))
+        return out.value
+
+    # -------------------------------------------------------------- entry points
+    def op_apply(self, U, Z, V, fp32: bool = False):
+        """Returns (F, G) with F = [L_y U | L_y^2 U | Omega o (U Z H)] and
+        G = [L_x V | L_x^2 V] (column-major device tensors)."""
+        dt = torch.float32 if fp32 else torch.float64
+        r = int(U.shape[1])
+        U, Z, V = self._col(U, dt), self._col(Z, dt), self._col(V, dt)
+        F = empty_colmajor(self.n_y, 2 * r + self.n_inj, self.device, dt)
+        G = empty_colmajor(self.n_x, max(2 * r, 1), self.device, dt)
+        fn = load().cr_op_apply_f32 if fp32 else load().cr_op_apply
+        _check(fn(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1), _ptr(V), _ld(V),
+                  _ptr(F), _ld(F), _ptr(G), _ld(G)))
+        return F, G[:, : 2 * r]
+
+    def als_step(self, U, Z, V, v0, **opts):
+        r = int(U.shape[1])
+        U, Z, V = self._col(U), self._col(Z), self._col(V)
+        v = self._col(v0).reshape(-1).clone()
+        u = torch.empty(self.n_y, device=self.device, dtype=torch.float64)
+        o = default_opts(**opts)
+        st = ALSStats()
+        s = _check(load().cr_als_step(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1),
+                                      _ptr(V), _ld(V), _ptr(v), _ptr(u), ctypes.byref(o),
+                                      ctypes.byref(st)))
+        stats = {f: getattr(st, f) for f, _ in ALSStats._fields_}
+        stats["status"] = STATUS_NAMES[s]
+        return u, v, stats
+
+    def galerkin_project(self, U, V, Z0=None, rtol=1e-12, maxit=0):
+        r = int(U.shape[1])
+        U, V = self._col(U), self._col(V)
+        Z = zeros_colmajor(r, r, self.device) if Z0 is None else self._col(Z0).clone()
+        it = c_int32()
+        s = _check(load().cr_galerkin_project(self.h, r, _ptr(U), _ld(U), _ptr(V), _ld(V),
+                                              _ptr(Z), _ld(Z), rtol, maxit, ctypes.byref(it)))
+        return Z, it.value, STATUS_NAMES[s]
+
+    def residual_norm(self, U, Z, V):
+        r = int(U.shape[1])
+        U, Z, V = self._col(U), self._col(Z), self._col(V)
+        a, b = c_double(), c_double()
+        _check(load().cr_residual_norm(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1),
+                                       _ptr(V), _ld(V), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def greedy_solve(self, resume=None, **opts):
+        """Algorithm 1.  Returns dict(U, V, Z, rank, stats, history, status)."""
+        o = default_opts(**opts)
+        R = int(o.max_rank)
+        U = zeros_colmajor(self.n_y, R, self.device)
+        V = zeros_colmajor(self.n_x, R, self.device)
+        Z = zeros_colmajor(R, R, self.device)
+        rank = c_int64(0)
+        if resume is not None:
+            U0, Z0, V0 = resume
+            r0 = int(U0.shape[1])
+            U[:, :r0] = self._col(U0)
+            V[:, :r0] = self._col(V0)
+            Z[:r0, :r0] = self._col(Z0)
+            rank.value = r0
+        hist = []
+
+        def cb(info, user):
+            i = info.contents
+            hist.append({f: getattr(i, f) for f, _ in RankInfo._fields_})
+
+        cbf = RANK_CB(cb)
+        st = SolveStats()
+        torch.cuda.synchronize(self.device)
+        s = _check(load().cr_greedy_solve(self.h, ctypes.byref(o), _ptr(U), _ptr(V), _ptr(Z),
+                                          ctypes.byref(rank), ctypes.byref(st), cbf, None))
+        r = rank.value
+        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+        return dict(U=U[:, :r], V=V[:, :r], Z=Z[:r, :r], rank=r, stats=stats, history=hist,
+                    status=STATUS_NAMES[s])

@@ -1,0 +1,1351 @@
+// libconnreg host side: problem handle, workspace, the C ABI entry points and
+// the greedy driver (Algorithm 1 of the paper) on top of the kernels in
+// k_blas.hip and k_cg.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "cr_internal.hpp"
+
+namespace cr {
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+}  // namespace cr
+
+using namespace cr;
+
+// ===================================================================== handle
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct cr_problem {
+  hipStream_t st = nullptr;
+  cr_precision prec = CR_PREC_FP64;
+  int64_t ny = 0, nx = 0;
+  int ninj = 0;
+  double lam = 0.0;
+  Geom gy, gx;
+  double* X64 = nullptr;
+  double* OY64 = nullptr;
+  float* X32 = nullptr;
+  float* OY32 = nullptr;
+  uint32_t* bits = nullptr;
+  int32_t* hptr = nullptr;
+  int32_t* hidx = nullptr;
+  int64_t nholes = 0;
+  bool use_holes = false;
+  double dnorm = 0.0;
+  double* hscal = nullptr;  // pinned host scratch
+  std::map<std::string, DevBuf> ws;
+  std::vector<void*> owned;
+
+  template <typename T>
+  T* buf(const std::string& name, int64_t count) {
+    size_t need = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    DevBuf& b = ws[name];
+    if (b.bytes >= need) return (T*)b.p;
+    if (b.p) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    if (hipMalloc(&b.p, need) != hipSuccess) {
+      b.p = nullptr;
+      set_error("device allocation of workspace '" + name + "' (" + std::to_string(need) +
+                " bytes) failed");
+      return nullptr;
+    }
+    b.bytes = need;
+    return (T*)b.p;
+  }
+  template <typename T>
+  const T* X() const;
+  template <typename T>
+  const T* OY() const;
+};
+template <>
+const double* cr_problem::X<double>() const { return X64; }
+template <>
+const float* cr_problem::X<float>() const { return X32; }
+template <>
+const double* cr_problem::OY<double>() const { return OY64; }
+template <>
+const float* cr_problem::OY<float>() const { return OY32; }
+
+#define WS(T, name, count)                                   \
+  ({                                                         \
+    T* p_ = P->buf<T>(name, (count));                        \
+    if (!p_) return CR_ENOMEM;                               \
+    p_;                                                      \
+  })
+
+static int64_t gemm_part_cap(const cr_problem* P) {
+  (void)P;
+  return (int64_t)1 << 24;  // doubles (128 MB) of split-K partials
+}
+
+// ===================================================================== small kernels
+// coef for the factored residual products (see apply_R / apply_RT)
+__global__ void k_rcoef(int ninj, int r, const double* __restrict__ y0,
+                        const double* __restrict__ Z, int64_t ldz, int trans, double lam,
+                        double* __restrict__ coef) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ninj) {
+    coef[t] = y0[t];
+    return;
+  }
+  const int e = t - ninj;
+  if (e >= 3 * r) return;
+  const int blk = e / r, i = e % r;
+  // R   : coef blocks [-lam Z q3 | -2lam Z q2 | -lam Z q1] over [U | LU | L2U],
+  //       q = y0 blocks [V^T v | LV^T v | L2V^T v]  -> source block 2,1,0
+  // R^T : coef blocks [-lam Z^T e1 | -2lam Z^T e2 | -lam Z^T e3] over [L2V | LV | V],
+  //       e = y0 blocks [U^T u | LU^T u | L2U^T u] -> source block 0,1,2
+  const int src = trans ? blk : 2 - blk;
+  const double sc = (blk == 1 ? -2.0 : -1.0) * lam;
+  const double* q = y0 + ninj + (int64_t)src * r;
+  double s = 0.0;
+  if (trans)
+    for (int k = 0; k < r; ++k) s += Z[(int64_t)i * ldz + k] * q[k];
+  else
+    for (int k = 0; k < r; ++k) s += Z[(int64_t)k * ldz + i] * q[k];
+  coef[t] = sc * s;
+}
+
+__global__ void k_set2(double* dst, const double* s0, double f0, const double* s1, double f1) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dst[0] = f0 * s0[0];
+    dst[1] = f1 * s1[0];
+  }
+}
+
+// mirror column j of a symmetric matrix into row j
+__global__ void k_mirror(double* B, int64_t ld, int j) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k <= j) B[(int64_t)k * ld + j] = B[(int64_t)j * ld + k];
+}
+
+// G[a](k, j) = G[a](j, k) = C[k + a*ldc] for k <= j
+__global__ void k_scatter_gram(int ninj, int j, const double* __restrict__ C, int64_t ldc,
+                               double* __restrict__ G, int64_t ldr) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ninj * (j + 1)) return;
+  const int a = (int)(e / (j + 1)), k = (int)(e % (j + 1));
+  const double v = C[(int64_t)a * ldc + k];
+  double* Ga = G + (int64_t)a * ldr * ldr;
+  Ga[(int64_t)j * ldr + k] = v;
+  Ga[(int64_t)k * ldr + j] = v;
+}
+
+// C[k + a*ldc] = c0[k] for all a (k < m)
+__global__ void k_bcast_cols(int m, int ninj, const double* __restrict__ c0, double* C,
+                             int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * ninj) return;
+  C[(e / m) * ldc + e % m] = c0[e % m];
+}
+
+// Cm = blockdiag(I_ninj, s1 Z^T, s2 Z^T, s3 Z^T), k x k
+__global__ void k_build_cm(int ninj, int r, const double* __restrict__ Z, int64_t ldz, double lam,
+                           double* __restrict__ Cm) {
+  const int k = ninj + 3 * r;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)k * k) return;
+  const int i = (int)(e % k), j = (int)(e / k);
+  double v = 0.0;
+  if (i < ninj || j < ninj) {
+    v = (i == j) ? 1.0 : 0.0;
+  } else {
+    const int bi = (i - ninj) / r, bj = (j - ninj) / r;
+    if (bi == bj) {
+      const int ii = (i - ninj) % r, jj = (j - ninj) % r;
+      const double s = (bi == 1 ? -2.0 : -1.0) * lam;
+      v = s * Z[(int64_t)ii * ldz + jj];  // (Z^T)(ii, jj) = Z(jj, ii)
+    }
+  }
+  Cm[e] = v;
+}
+
+__global__ void k_neg(int n, const double* __restrict__ a, double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = -a[i];
+}
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// ===================================================================== solver context
+template <typename T>
+struct Ctx {
+  cr_problem* P;
+  hipStream_t st;
+  int64_t ny, nx;
+  int ninj;
+  double lam;
+  int rmax;  // capacity of the rank dimension (leading dimension of Grams)
+  // current iterate (bases in T, core in double)
+  T* U = nullptr;
+  int64_t ldu = 0;
+  T* V = nullptr;
+  int64_t ldv = 0;
+  T *LU = nullptr, *L2U = nullptr, *LV = nullptr, *L2V = nullptr;
+  double* Z = nullptr;
+  int64_t ldz = 0;
+  T* N = nullptr;
+  double *Ht = nullptr, *St = nullptr, *G = nullptr;
+  double *By1 = nullptr, *By2 = nullptr, *Bx1 = nullptr, *Bx2 = nullptr;
+  double* Tm = nullptr;
+  // vectors
+  T *vu = nullptr, *vv = nullptr, *rhs_u = nullptr, *rhs_v = nullptr, *dvec = nullptr;
+  T *minv_u = nullptr, *minv_v = nullptr, *Lv = nullptr, *Lu = nullptr;
+  T* pw_u[6];
+  T* pw_v[6];
+  double *y0 = nullptr, *coef = nullptr, *cu = nullptr, *cv = nullptr, *gw = nullptr;
+  double *sc = nullptr, *part = nullptr, *pcgpart = nullptr, *sbuf = nullptr, *gpart = nullptr;
+  double* tmp = nullptr;
+  int pcg_vpt_u = 1, pcg_vpt_v = 1, pcg_nwg_u = 1, pcg_nwg_v = 1;
+  // stats of the last ALS
+  int it_u = 0, it_v = 0, notconv = 0;
+
+  explicit Ctx(cr_problem* p)
+      : P(p), st(p->st), ny(p->ny), nx(p->nx), ninj(p->ninj), lam(p->lam), rmax(0) {}
+
+  const T* X() const { return P->X<T>(); }
+  const T* OY() const { return P->OY<T>(); }
+
+  // ------------------------------------------------------------ allocation
+  cr_status alloc_vectors(int vpt_opt) {
+    const int64_t nmax = std::max(ny, nx);
+    vu = WS(T, "vu", ny);
+    vv = WS(T, "vv", nx);
+    rhs_u = WS(T, "rhs_u", ny);
+    rhs_v = WS(T, "rhs_v", nx);
+    dvec = WS(T, "dvec", ny);
+    minv_u = WS(T, "minv_u", ny);
+    minv_v = WS(T, "minv_v", nx);
+    Lv = WS(T, "Lv", nx);
+    Lu = WS(T, "Lu", ny);
+    T* pw = WS(T, "pcgwork", 6 * nmax);
+    for (int k = 0; k < 6; ++k) {
+      pw_u[k] = pw + k * nmax;
+      pw_v[k] = pw + k * nmax;
+    }
+    const int kmax = ninj + 3 * std::max(rmax, 1) + 8;
+    y0 = WS(double, "y0", kmax);
+    coef = WS(double, "coef", kmax);
+    cu = WS(double, "cu", 4);
+    cv = WS(double, "cv", 4);
+    gw = WS(double, "gw", ninj);
+    sc = WS(double, "sc", 32);
+    tmp = WS(double, "tmp", 16);
+    sbuf = WS(double, "sbuf", ninj);
+    const int64_t pt = std::max(gemv_t_part_size(nmax, kmax), gemv_t_part_size(nmax, 1));
+    part = WS(double, "part", pt);
+    // PCG grid sizes
+    PcgArgs<T> probe{};
+    probe.g = P->gy;
+    probe.Xm = nullptr;
+    const int maxwg_u = pcg_max_wg<T>(probe);
+    probe.g = P->gx;
+    probe.Xm = X();
+    const int maxwg_v = pcg_max_wg<T>(probe);
+    if (maxwg_u <= 0 || maxwg_v <= 0) {
+      set_error("cooperative launch not available for the PCG kernel");
+      return CR_EHIP;
+    }
+    auto pick = [&](int64_t n, int maxwg, int& vpt, int& nwg) -> bool {
+      int v = vpt_opt > 0 ? vpt_opt : (int)std::min<int64_t>(8, std::max<int64_t>(1, (n + NT * 512 - 1) / (NT * 512)));
+      while (v <= 8) {
+        const int64_t w = std::max<int64_t>(1, (n + (int64_t)NT * v - 1) / ((int64_t)NT * v));
+        if (w <= maxwg) {
+          vpt = v;
+          nwg = (int)w;
+          return true;
+        }
+        v *= 2;
+      }
+      return false;
+    };
+    if (!pick(ny, maxwg_u, pcg_vpt_u, pcg_nwg_u) || !pick(nx, maxwg_v, pcg_vpt_v, pcg_nwg_v)) {
+      set_error("problem too large for one cooperative PCG grid");
+      return CR_EINVAL;
+    }
+    const int nwg = std::max(pcg_nwg_u, pcg_nwg_v);
+    pcgpart = WS(double, "pcgpart", (int64_t)(5 + ninj) * nwg);
+    return CR_OK;
+  }
+
+  cr_status alloc_rank(int rcap) {
+    rmax = std::max(rcap, 1);
+    const int64_t r2 = (int64_t)rmax * rmax;
+    LU = WS(T, "LU", ny * rmax);
+    L2U = WS(T, "L2U", ny * rmax);
+    LV = WS(T, "LV", nx * rmax);
+    L2V = WS(T, "L2V", nx * rmax);
+    N = WS(T, "N", ny * ninj);
+    Ht = WS(double, "Ht", (int64_t)ninj * rmax);
+    St = WS(double, "St", (int64_t)ninj * rmax);
+    G = WS(double, "G", (int64_t)ninj * r2);
+    By1 = WS(double, "By1", r2);
+    By2 = WS(double, "By2", r2);
+    Bx1 = WS(double, "Bx1", r2);
+    Bx2 = WS(double, "Bx2", r2);
+    Tm = WS(double, "Tm", (int64_t)rmax * ninj);
+    gpart = WS(double, "gpart", gemm_part_cap(P));
+    return CR_OK;
+  }
+
+  cr_status read_scalars(const double* dev, int count, double* host) {
+    CR_HIP(hipMemcpyAsync(P->hscal, dev, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+    CR_HIP(hipStreamSynchronize(st));
+    std::memcpy(host, P->hscal, sizeof(double) * count);
+    return CR_OK;
+  }
+
+  // ------------------------------------------------------------ derived data
+  // stencil columns [c0, c0+nc) of U, V into LU, L2U, LV, L2V
+  cr_status stencil_cols(int c0, int nc) {
+    CR_TRY(stencil<T>(P->gy, nc, U + c0 * ldu, ldu, LU + c0 * ny, ny, st));
+    CR_TRY(stencil<T>(P->gy, nc, LU + c0 * ny, ny, L2U + c0 * ny, ny, st));
+    CR_TRY(stencil<T>(P->gx, nc, V + c0 * ldv, ldv, LV + c0 * nx, nx, st));
+    CR_TRY(stencil<T>(P->gx, nc, LV + c0 * nx, nx, L2V + c0 * nx, nx, st));
+    return CR_OK;
+  }
+
+  // H^T = X^T V (ninj x r, ld ninj)
+  cr_status compute_Ht(int r) {
+    if (r == 0) return CR_OK;
+    Blocks<T> A, B;
+    A.clear();
+    B.clear();
+    A.add(X(), nx, ninj);
+    B.add(V, ldv, r);
+    return gemm_tn<T>(nx, A, B, nullptr, nullptr, 0, Ht, ninj, gpart, gemm_part_cap(P), st);
+  }
+
+  // N = OY - Omega o (U Z H)
+  cr_status build_N(int r) {
+    if (r > 0)
+      CR_TRY(small_gemm(r, ninj, r, Z, ldz, false, Ht, ninj, true, 1.0, Tm, r, st));
+    return masked_tall_gemm<T>(ny, r, ninj, U, ldu, Tm, r, P->bits, OY(), ny, N, ny, st);
+  }
+
+  // out = R v  (R = N X^T - lam (U Z L2V^T + 2 LU Z LV^T + L2U Z V^T)); y0 keeps
+  // [X^T v | V^T v | LV^T v | L2V^T v]
+  cr_status apply_R(int r, const T* v, T* out) {
+    Blocks<T> A;
+    A.clear();
+    A.add(X(), nx, ninj);
+    A.add(V, ldv, r);
+    A.add(LV, nx, r);
+    A.add(L2V, nx, r);
+    CR_TRY(gemv_t<T>(nx, A, v, y0, part, st));
+    const int k = ninj + 3 * r;
+    hipLaunchKernelGGL(k_rcoef, dim3(nblk(k, 128)), dim3(128), 0, st, ninj, r, y0, Z, ldz, 0,
+                       lam, coef);
+    CR_HIP(hipGetLastError());
+    Blocks<T> B;
+    B.clear();
+    B.add(N, ny, ninj);
+    B.add(U, ldu, r);
+    B.add(LU, ny, r);
+    B.add(L2U, ny, r);
+    return gemv_n<T>(ny, B, coef, 0.0, out, st);
+  }
+
+  // out = R^T u; y0 keeps [N^T u | U^T u | LU^T u | L2U^T u]
+  cr_status apply_RT(int r, const T* u, T* out) {
+    Blocks<T> A;
+    A.clear();
+    A.add(N, ny, ninj);
+    A.add(U, ldu, r);
+    A.add(LU, ny, r);
+    A.add(L2U, ny, r);
+    CR_TRY(gemv_t<T>(ny, A, u, y0, part, st));
+    const int k = ninj + 3 * r;
+    hipLaunchKernelGGL(k_rcoef, dim3(nblk(k, 128)), dim3(128), 0, st, ninj, r, y0, Z, ldz, 1,
+                       lam, coef);
+    CR_HIP(hipGetLastError());
+    Blocks<T> B;
+    B.clear();
+    B.add(X(), nx, ninj);
+    B.add(L2V, nx, r);
+    B.add(LV, nx, r);
+    B.add(V, ldv, r);
+    return gemv_n<T>(nx, B, coef, 0.0, out, st);
+  }
+
+  cr_status dot(int64_t n, const T* a, const T* b, double* out) {
+    Blocks<T> A;
+    A.clear();
+    A.add(a, n, 1);
+    return gemv_t<T>(n, A, b, out, part, st);
+  }
+
+  // ------------------------------------------------------------ ALS
+  cr_status pcg(bool usys, const T* b, T* xout, double rtol, int maxit, double* scal) {
+    PcgArgs<T> a{};
+    a.g = usys ? P->gy : P->gx;
+    a.lam = lam;
+    a.coef = usys ? cu : cv;
+    a.dvec = usys ? dvec : nullptr;
+    a.Xm = usys ? nullptr : X();
+    a.ldx = nx;
+    a.ninj = ninj;
+    a.gw = gw;
+    a.minv = usys ? minv_u : minv_v;
+    a.b = b;
+    T** w = usys ? pw_u : pw_v;
+    a.x = w[0];
+    a.r = w[1];
+    a.z = w[2];
+    a.p = w[3];
+    a.t = w[4];
+    a.q = w[5];
+    a.xout = xout;
+    a.part = pcgpart;
+    a.sbuf = sbuf;
+    a.scal = scal;
+    a.rtol = rtol;
+    a.maxit = maxit;
+    a.vpt = usys ? pcg_vpt_u : pcg_vpt_v;
+    return pcg_solve<T>(a, usys ? pcg_nwg_u : pcg_nwg_v, st);
+  }
+
+  struct SolveOut {
+    double norm = 0.0, relres = 0.0;
+    int iters = 0, status = 0;
+  };
+
+  cr_status dot64(int64_t n, const double* a, const double* b, double* out) {
+    Blocks<double> A;
+    A.clear();
+    A.add(a, n, 1);
+    return gemv_t<double>(n, A, b, out, part, st);
+  }
+
+  // Solve the u-system (usys) or the v-system for b; xout = unit solution.
+  // FP64: one PCG launch; its scalars stay in dsc[0..3] for a later read.
+  // Mixed: FP32 PCG corrections inside an FP64 residual-and-refinement loop
+  // (x accumulated in FP64, r = b - A x evaluated in FP64 arithmetic).
+  cr_status solve_sys(bool usys, const T* b, T* xout, double rtol, int maxit, double* dsc,
+                      SolveOut* out, bool& deferred) {
+    if (std::is_same<T, double>::value) {
+      deferred = true;
+      return pcg(usys, b, xout, rtol, maxit, dsc);
+    }
+    deferred = false;
+    const int64_t n = usys ? ny : nx;
+    const Geom& g = usys ? P->gy : P->gx;
+    double* x64 = WS(double, "ref_x", n);
+    double* r64 = WS(double, "ref_r", n);
+    double* t64 = WS(double, "ref_t", n);
+    T* rb = WS(T, "ref_b", n);
+    T** w = usys ? pw_u : pw_v;
+    const double in_rtol = std::max(rtol, 1e-5);
+    *out = SolveOut{};
+    double h[4], q[2];
+    CR_TRY(dot(n, b, b, tmp + 9));
+    CR_TRY(pcg(usys, b, xout, in_rtol, maxit, dsc));
+    CR_TRY(read_scalars(dsc, 4, h));
+    out->iters += (int)h[2];
+    if (h[3] == 2.0) {
+      out->status = 2;
+      return CR_OK;
+    }
+    CR_TRY(accumulate<T>(n, w[0], x64, true, st));
+    double rr = 0.0, bb = 0.0, rr_prev = -1.0;
+    for (int k = 0; k < 12; ++k) {
+      if (!usys) {
+        Blocks<T> A;
+        A.clear();
+        A.add(X(), nx, ninj);
+        CR_TRY((gemv_tx<T, double>(nx, A, x64, y0, part, st)));
+      }
+      CR_TRY(als_residual<T>(g, lam, usys ? cu : cv, usys ? dvec : nullptr,
+                             usys ? nullptr : X(), nx, ninj, gw, y0, b, x64, t64, r64, st));
+      CR_TRY(dot64(n, r64, r64, tmp + 10));
+      CR_TRY(read_scalars(tmp + 9, 2, q));
+      bb = q[0];
+      rr = q[1];
+      if (!(rr > rtol * rtol * bb)) break;
+      // stagnation at the FP64 floor of the residual: stop refining
+      if (rr_prev >= 0.0 && rr > 0.25 * rr_prev) break;
+      rr_prev = rr;
+      CR_TRY((convert2d<T, double>(n, 1, r64, n, rb, n, st)));
+      CR_TRY(pcg(usys, rb, xout, in_rtol, maxit, dsc));
+      CR_TRY(read_scalars(dsc, 4, h));
+      out->iters += (int)h[2];
+      if (h[3] == 2.0) break;
+      CR_TRY(accumulate<T>(n, w[0], x64, false, st));
+    }
+    out->relres = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    out->status = (rr <= rtol * rtol * bb) ? 0 : 1;
+    CR_TRY(dot64(n, x64, x64, tmp + 11));
+    CR_TRY(normalize_out<T>(n, x64, tmp + 11, xout, st));
+    CR_TRY(read_scalars(tmp + 11, 1, h));
+    out->norm = std::sqrt(std::max(h[0], 0.0));
+    return CR_OK;
+  }
+
+  // One ALS sweep: u from v (eq. ALS_linsys), then v from u (eq. ALS_linsys_v).
+  cr_status sweep(int r, T* v, T* u, double rtol, int maxit, SolveOut* ou, SolveOut* ov) {
+    bool du = false, dv = false;
+    // u-half
+    CR_TRY(stencil<T>(P->gx, 1, v, nx, Lv, nx, st));
+    CR_TRY(apply_R(r, v, rhs_u));  // y0[0:ninj] = h = X^T v
+    CR_TRY(masked_quad_ws<T>(ny, ninj, P->bits, y0, dvec, tmp + 8, st));
+    CR_TRY(dot(nx, Lv, v, tmp + 0));   // b = v^T L_x v
+    CR_TRY(dot(nx, Lv, Lv, tmp + 1));  // a = ||L_x v||^2
+    hipLaunchKernelGGL(k_set2, dim3(1), dim3(1), 0, st, cu, tmp + 0, 2.0, tmp + 1, 1.0);
+    CR_HIP(hipGetLastError());
+    CR_TRY(pcg_diag<T>(P->gy, lam, cu, dvec, nullptr, 0, 0, nullptr, minv_u, st));
+    CR_TRY(solve_sys(true, rhs_u, u, rtol, maxit, sc + 0, ou, du));
+    // v-half
+    CR_TRY(stencil<T>(P->gy, 1, u, ny, Lu, ny, st));
+    CR_TRY(apply_RT(r, u, rhs_v));
+    CR_TRY(masked_colsq<T>(ny, ninj, P->bits, u, gw, part, st));
+    CR_TRY(dot(ny, Lu, u, tmp + 2));   // c = u^T L_y u
+    CR_TRY(dot(ny, Lu, Lu, tmp + 3));  // e = ||L_y u||^2
+    hipLaunchKernelGGL(k_set2, dim3(1), dim3(1), 0, st, cv, tmp + 2, 2.0, tmp + 3, 1.0);
+    CR_HIP(hipGetLastError());
+    CR_TRY(pcg_diag<T>(P->gx, lam, cv, nullptr, X(), nx, ninj, gw, minv_v, st));
+    CR_TRY(solve_sys(false, rhs_v, v, rtol, maxit, sc + 4, ov, dv));
+    if (du || dv) {
+      double hs[8];
+      CR_TRY(read_scalars(sc, 8, hs));
+      if (du) *ou = SolveOut{hs[0], hs[1], (int)hs[2], (int)hs[3]};
+      if (dv) *ov = SolveOut{hs[4], hs[5], (int)hs[6], (int)hs[7]};
+    }
+    return CR_OK;
+  }
+
+  cr_status als(int r, T* v, T* u, const cr_solve_opts& o, cr_als_stats* stats, bool& zero_rhs) {
+    zero_rhs = false;
+    int sweeps = 0;
+    double delta = 0.0;
+    SolveOut su, sv;
+    it_u = it_v = notconv = 0;
+    const int fixed = o.als_fixed_sweeps;
+    while (true) {
+      CR_TRY(sweep(r, v, u, o.pcg_rtol, o.pcg_maxit, &su, &sv));
+      ++sweeps;
+      it_u += su.iters;
+      it_v += sv.iters;
+      notconv += (su.status == 1) + (sv.status == 1);
+      if (su.status == 2 || sv.status == 2 || !(su.norm > 0.0) || !(sv.norm > 0.0)) {
+        zero_rhs = true;
+        break;
+      }
+      delta = std::fabs(su.norm / sv.norm - 1.0);
+      if (fixed > 0) {
+        if (sweeps >= fixed) break;
+      } else if (delta <= o.als_delta || sweeps >= o.als_max_sweeps) {
+        break;
+      }
+    }
+    if (stats) {
+      stats->sweeps = sweeps;
+      stats->delta = delta;
+      stats->unorm = su.norm;
+      stats->vnorm = sv.norm;
+      stats->pcg_iters_u = it_u;
+      stats->pcg_iters_v = it_v;
+      stats->pcg_notconv = notconv;
+    }
+    return CR_OK;
+  }
+
+  // x <- x - B (B^T x) twice, then normalise; breakdown when ||x_perp|| <= tol ||x||.
+  cr_status cgs2(int64_t n, const T* B, int64_t ldb, int j, T* x, double tol, bool& breakdown) {
+    double h[2];
+    CR_TRY(dot(n, x, x, tmp + 4));
+    if (j > 0) {
+      Blocks<T> A;
+      A.clear();
+      A.add(B, ldb, j);
+      for (int pass = 0; pass < 2; ++pass) {
+        CR_TRY(gemv_t<T>(n, A, x, y0, part, st));
+        hipLaunchKernelGGL(k_neg, dim3(nblk(j)), dim3(256), 0, st, j, y0, coef);
+        CR_HIP(hipGetLastError());
+        CR_TRY(gemv_n<T>(n, A, coef, 1.0, x, st));
+      }
+    }
+    CR_TRY(dot(n, x, x, tmp + 5));
+    CR_TRY(read_scalars(tmp + 4, 2, h));
+    breakdown = !(h[1] > tol * tol * h[0]) || !std::isfinite(h[1]);
+    if (breakdown) return CR_OK;
+    return scale_inv_sqrt<T>(n, x, tmp + 5, st);
+  }
+
+  // ------------------------------------------------------------ Grams
+  // masked Gram column j: G_a(k, j) = sum_i U_ik omega_ia U_ij, k <= j
+  cr_status gram_column(int j, int64_t ldr) {
+    double* C = WS(double, "gramcol", (int64_t)(j + 1) * ninj);
+    const T* uj = U + (int64_t)j * ldu;
+    Blocks<T> A;
+    A.clear();
+    A.add(U, ldu, j + 1);
+    if (P->use_holes) {
+      CR_TRY(gemv_t<T>(ny, A, uj, y0, part, st));
+      const int64_t m = (int64_t)(j + 1) * ninj;
+      hipLaunchKernelGGL(k_bcast_cols, dim3(nblk(m)), dim3(256), 0, st, j + 1, ninj, y0, C,
+                         (int64_t)(j + 1));
+      CR_HIP(hipGetLastError());
+      CR_TRY(hole_gram_col<T>(ninj, P->hptr, P->hidx, j + 1, U, ldu, uj, C, j + 1, st));
+    } else {
+      Blocks<T> Bd;
+      Bd.clear();
+      CR_TRY(gemm_tn<T>(ny, A, Bd, P->bits, uj, ninj, C, j + 1, gpart, gemm_part_cap(P), st));
+    }
+    const int64_t m = (int64_t)(j + 1) * ninj;
+    hipLaunchKernelGGL(k_scatter_gram, dim3(nblk(m)), dim3(256), 0, st, ninj, j, C,
+                       (int64_t)(j + 1), G, ldr);
+    CR_HIP(hipGetLastError());
+    return CR_OK;
+  }
+
+  // all projected quantities for new column j (columns < j already present)
+  cr_status project_column(int j, int64_t ldr) {
+    const T* uj = U + (int64_t)j * ldu;
+    const T* vj = V + (int64_t)j * ldv;
+    const T* luj = LU + (int64_t)j * ny;
+    const T* lvj = LV + (int64_t)j * nx;
+    Blocks<T> A;
+    A.clear();
+    A.add(U, ldu, j + 1);
+    CR_TRY(gemv_t<T>(ny, A, luj, By1 + j * ldr, part, st));
+    A.clear();
+    A.add(LU, ny, j + 1);
+    CR_TRY(gemv_t<T>(ny, A, luj, By2 + j * ldr, part, st));
+    A.clear();
+    A.add(V, ldv, j + 1);
+    CR_TRY(gemv_t<T>(nx, A, lvj, Bx1 + j * ldr, part, st));
+    A.clear();
+    A.add(LV, nx, j + 1);
+    CR_TRY(gemv_t<T>(nx, A, lvj, Bx2 + j * ldr, part, st));
+    for (double* B : {By1, By2, Bx1, Bx2}) {
+      hipLaunchKernelGGL(k_mirror, dim3(nblk(j + 1)), dim3(256), 0, st, B, ldr, j);
+      CR_HIP(hipGetLastError());
+    }
+    A.clear();
+    A.add(X(), nx, ninj);
+    CR_TRY(gemv_t<T>(nx, A, vj, Ht + (int64_t)j * ninj, part, st));
+    A.clear();
+    A.add(OY(), ny, ninj);
+    CR_TRY(gemv_t<T>(ny, A, uj, St + (int64_t)j * ninj, part, st));
+    return gram_column(j, ldr);
+  }
+
+  // ------------------------------------------------------------ Galerkin
+  cr_status galerkin(int r, int64_t ldr, double rtol, int maxit, double* scal4) {
+    const int64_t r2 = ldr * ldr;
+    GalerkinArgs a{};
+    a.r = r;
+    a.ldr = (int)ldr;
+    a.ninj = ninj;
+    a.lam = lam;
+    a.G = G;
+    a.H = Ht;
+    a.S = St;
+    a.By1 = By1;
+    a.By2 = By2;
+    a.Bx1 = Bx1;
+    a.Bx2 = Bx2;
+    a.Z = Z;
+    a.R = WS(double, "gR", r2);
+    a.P = WS(double, "gP", r2);
+    a.Q = WS(double, "gQ", r2);
+    a.Y2 = WS(double, "gY2", r2);
+    a.Bm = WS(double, "gB", r2);
+    a.SG = WS(double, "gSG", ldr * ninj);
+    const int maxwg = galerkin_max_wg(r);
+    if (maxwg <= 0) {
+      set_error("cooperative launch not available for the Galerkin kernel");
+      return CR_EHIP;
+    }
+    const int nwg = std::max(1, std::min(maxwg, std::max(ninj, r)));
+    a.part = WS(double, "galpart", 6 * nwg);
+    a.scal = sc + 8;
+    a.rtol = rtol;
+    a.maxit = maxit;
+    CR_TRY(galerkin_cg(a, nwg, st));
+    return read_scalars(sc + 8, 4, scal4);
+  }
+
+  // ------------------------------------------------------------ residual norm
+  cr_status residual(int r, double* abs_out, double* rel_out) {
+    const int k = ninj + 3 * r;
+    const int64_t k2 = (int64_t)k * k;
+    double* GF = WS(double, "resGF", k2);
+    double* GX = WS(double, "resGX", k2);
+    double* Cm = WS(double, "resCm", k2);
+    double* M1 = WS(double, "resM1", k2);
+    Blocks<T> F;
+    F.clear();
+    F.add(N, ny, ninj);
+    F.add(U, ldu, r);
+    F.add(LU, ny, r);
+    F.add(L2U, ny, r);
+    CR_TRY(gemm_tn<T>(ny, F, F, nullptr, nullptr, 0, GF, k, gpart, gemm_part_cap(P), st));
+    Blocks<T> Gx;
+    Gx.clear();
+    Gx.add(X(), nx, ninj);
+    Gx.add(L2V, nx, r);
+    Gx.add(LV, nx, r);
+    Gx.add(V, ldv, r);
+    CR_TRY(gemm_tn<T>(nx, Gx, Gx, nullptr, nullptr, 0, GX, k, gpart, gemm_part_cap(P), st));
+    hipLaunchKernelGGL(k_build_cm, dim3(nblk(k2)), dim3(256), 0, st, ninj, r, Z, ldz, lam, Cm);
+    CR_HIP(hipGetLastError());
+    // M1 = GX Cm ; Cm <- Cm^T M1 is stored in GX (no longer needed)
+    CR_TRY(small_gemm(k, k, k, GX, k, false, Cm, k, false, 1.0, M1, k, st));
+    CR_TRY(small_gemm(k, k, k, Cm, k, true, M1, k, false, 1.0, GX, k, st));
+    // ||R||^2 = sum_ij GF_ij GX_ij
+    Blocks<double> A;
+    A.clear();
+    A.add(GF, k2, 1);
+    double* part64 = (double*)part;
+    CR_TRY(gemv_t<double>(k2, A, GX, tmp + 6, part64, st));
+    double h;
+    CR_TRY(read_scalars(tmp + 6, 1, &h));
+    const double nr = std::sqrt(std::max(h, 0.0));
+    if (abs_out) *abs_out = nr;
+    if (rel_out) *rel_out = P->dnorm > 0 ? nr / P->dnorm : nr;
+    return CR_OK;
+  }
+};
+
+// ===================================================================== create / destroy
+static cr_status build_geom(const cr_csr& L, Geom& g, const char* which) {
+  const int64_t n = L.n;
+  if (n <= 0 || !L.rowptr || !L.colidx || !L.val) {
+    set_error(std::string(which) + ": empty or null CSR");
+    return CR_EINVAL;
+  }
+  if (n > INT32_MAX) {
+    set_error(std::string(which) + ": too many voxels");
+    return CR_EINVAL;
+  }
+  int K = 1;
+  std::vector<uint8_t> deg(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int b = L.rowptr[i], e = L.rowptr[i + 1];
+    if (e < b) {
+      set_error(std::string(which) + ": rowptr not monotone");
+      return CR_EINVAL;
+    }
+    int off = 0;
+    double diag = 0.0;
+    bool has_diag = false;
+    for (int k = b; k < e; ++k) {
+      const int j = L.colidx[k];
+      if (j < 0 || j >= n) {
+        set_error(std::string(which) + ": column index out of range");
+        return CR_EINVAL;
+      }
+      if (j == i) {
+        diag = L.val[k];
+        has_diag = true;
+      } else {
+        if (L.val[k] != -1.0) {
+          set_error(std::string(which) + ": off-diagonal entries must be -1 (graph Laplacian)");
+          return CR_EINVAL;
+        }
+        ++off;
+      }
+    }
+    if (off > 8) {
+      set_error(std::string(which) + ": more than 8 neighbours per voxel");
+      return CR_EINVAL;
+    }
+    if ((off > 0 || has_diag) && diag != (double)off) {
+      set_error(std::string(which) + ": diagonal must equal the neighbour count");
+      return CR_EINVAL;
+    }
+    deg[i] = (uint8_t)off;
+    K = std::max(K, off);
+  }
+  std::vector<int32_t> nbr((size_t)K * n);
+  for (int64_t i = 0; i < n; ++i) {
+    int c = 0;
+    for (int k = L.rowptr[i]; k < L.rowptr[i + 1]; ++k) {
+      const int j = L.colidx[k];
+      if (j == i) continue;
+      // symmetry: row j must contain i
+      const int* rb = L.colidx + L.rowptr[j];
+      const int* re = L.colidx + L.rowptr[j + 1];
+      bool found = false;
+      for (const int* q = rb; q < re; ++q)
+        if (*q == i) {
+          found = true;
+          break;
+        }
+      if (!found) {
+        set_error(std::string(which) + ": Laplacian not symmetric");
+        return CR_EINVAL;
+      }
+      nbr[(size_t)c * n + i] = j;
+      ++c;
+    }
+    for (; c < K; ++c) nbr[(size_t)c * n + i] = (int32_t)i;
+  }
+  g.n = n;
+  g.K = K;
+  if (hipMalloc(&g.nbr, sizeof(int32_t) * nbr.size()) != hipSuccess ||
+      hipMalloc(&g.deg, n) != hipSuccess) {
+    set_error("device allocation of the neighbour table failed");
+    return CR_ENOMEM;
+  }
+  CR_HIP(hipMemcpy(g.nbr, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice));
+  CR_HIP(hipMemcpy(g.deg, deg.data(), n, hipMemcpyHostToDevice));
+  return CR_OK;
+}
+
+template <typename T>
+static cr_status dev_alloc(cr_problem* P, T** p, int64_t count) {
+  if (hipMalloc((void**)p, sizeof(T) * (size_t)std::max<int64_t>(count, 1)) != hipSuccess) {
+    set_error("device allocation failed");
+    return CR_ENOMEM;
+  }
+  P->owned.push_back(*p);
+  return CR_OK;
+}
+
+static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* stream,
+                             cr_problem* P) {
+  P->st = (hipStream_t)stream;
+  P->prec = prec;
+  P->ny = d->Ly.n;
+  P->nx = d->Lx.n;
+  P->ninj = (int)d->n_inj;
+  P->lam = d->lambda;
+  if (d->n_inj <= 0 || d->n_inj > 1024) {
+    set_error("n_inj must be in [1, 1024]");
+    return CR_EINVAL;
+  }
+  if (!d->X || !d->Y || !d->Omega || d->ldx < P->nx || d->ldy < P->ny || d->ldo < P->ny) {
+    set_error("X, Y, Omega must be non-null with ld >= rows");
+    return CR_EINVAL;
+  }
+  if (!(d->lambda >= 0.0) || !std::isfinite(d->lambda)) {
+    set_error("lambda must be finite and >= 0");
+    return CR_EINVAL;
+  }
+  CR_TRY(build_geom(d->Ly, P->gy, "L_y"));
+  CR_TRY(build_geom(d->Lx, P->gx, "L_x"));
+  const int64_t ny = P->ny, nx = P->nx, ni = P->ninj;
+  std::vector<double> X((size_t)nx * ni), Y((size_t)ny * ni);
+  std::vector<uint8_t> Om((size_t)ny * ni);
+  CR_HIP(hipMemcpy2D(X.data(), nx * sizeof(double), d->X, d->ldx * sizeof(double),
+                     nx * sizeof(double), ni, hipMemcpyDeviceToHost));
+  CR_HIP(hipMemcpy2D(Y.data(), ny * sizeof(double), d->Y, d->ldy * sizeof(double),
+                     ny * sizeof(double), ni, hipMemcpyDeviceToHost));
+  CR_HIP(hipMemcpy2D(Om.data(), ny, d->Omega, d->ldo, ny, ni, hipMemcpyDeviceToHost));
+  for (double x : X)
+    if (!std::isfinite(x)) {
+      set_error("X has non-finite entries");
+      return CR_ENONFINITE;
+    }
+  std::vector<double> OY((size_t)ny * ni);
+  std::vector<float> OYf((size_t)ny * ni), Xf((size_t)nx * ni);
+  const int nw = (int)((ni + 31) / 32);
+  std::vector<uint32_t> bits((size_t)nw * ny, 0u);
+  std::vector<int32_t> hptr(ni + 1, 0), hidx;
+  for (int64_t a = 0; a < ni; ++a) {
+    hptr[a] = (int32_t)hidx.size();
+    for (int64_t i = 0; i < ny; ++i) {
+      const size_t e = (size_t)a * ny + i;
+      const bool obs = Om[e] != 0;
+      if (obs && !std::isfinite(Y[e])) {
+        set_error("Y has non-finite observed entries");
+        return CR_ENONFINITE;
+      }
+      OY[e] = obs ? Y[e] : 0.0;
+      OYf[e] = (float)OY[e];
+      if (obs)
+        bits[(size_t)(a / 32) * ny + i] |= 1u << (a % 32);
+      else
+        hidx.push_back((int32_t)i);
+    }
+  }
+  hptr[ni] = (int32_t)hidx.size();
+  for (size_t e = 0; e < X.size(); ++e) Xf[e] = (float)X[e];
+  P->nholes = (int64_t)hidx.size();
+  P->use_holes = P->nholes * 8 <= ny * ni;
+  CR_TRY(dev_alloc(P, &P->X64, nx * ni));
+  CR_TRY(dev_alloc(P, &P->X32, nx * ni));
+  CR_TRY(dev_alloc(P, &P->OY64, ny * ni));
+  CR_TRY(dev_alloc(P, &P->OY32, ny * ni));
+  CR_TRY(dev_alloc(P, &P->bits, (int64_t)nw * ny));
+  CR_TRY(dev_alloc(P, &P->hptr, ni + 1));
+  CR_TRY(dev_alloc(P, &P->hidx, std::max<int64_t>(P->nholes, 1)));
+  CR_HIP(hipMemcpy(P->X64, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice));
+  CR_HIP(hipMemcpy(P->X32, Xf.data(), sizeof(float) * Xf.size(), hipMemcpyHostToDevice));
+  CR_HIP(hipMemcpy(P->OY64, OY.data(), sizeof(double) * OY.size(), hipMemcpyHostToDevice));
+  CR_HIP(hipMemcpy(P->OY32, OYf.data(), sizeof(float) * OYf.size(), hipMemcpyHostToDevice));
+  CR_HIP(hipMemcpy(P->bits, bits.data(), sizeof(uint32_t) * bits.size(), hipMemcpyHostToDevice));
+  CR_HIP(hipMemcpy(P->hptr, hptr.data(), sizeof(int32_t) * hptr.size(), hipMemcpyHostToDevice));
+  if (P->nholes)
+    CR_HIP(hipMemcpy(P->hidx, hidx.data(), sizeof(int32_t) * hidx.size(), hipMemcpyHostToDevice));
+  if (hipHostMalloc((void**)&P->hscal, 64 * sizeof(double)) != hipSuccess) {
+    set_error("pinned host allocation failed");
+    return CR_ENOMEM;
+  }
+  // ||D||_F^2 = trace((OY^T OY)(X^T X))
+  double* gpart = P->buf<double>("gpart", gemm_part_cap(P));
+  double* g1 = P->buf<double>("dn1", ni * ni);
+  double* g2 = P->buf<double>("dn2", ni * ni);
+  double* s = P->buf<double>("dns", 1);
+  double* pp = P->buf<double>("part", gemv_t_part_size(ni * ni, 1) + 1);
+  if (!gpart || !g1 || !g2 || !s || !pp) return CR_ENOMEM;
+  Blocks<double> A, B;
+  A.clear();
+  A.add(P->OY64, ny, (int)ni);
+  CR_TRY(gemm_tn<double>(ny, A, A, nullptr, nullptr, 0, g1, ni, gpart, gemm_part_cap(P), P->st));
+  B.clear();
+  B.add(P->X64, nx, (int)ni);
+  CR_TRY(gemm_tn<double>(nx, B, B, nullptr, nullptr, 0, g2, ni, gpart, gemm_part_cap(P), P->st));
+  Blocks<double> C;
+  C.clear();
+  C.add(g1, ni * ni, 1);
+  CR_TRY(gemv_t<double>(ni * ni, C, g2, s, pp, P->st));
+  CR_HIP(hipMemcpyAsync(P->hscal, s, sizeof(double), hipMemcpyDeviceToHost, P->st));
+  CR_HIP(hipStreamSynchronize(P->st));
+  P->dnorm = std::sqrt(std::max(P->hscal[0], 0.0));
+  return CR_OK;
+}
+
+extern "C" cr_status cr_problem_create(const cr_problem_desc* desc, cr_precision prec,
+                                       void* hip_stream, cr_problem** out) {
+  if (!desc || !out) {
+    set_error("null argument");
+    return CR_EINVAL;
+  }
+  if (prec != CR_PREC_FP64 && prec != CR_PREC_MIXED) {
+    set_error("unknown precision");
+    return CR_EINVAL;
+  }
+  *out = nullptr;
+  cr_problem* P = new cr_problem();
+  cr_status s = create_impl(desc, prec, hip_stream, P);
+  if (s != CR_OK) {
+    cr_problem_destroy(P);
+    return s;
+  }
+  *out = P;
+  return CR_OK;
+}
+
+extern "C" void cr_problem_destroy(cr_problem* P) {
+  if (!P) return;
+  (void)hipStreamSynchronize(P->st);
+  for (auto& kv : P->ws)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (void* p : P->owned) (void)hipFree(p);
+  if (P->gy.nbr) (void)hipFree(P->gy.nbr);
+  if (P->gy.deg) (void)hipFree(P->gy.deg);
+  if (P->gx.nbr) (void)hipFree(P->gx.nbr);
+  if (P->gx.deg) (void)hipFree(P->gx.deg);
+  if (P->hscal) (void)hipHostFree(P->hscal);
+  delete P;
+}
+
+extern "C" cr_status cr_rhs_norm(cr_problem* P, double* out) {
+  if (!P || !out) {
+    set_error("null argument");
+    return CR_EINVAL;
+  }
+  *out = P->dnorm;
+  return CR_OK;
+}
+
+extern "C" const char* cr_last_error(void) { return g_err.c_str(); }
+extern "C" const char* cr_version(void) { return "libconnreg 0.1 (gfx950)"; }
+
+extern "C" void cr_solve_opts_default(cr_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_rank = 20;
+  o->tau_dW = 0.0;
+  o->tau_res = 0.0;
+  o->als_delta = 0.1;
+  o->als_max_sweeps = 10;
+  o->als_fixed_sweeps = 0;
+  o->pcg_rtol = 1e-8;
+  o->pcg_maxit = 5000;
+  o->galerkin_rtol = 0.0;
+  o->galerkin_maxit = 0;
+  o->seed = 0;
+  o->orth_tol = 1e-10;
+  o->pcg_vpt = 0;
+  o->verbose = 0;
+}
+
+// ===================================================================== op_apply
+template <typename T>
+static cr_status op_apply_impl(cr_problem* P, int64_t r, const T* U, int64_t ldu, const T* Z,
+                               int64_t ldz, const T* V, int64_t ldv, T* F, int64_t ldf, T* G,
+                               int64_t ldg) {
+  if (!P || r < 0 || (r > 0 && (!U || !Z || !V)) || !F || (r > 0 && !G)) {
+    set_error("null argument or negative rank");
+    return CR_EINVAL;
+  }
+  const int64_t ny = P->ny, nx = P->nx;
+  const int ninj = P->ninj;
+  if ((r > 0 && (ldu < ny || ldv < nx || ldz < r || ldg < nx)) || ldf < ny) {
+    set_error("leading dimension too small");
+    return CR_EINVAL;
+  }
+  hipStream_t st = P->st;
+  const int rr = (int)r;
+  CR_TRY(stencil<T>(P->gy, rr, U, ldu, F, ldf, st));
+  CR_TRY(stencil<T>(P->gy, rr, F, ldf, F + r * ldf, ldf, st));
+  CR_TRY(stencil<T>(P->gx, rr, V, ldv, G, ldg, st));
+  CR_TRY(stencil<T>(P->gx, rr, G, ldg, G + r * ldg, ldg, st));
+  double* Tm = WS(double, "Tm_op", std::max<int64_t>(r, 1) * ninj);
+  if (r > 0) {
+    double* Ht = WS(double, "Ht_op", (int64_t)ninj * r);
+    double* Zd = WS(double, "Zd_op", r * r);
+    double* gpart = WS(double, "gpart", gemm_part_cap(P));
+    Blocks<T> A, B;
+    A.clear();
+    B.clear();
+    A.add(P->X<T>(), nx, ninj);
+    B.add(V, ldv, rr);
+    CR_TRY(gemm_tn<T>(nx, A, B, nullptr, nullptr, 0, Ht, ninj, gpart, gemm_part_cap(P), st));
+    CR_TRY((convert2d<double, T>(r, r, Z, ldz, Zd, r, st)));
+    CR_TRY(small_gemm(rr, ninj, rr, Zd, r, false, Ht, ninj, true, 1.0, Tm, r, st));
+  }
+  return masked_tall_gemm<T>(ny, rr, ninj, U, ldu, Tm, std::max<int64_t>(r, 1), P->bits,
+                             (const T*)nullptr, 0, F + 2 * r * ldf, ldf, st);
+}
+
+extern "C" cr_status cr_op_apply(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                 const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                                 double* F, int64_t ldf, double* G, int64_t ldg) {
+  return op_apply_impl<double>(P, r, U, ldu, Z, ldz, V, ldv, F, ldf, G, ldg);
+}
+
+extern "C" cr_status cr_op_apply_f32(cr_problem* P, int64_t r, const float* U, int64_t ldu,
+                                     const float* Z, int64_t ldz, const float* V, int64_t ldv,
+                                     float* F, int64_t ldf, float* G, int64_t ldg) {
+  return op_apply_impl<float>(P, r, U, ldu, Z, ldz, V, ldv, F, ldf, G, ldg);
+}
+
+// ===================================================================== iterate setup
+// Bring an external iterate (double U, Z, V) into ctx: bases in T (copied when
+// T is float or the leading dimensions differ), core copied to ld r, derived
+// stencils, H^T and N.
+template <typename T>
+static cr_status load_iterate(Ctx<T>& c, int r, const double* U, int64_t ldu, const double* Z,
+                              int64_t ldz, const double* V, int64_t ldv, bool need_N) {
+  cr_problem* P = c.P;
+  const int64_t ny = c.ny, nx = c.nx;
+  c.U = WS(T, "U_in", ny * std::max(r, 1));
+  c.V = WS(T, "V_in", nx * std::max(r, 1));
+  c.ldu = ny;
+  c.ldv = nx;
+  if (r > 0) {
+    CR_TRY((convert2d<T, double>(ny, r, U, ldu, c.U, ny, c.st)));
+    CR_TRY((convert2d<T, double>(nx, r, V, ldv, c.V, nx, c.st)));
+  }
+  c.Z = WS(double, "Z_in", (int64_t)std::max(r, 1) * std::max(r, 1));
+  c.ldz = std::max(r, 1);
+  if (r > 0 && Z) CR_TRY((convert2d<double, double>(r, r, Z, ldz, c.Z, r, c.st)));
+  CR_TRY(c.alloc_rank(std::max(r, 1)));
+  if (r > 0) CR_TRY(c.stencil_cols(0, r));
+  if (need_N) {
+    CR_TRY(c.compute_Ht(r));
+    CR_TRY(c.build_N(r));
+  }
+  return CR_OK;
+}
+
+template <typename T>
+static cr_status als_step_impl(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                               const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                               double* v_io, double* u_out, const cr_solve_opts* opts,
+                               cr_als_stats* stats) {
+  cr_solve_opts o;
+  if (opts)
+    o = *opts;
+  else
+    cr_solve_opts_default(&o);
+  Ctx<T> c(P);
+  CR_TRY(load_iterate<T>(c, (int)r, U, ldu, Z, ldz, V, ldv, true));
+  CR_TRY(c.alloc_vectors(o.pcg_vpt));
+  CR_TRY((convert2d<T, double>(c.nx, 1, v_io, c.nx, c.vv, c.nx, c.st)));
+  // normalise the initial vector
+  CR_TRY(c.dot(c.nx, c.vv, c.vv, c.tmp + 7));
+  CR_TRY(scale_inv_sqrt<T>(c.nx, c.vv, c.tmp + 7, c.st));
+  bool zero = false;
+  CR_TRY(c.als((int)r, c.vv, c.vu, o, stats, zero));
+  CR_TRY((convert2d<double, T>(c.nx, 1, c.vv, c.nx, v_io, c.nx, c.st)));
+  CR_TRY((convert2d<double, T>(c.ny, 1, c.vu, c.ny, u_out, c.ny, c.st)));
+  CR_HIP(hipStreamSynchronize(c.st));
+  if (zero) {
+    set_error("ALS right-hand side vanished");
+    return CR_BREAKDOWN;
+  }
+  return c.notconv ? CR_NOTCONV : CR_OK;
+}
+
+extern "C" cr_status cr_als_step(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                 const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                                 double* v_io, double* u_out, const cr_solve_opts* opts,
+                                 cr_als_stats* stats) {
+  if (!P || r < 0 || !v_io || !u_out || (r > 0 && (!U || !Z || !V))) {
+    set_error("null argument or negative rank");
+    return CR_EINVAL;
+  }
+  return P->prec == CR_PREC_MIXED
+             ? als_step_impl<float>(P, r, U, ldu, Z, ldz, V, ldv, v_io, u_out, opts, stats)
+             : als_step_impl<double>(P, r, U, ldu, Z, ldz, V, ldv, v_io, u_out, opts, stats);
+}
+
+template <typename T>
+static cr_status galerkin_impl(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                               const double* V, int64_t ldv, double* Z_io, int64_t ldz,
+                               double rtol, int32_t maxit, int32_t* iters_out) {
+  Ctx<T> c(P);
+  CR_TRY(load_iterate<T>(c, (int)r, U, ldu, Z_io, ldz, V, ldv, false));
+  const int rr = (int)r;
+  const int64_t ldr = rr;
+  // projected data in ld r
+  for (double* B : {c.By1, c.By2, c.Bx1, c.Bx2}) CR_HIP(hipMemsetAsync(B, 0, sizeof(double) * ldr * ldr, c.st));
+  CR_TRY(c.alloc_vectors(0));
+  for (int j = 0; j < rr; ++j) CR_TRY(c.project_column(j, ldr));
+  double s[4];
+  CR_TRY(c.galerkin(rr, ldr, rtol, maxit > 0 ? maxit : 50 * rr + 200, s));
+  CR_TRY((convert2d<double, double>(r, r, c.Z, r, Z_io, ldz, c.st)));
+  CR_HIP(hipStreamSynchronize(c.st));
+  if (iters_out) *iters_out = (int32_t)s[0];
+  if (s[2] == 2.0) {
+    set_error("projected operator not positive definite on a CG direction");
+    return CR_ENONFINITE;
+  }
+  return s[2] == 1.0 ? CR_NOTCONV : CR_OK;
+}
+
+extern "C" cr_status cr_galerkin_project(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                         const double* V, int64_t ldv, double* Z_io, int64_t ldz,
+                                         double rtol, int32_t maxit, int32_t* iters_out) {
+  if (!P || r <= 0 || !U || !V || !Z_io || ldu < P->ny || ldv < P->nx || ldz < r) {
+    set_error("invalid arguments to cr_galerkin_project");
+    return CR_EINVAL;
+  }
+  return P->prec == CR_PREC_MIXED
+             ? galerkin_impl<float>(P, r, U, ldu, V, ldv, Z_io, ldz, rtol, maxit, iters_out)
+             : galerkin_impl<double>(P, r, U, ldu, V, ldv, Z_io, ldz, rtol, maxit, iters_out);
+}
+
+template <typename T>
+static cr_status residual_impl(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                               const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                               double* abs_out, double* rel_out) {
+  Ctx<T> c(P);
+  CR_TRY(load_iterate<T>(c, (int)r, U, ldu, Z, ldz, V, ldv, true));
+  CR_TRY(c.alloc_vectors(0));
+  return c.residual((int)r, abs_out, rel_out);
+}
+
+extern "C" cr_status cr_residual_norm(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                      const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                                      double* abs_out, double* rel_out) {
+  if (!P || r < 0 || (r > 0 && (!U || !Z || !V || ldu < P->ny || ldv < P->nx || ldz < r))) {
+    set_error("invalid arguments to cr_residual_norm");
+    return CR_EINVAL;
+  }
+  return P->prec == CR_PREC_MIXED
+             ? residual_impl<float>(P, r, U, ldu, Z, ldz, V, ldv, abs_out, rel_out)
+             : residual_impl<double>(P, r, U, ldu, Z, ldz, V, ldv, abs_out, rel_out);
+}
+
+// ===================================================================== greedy solve
+template <typename T>
+static cr_status greedy_impl(cr_problem* P, const cr_solve_opts& o, double* Uo, double* Vo,
+                             double* Zo, int64_t* rank_io, cr_solve_stats* stats, cr_rank_cb cb,
+                             void* user) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  const int rmax = o.max_rank;
+  const int64_t ny = P->ny, nx = P->nx;
+  Ctx<T> c(P);
+  CR_TRY(c.alloc_rank(rmax));
+  CR_TRY(c.alloc_vectors(o.pcg_vpt));
+  // bases: the caller's buffers directly in FP64, internal copies otherwise
+  if (std::is_same<T, double>::value) {
+    c.U = (T*)Uo;
+    c.V = (T*)Vo;
+  } else {
+    c.U = WS(T, "Ug", ny * rmax);
+    c.V = WS(T, "Vg", nx * rmax);
+  }
+  c.ldu = ny;
+  c.ldv = nx;
+  c.Z = Zo;
+  c.ldz = rmax;
+  const int64_t ldr = rmax;
+  double* Zold = WS(double, "Zold", (int64_t)rmax * rmax);
+  int r0 = (int)*rank_io;
+  if (r0 < 0 || r0 > rmax) {
+    set_error("rank_io out of range");
+    return CR_EINVAL;
+  }
+  // clear everything beyond the resumed core
+  std::vector<double> hz((size_t)rmax * rmax, 0.0), hzo((size_t)rmax * rmax, 0.0);
+  if (r0 > 0) {
+    CR_HIP(hipMemcpy2DAsync(hz.data(), rmax * sizeof(double), Zo, rmax * sizeof(double),
+                            r0 * sizeof(double), r0, hipMemcpyDeviceToHost, c.st));
+    CR_HIP(hipStreamSynchronize(c.st));
+  }
+  CR_HIP(hipMemcpyAsync(Zo, hz.data(), sizeof(double) * hz.size(), hipMemcpyHostToDevice, c.st));
+  for (double* B : {c.By1, c.By2, c.Bx1, c.Bx2})
+    CR_HIP(hipMemsetAsync(B, 0, sizeof(double) * ldr * ldr, c.st));
+  CR_HIP(hipMemsetAsync(c.G, 0, sizeof(double) * ldr * ldr * c.ninj, c.st));
+  if (r0 > 0) {
+    if (!std::is_same<T, double>::value) {
+      CR_TRY((convert2d<T, double>(ny, r0, Uo, ny, c.U, ny, c.st)));
+      CR_TRY((convert2d<T, double>(nx, r0, Vo, nx, c.V, nx, c.st)));
+    }
+    CR_TRY(c.stencil_cols(0, r0));
+    for (int j = 0; j < r0; ++j) CR_TRY(c.project_column(j, ldr));
+  }
+  CR_TRY(c.build_N(r0));
+  const double tau = o.tau_res > 0 ? o.tau_res : o.tau_dW;
+  const double g_rtol = o.galerkin_rtol > 0 ? o.galerkin_rtol : std::max(tau, 1e-14) / 2;
+  cr_status final_status = CR_OK;
+  int r = r0;
+  double relres = 1.0, dW = 1.0;
+  int64_t tot_pcg = 0, tot_gal = 0;
+  int tot_notconv = 0;
+  if (r0 > 0) CR_TRY(c.residual(r0, nullptr, &relres));
+  bool stop = (o.tau_res > 0 && r0 > 0 && relres <= o.tau_res);
+  while (!stop && r < rmax) {
+    const int j = r;
+    // initial ALS vector: v = R^T q / ||R^T q||, q from SplitMix64 stream j
+    CR_TRY(splitmix_fill<T>(ny, o.seed, (uint64_t)j, c.vu, c.st));
+    CR_TRY(c.apply_RT(j, c.vu, c.vv));
+    CR_TRY(c.dot(nx, c.vv, c.vv, c.tmp + 7));
+    CR_TRY(scale_inv_sqrt<T>(nx, c.vv, c.tmp + 7, c.st));
+    cr_als_stats as{};
+    bool zero = false;
+    CR_TRY(c.als(j, c.vv, c.vu, o, &as, zero));
+    tot_pcg += as.pcg_iters_u + as.pcg_iters_v;
+    tot_notconv += as.pcg_notconv;
+    if (zero) {
+      final_status = CR_BREAKDOWN;
+      break;
+    }
+    // U_{j+1} = orth([U_j, u]), V_{j+1} = orth([V_j, v]) by CGS2 into column j
+    T* uj = c.U + (int64_t)j * ny;
+    T* vj = c.V + (int64_t)j * nx;
+    CR_HIP(hipMemcpyAsync(uj, c.vu, sizeof(T) * ny, hipMemcpyDeviceToDevice, c.st));
+    CR_HIP(hipMemcpyAsync(vj, c.vv, sizeof(T) * nx, hipMemcpyDeviceToDevice, c.st));
+    bool bu = false, bv = false;
+    CR_TRY(c.cgs2(ny, c.U, ny, j, uj, o.orth_tol, bu));
+    CR_TRY(c.cgs2(nx, c.V, nx, j, vj, o.orth_tol, bv));
+    if (bu || bv) {
+      final_status = CR_BREAKDOWN;
+      break;
+    }
+    CR_TRY(c.stencil_cols(j, 1));
+    CR_TRY(c.project_column(j, ldr));
+    // Galerkin update from the padded previous core (row/column j are zero)
+    CR_HIP(hipMemcpyAsync(Zold, Zo, sizeof(double) * ldr * ldr, hipMemcpyDeviceToDevice, c.st));
+    double gs[4];
+    const int gmax = o.galerkin_maxit > 0 ? o.galerkin_maxit : 50 * (j + 1) + 200;
+    CR_TRY(c.galerkin(j + 1, ldr, g_rtol, gmax, gs));
+    if (gs[2] == 2.0) {
+      set_error("projected operator not positive definite on a CG direction");
+      return CR_ENONFINITE;
+    }
+    tot_gal += (int64_t)gs[0];
+    r = j + 1;
+    CR_TRY(c.build_N(r));
+    CR_TRY(c.residual(r, nullptr, &relres));
+    // delta W = ||Z_j - pad(Z_{j-1})||_F / ||Z_j||_F (orthonormal bases)
+    CR_HIP(hipMemcpyAsync(hz.data(), Zo, sizeof(double) * ldr * ldr, hipMemcpyDeviceToHost, c.st));
+    CR_HIP(hipMemcpyAsync(hzo.data(), Zold, sizeof(double) * ldr * ldr, hipMemcpyDeviceToHost,
+                          c.st));
+    CR_HIP(hipStreamSynchronize(c.st));
+    double dd = 0.0, zz = 0.0;
+    for (int q = 0; q < r; ++q)
+      for (int p = 0; p < r; ++p) {
+        const double a = hz[(size_t)q * ldr + p], b = hzo[(size_t)q * ldr + p];
+        dd += (a - b) * (a - b);
+        zz += a * a;
+      }
+    dW = zz > 0 ? std::sqrt(dd / zz) : 0.0;
+    const double secs = std::chrono::duration<double>(clk::now() - t0).count();
+    if (!std::isfinite(relres)) {
+      set_error("non-finite residual");
+      return CR_ENONFINITE;
+    }
+    if (o.verbose)
+      std::fprintf(stderr,
+                   "[connreg] rank %3d relres %.3e dW %.3e E %.6e sweeps %d pcg %d/%d gal %d  %.3fs\n",
+                   r, relres, dW, gs[3], as.sweeps, as.pcg_iters_u, as.pcg_iters_v, (int)gs[0],
+                   secs);
+    if (cb) {
+      cr_rank_info info{};
+      info.rank = r;
+      info.relres = relres;
+      info.dW = dW;
+      info.energy = gs[3];
+      info.sweeps = as.sweeps;
+      info.pcg_iters = as.pcg_iters_u + as.pcg_iters_v;
+      info.galerkin_iters = (int)gs[0];
+      info.seconds = secs;
+      cb(&info, user);
+    }
+    if ((o.tau_res > 0 && relres <= o.tau_res) || (o.tau_dW > 0 && dW <= o.tau_dW)) stop = true;
+  }
+  if (!stop && final_status == CR_OK && (o.tau_res > 0 || o.tau_dW > 0)) final_status = CR_NOTCONV;
+  if (!std::is_same<T, double>::value && r > 0) {
+    CR_TRY((convert2d<double, T>(ny, r, c.U, ny, Uo, ny, c.st)));
+    CR_TRY((convert2d<double, T>(nx, r, c.V, nx, Vo, nx, c.st)));
+  }
+  CR_HIP(hipStreamSynchronize(c.st));
+  *rank_io = r;
+  if (stats) {
+    stats->rank = r;
+    stats->relres = relres;
+    stats->dW = dW;
+    stats->pcg_iters = tot_pcg;
+    stats->galerkin_iters = tot_gal;
+    stats->pcg_notconv = tot_notconv;
+    stats->seconds = std::chrono::duration<double>(clk::now() - t0).count();
+  }
+  return final_status;
+}
+
+extern "C" cr_status cr_greedy_solve(cr_problem* P, const cr_solve_opts* opts, double* U,
+                                     double* V, double* Z, int64_t* rank_io,
+                                     cr_solve_stats* stats, cr_rank_cb cb, void* user) {
+  if (!P || !opts || !U || !V || !Z || !rank_io) {
+    set_error("null argument");
+    return CR_EINVAL;
+  }
+  if (opts->max_rank <= 0 || opts->max_rank > std::min<int64_t>(std::min(P->nx, P->ny), 2000)) {
+    set_error("max_rank must be in [1, min(n_x, n_y, 2000)]");
+    return CR_EINVAL;
+  }
+  if (opts->pcg_maxit <= 0 || !(opts->pcg_rtol > 0)) {
+    set_error("pcg_maxit and pcg_rtol must be positive");
+    return CR_EINVAL;
+  }
+  return P->prec == CR_PREC_MIXED
+             ? greedy_impl<float>(P, *opts, U, V, Z, rank_io, stats, cb, user)
+             : greedy_impl<double>(P, *opts, U, V, Z, rank_io, stats, cb, user);
+}

@@ -1,0 +1,216 @@
+// Internal declarations of libconnreg (not installed; the public C ABI is
+// include/connreg.h).  Kernels are written for gfx950 (CDNA4, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/connreg.h"
+
+namespace cr {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+
+#define CR_HIP(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      ::cr::set_error(std::string("HIP error ") + hipGetErrorString(e_) +   \
+                      " at " __FILE__ ":" + std::to_string(__LINE__));      \
+      return CR_EHIP;                                                       \
+    }                                                                       \
+  } while (0)
+
+#define CR_TRY(call)                 \
+  do {                               \
+    cr_status s_ = (call);           \
+    if (s_ < 0) return s_;           \
+  } while (0)
+
+constexpr int WAVE = 64;
+constexpr int NT = 256;  // threads per workgroup for streaming kernels
+
+// ---------------------------------------------------------------- geometry
+// A voxel graph Laplacian L = Deg - Adj stored as an ELL neighbour table of
+// width K, structure-of-arrays (nbr[k*n + i]); an absent neighbour points to
+// the voxel itself, so (L w)_i = K w_i - sum_k w[nbr[k*n+i]] for every row.
+struct Geom {
+  int64_t n = 0;
+  int K = 0;
+  int32_t* nbr = nullptr;  // device, K*n
+  uint8_t* deg = nullptr;  // device, n
+};
+
+// A column-block list: columns [col0, col0+ncols) of the logical matrix live
+// at p + (c-col0)*ld.  Up to 6 blocks, passed by value to kernels.
+template <typename T>
+struct Blocks {
+  static constexpr int MAXB = 6;
+  const T* p[MAXB];
+  int64_t ld[MAXB];
+  int col0[MAXB + 1];
+  int nb = 0;
+  void clear() { nb = 0; col0[0] = 0; }
+  void add(const T* ptr, int64_t ldp, int ncols) {
+    if (ncols <= 0) return;
+    p[nb] = ptr; ld[nb] = ldp; col0[nb + 1] = col0[nb] + ncols; ++nb;
+  }
+  __host__ __device__ int ncols() const { return nb ? col0[nb] : 0; }
+  __device__ __forceinline__ const T* col(int c) const {
+    int b = 0;
+#pragma unroll
+    for (int k = 1; k < MAXB; ++k)
+      if (k < nb && c >= col0[k]) b = k;
+    return p[b] + (int64_t)(c - col0[b]) * ld[b];
+  }
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return CR_OK or CR_EHIP.
+// Stencil: out[:,c] = L w[:,c] for c < ncols (w, out column-major).
+template <typename T>
+cr_status stencil(const Geom& g, int ncols, const T* w, int64_t ldw, T* out, int64_t ldo,
+                  hipStream_t st);
+
+// y[c] = sum_i A[i,c] * x[i] for the block list A (n rows), accumulated in
+// double; y written as double.  part: workspace of >= ncols * nrb doubles.
+template <typename T>
+cr_status gemv_t(int64_t n, const Blocks<T>& A, const T* x, double* y, double* part,
+                 hipStream_t st);
+int64_t gemv_t_part_size(int64_t n, int ncols);
+// the same with an x vector of another type (FP32 matrix, FP64 vector)
+template <typename T, typename TX>
+cr_status gemv_tx(int64_t n, const Blocks<T>& A, const TX* x, double* y, double* part,
+                  hipStream_t st);
+
+// y = beta*y + sum_c A[:,c] * coef[c]; coef is a device double array.
+template <typename T>
+cr_status gemv_n(int64_t n, const Blocks<T>& A, const double* coef, double beta, T* y,
+                 hipStream_t st);
+
+// C (p x q, ldc, double) = A^T B for block lists A, B over n rows.  When
+// mask_bits is non-null B is implicit: B[i,a] = omega_{i,a} * w[i] with
+// omega bit a of word bits[(a/32)*n + i].  part: >= ksplit*p*q doubles.
+template <typename T>
+cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint32_t* mask_bits,
+                  const T* w, int q_mask, double* C, int64_t ldc, double* part,
+                  int64_t part_cap, hipStream_t st);
+
+// N = OY - Omega o (U T)  (n x ninj), or, with OY == nullptr, N = Omega o (U T).
+// U: n x r (ldu), T: r x ninj (double, ldt).
+template <typename T>
+cr_status masked_tall_gemm(int64_t n, int r, int ninj, const T* U, int64_t ldu,
+                           const double* Tm, int64_t ldt, const uint32_t* bits,
+                           const T* OY, int64_t ldoy, T* N, int64_t ldn, hipStream_t st);
+
+// d_i = sum_a omega_ia h_a^2 (h: device double, ninj); tmp: 1 device double
+template <typename T>
+cr_status masked_quad_ws(int64_t n, int ninj, const uint32_t* bits, const double* h, T* d,
+                         double* tmp, hipStream_t st);
+
+// g_a = sum_i omega_ia w_i^2 (double out), part >= ninj*nrb doubles
+template <typename T>
+cr_status masked_colsq(int64_t n, int ninj, const uint32_t* bits, const T* w, double* g,
+                       double* part, hipStream_t st);
+
+// elementwise helpers
+template <typename Td, typename Ts>
+cr_status convert(int64_t n, const Ts* src, Td* dst, hipStream_t st);
+template <typename Td, typename Ts>
+cr_status convert2d(int64_t rows, int64_t cols, const Ts* src, int64_t lds, Td* dst,
+                    int64_t ldd, hipStream_t st);
+
+// ---------------------------------------------------------------- PCG
+// SPD system on one voxel graph:
+//   A x = lam*(L^2 x + c1 L x + c0 x) + dvec o x + Xm diag(gw) Xm^T x
+// Jacobi preconditioned CG from x0 = 0 in one cooperative launch; on exit
+// xout = x / ||x|| and scal[0] = ||x||, scal[1] = final ||r||/||b||,
+// scal[2] = iterations, scal[3] = status (0 ok, 1 not converged, 2 breakdown).
+template <typename T>
+struct PcgArgs {
+  Geom g;
+  double lam;
+  const double* coef;   // device: coef[0] = c1, coef[1] = c0
+  const T* dvec;        // may be null
+  const T* Xm;          // may be null (no low-rank term)
+  int64_t ldx;
+  int ninj;
+  const double* gw;     // ninj weights (device)
+  const T* minv;        // Jacobi inverse diagonal
+  const T* b;
+  T* x; T* r; T* z; T* p; T* t; T* q;
+  T* xout;
+  double* part;         // >= nwg*5 + ninj*nwg
+  double* sbuf;         // >= ninj
+  double* scal;         // >= 4
+  double rtol;
+  int maxit;
+  int vpt;              // voxels per thread
+};
+template <typename T>
+cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st);
+template <typename T>
+int pcg_max_wg(const PcgArgs<T>& a);
+
+// Jacobi inverse diagonal: minv_i = 1 / (lam*(deg^2 + deg + c1*deg + c0) + d_i
+//                                        + sum_a gw_a Xm_ia^2)
+template <typename T>
+cr_status pcg_diag(const Geom& g, double lam, const double* coef, const T* dvec, const T* Xm,
+                   int64_t ldx, int ninj, const double* gw, T* minv, hipStream_t st);
+
+// FP64 residual of the same operator for iterative refinement:
+//   r = b - (lam*(L^2 x + c1 L x + c0 x) + dvec o x + Xm (gw o s)),  s = Xm^T x given,
+// x, r, t (= L x, written here) in FP64; operator data in T.
+template <typename T>
+cr_status als_residual(const Geom& g, double lam, const double* coef, const T* dvec, const T* Xm,
+                       int64_t ldx, int ninj, const double* gw, const double* s, const T* b,
+                       const double* x, double* t, double* r, hipStream_t st);
+// x += e (e in T, x in FP64); x = e when init
+template <typename T>
+cr_status accumulate(int64_t n, const T* e, double* x, bool init, hipStream_t st);
+// out = (T)(x / sqrt(nrm2[0]))
+template <typename T>
+cr_status normalize_out(int64_t n, const double* x, const double* nrm2, T* out, hipStream_t st);
+
+// ---------------------------------------------------------------- Galerkin
+struct GalerkinArgs {
+  int r, ldr, ninj;
+  double lam;
+  const double* G;    // ninj blocks of ldr*ldr (col-major r x r each)
+  const double* H;    // H = V^T X stored transposed: H(k,a) = H[a + k*ninj]
+  const double* S;    // S = U^T (Omega o Y) stored the same way
+  const double* By1; const double* By2; const double* Bx1; const double* Bx2;  // ld ldr
+  double* Z;          // in/out, ld ldr
+  double* R; double* P; double* Q; double* Y2; double* Bm;  // work, r x r (ld ldr)
+  double* SG;         // work, r x ninj (ld ldr)
+  double* part;       // >= 6*nwg
+  double* scal;       // out: [0] iters, [1] relres, [2] status, [3] energy
+  double rtol;
+  int maxit;
+};
+cr_status galerkin_cg(const GalerkinArgs& a, int nwg, hipStream_t st);
+int galerkin_max_wg(int r);
+
+// ---------------------------------------------------------------- small ops
+// out[i] = sum_k M[i + k*ldm] * v[k] * alpha  (i < m, k < kk), single block
+cr_status small_gemv(int m, int kk, const double* M, int64_t ldm, bool trans, const double* v,
+                     double alpha, double* out, hipStream_t st);
+// C (m x n, ldc) = alpha * op(A) op(B), op = transpose when ta/tb, all double, small
+cr_status small_gemm(int m, int n, int k, const double* A, int64_t lda, bool ta, const double* B,
+                     int64_t ldb, bool tb, double alpha, double* C, int64_t ldc, hipStream_t st);
+
+// x[i] *= 1/sqrt(nrm2[0]) with nrm2 a device double
+template <typename T>
+cr_status scale_inv_sqrt(int64_t n, T* x, const double* nrm2, hipStream_t st);
+// q[i] = SplitMix64 uniform in [-1,1) (stream `stream` of `seed`)
+template <typename T>
+cr_status splitmix_fill(int64_t n, uint64_t seed, uint64_t stream, T* q, hipStream_t st);
+// hole-list Gram update: Gcol[a][c] -= sum_{i in hole_a} U[i,c] w[i] (c < r)
+template <typename T>
+cr_status hole_gram_col(int ninj, const int32_t* hptr, const int32_t* hidx, int r,
+                        const T* U, int64_t ldu, const T* w, double* out, int64_t ldo,
+                        hipStream_t st);
+
+}  // namespace cr

@@ -1,0 +1,670 @@
+// Streaming kernels of the greedy low-rank solver (gfx950, wave64):
+// graph-Laplacian stencils, tall-skinny products over voxel-length columns,
+// the masked products of the data term, and small helpers.
+#include <hip/hip_runtime.h>
+
+#include "cr_internal.hpp"
+
+namespace cr {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// ============================================================== stencil
+// (L w)_i = K w_i - sum_k w[nbr_k(i)] : with self-padded absent neighbours
+// this equals deg_i w_i - sum_{j adjacent} w_j, the graph Laplacian row.
+template <typename T, int K>
+__global__ __launch_bounds__(NT) void k_stencil(int64_t n, const int32_t* __restrict__ nbr,
+                                                int ncols, const T* __restrict__ w, int64_t ldw,
+                                                T* __restrict__ out, int64_t ldo) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  int32_t nb[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) nb[k] = nbr[(int64_t)k * n + i];
+  for (int c = blockIdx.y; c < ncols; c += gridDim.y) {
+    const T* wc = w + (int64_t)c * ldw;
+    T s = (T)K * wc[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s -= wc[nb[k]];
+    out[(int64_t)c * ldo + i] = s;
+  }
+}
+
+template <typename T>
+cr_status stencil(const Geom& g, int ncols, const T* w, int64_t ldw, T* out, int64_t ldo,
+                  hipStream_t st) {
+  if (ncols <= 0 || g.n == 0) return CR_OK;
+  dim3 grid((unsigned)((g.n + NT - 1) / NT), (unsigned)std::min(ncols, 16));
+  switch (g.K) {
+#define CASE(KK)                                                                         \
+  case KK:                                                                               \
+    hipLaunchKernelGGL((k_stencil<T, KK>), grid, dim3(NT), 0, st, g.n, g.nbr, ncols, w, \
+                       ldw, out, ldo);                                                   \
+    break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default:
+      set_error("stencil width out of range");
+      return CR_EINVAL;
+  }
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ============================================================== gemv_t
+// y = A^T x.  Workgroup b owns rows [b*RB, (b+1)*RB), RB = 64*RPL; wave w of
+// the 4 handles columns w, w+4, ...; lane l owns rows b*RB + l + 64 m, so
+// every column read is a coalesced 64-wide load.  Partial sums per
+// (column, workgroup) go to `part`; a second kernel sums them in a fixed
+// order (deterministic).
+constexpr int GT_RPL = 8;
+constexpr int GT_RB = 64 * GT_RPL;
+
+template <typename T, typename TX>
+__global__ __launch_bounds__(NT) void k_gemv_t(int64_t n, Blocks<T> A, const TX* __restrict__ x,
+                                               double* __restrict__ part, int nrb) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int64_t r0 = (int64_t)blockIdx.x * GT_RB + lane;
+  double xv[GT_RPL];
+#pragma unroll
+  for (int m = 0; m < GT_RPL; ++m) {
+    int64_t row = r0 + 64 * m;
+    xv[m] = row < n ? (double)x[row] : 0.0;
+  }
+  const int nc = A.ncols();
+  const bool full = (int64_t)(blockIdx.x + 1) * GT_RB <= n;
+  for (int c0 = wv; c0 < nc; c0 += 4 * 4) {
+    double acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int c = c0 + 4 * u;
+      if (c < nc) {
+        const T* col = A.col(c);
+        if (full) {
+#pragma unroll
+          for (int m = 0; m < GT_RPL; ++m) acc[u] += (double)col[r0 + 64 * m] * xv[m];
+        } else {
+#pragma unroll
+          for (int m = 0; m < GT_RPL; ++m) {
+            int64_t row = r0 + 64 * m;
+            if (row < n) acc[u] += (double)col[row] * xv[m];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int c = c0 + 4 * u;
+      double s = wave_sum(acc[u]);
+      if (lane == 0 && c < nc) part[(int64_t)c * nrb + blockIdx.x] = s;
+    }
+  }
+}
+
+// y[c] = sum_b part[c*nrb + b], one wave per column, fixed order.
+__global__ __launch_bounds__(NT) void k_reduce_part(int ncols, int nrb,
+                                                    const double* __restrict__ part,
+                                                    double* __restrict__ y) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int c = blockIdx.x * (NT / WAVE) + threadIdx.x / WAVE;
+  if (c >= ncols) return;
+  double s = 0.0;
+  for (int b = lane; b < nrb; b += WAVE) s += part[(int64_t)c * nrb + b];
+  s = wave_sum(s);
+  if (lane == 0) y[c] = s;
+}
+
+int64_t gemv_t_part_size(int64_t n, int ncols) {
+  return ((n + GT_RB - 1) / GT_RB) * (int64_t)ncols;
+}
+
+template <typename T, typename TX>
+cr_status gemv_tx(int64_t n, const Blocks<T>& A, const TX* x, double* y, double* part,
+                  hipStream_t st) {
+  const int nc = A.ncols();
+  if (nc == 0) return CR_OK;
+  const int nrb = (int)std::max<int64_t>(1, (n + GT_RB - 1) / GT_RB);
+  if (n == 0) {
+    CR_HIP(hipMemsetAsync(y, 0, sizeof(double) * nc, st));
+    return CR_OK;
+  }
+  hipLaunchKernelGGL((k_gemv_t<T, TX>), dim3(nrb), dim3(NT), 0, st, n, A, x, part, nrb);
+  CR_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_part, dim3((nc + 3) / 4), dim3(NT), 0, st, nc, nrb, part, y);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+template <typename T>
+cr_status gemv_t(int64_t n, const Blocks<T>& A, const T* x, double* y, double* part,
+                 hipStream_t st) {
+  return gemv_tx<T, T>(n, A, x, y, part, st);
+}
+
+// ============================================================== gemv_n
+// y = beta*y + sum_c A[:,c] coef[c]; one thread per row, coefficients in LDS.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gemv_n(int64_t n, Blocks<T> A,
+                                               const double* __restrict__ coef, double beta,
+                                               T* __restrict__ y) {
+  extern __shared__ double cs[];
+  const int nc = A.ncols();
+  for (int c = threadIdx.x; c < nc; c += NT) cs[c] = coef[c];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int b = 0; b < A.nb; ++b) {
+    const T* p = A.p[b] + i;
+    const int64_t ld = A.ld[b];
+    const int cb = A.col0[b], ce = A.col0[b + 1];
+    int c = cb;
+    for (; c + 4 <= ce; c += 4) {
+      double a0 = (double)p[(int64_t)(c - cb) * ld];
+      double a1 = (double)p[(int64_t)(c - cb + 1) * ld];
+      double a2 = (double)p[(int64_t)(c - cb + 2) * ld];
+      double a3 = (double)p[(int64_t)(c - cb + 3) * ld];
+      acc += a0 * cs[c] + a1 * cs[c + 1] + a2 * cs[c + 2] + a3 * cs[c + 3];
+    }
+    for (; c < ce; ++c) acc += (double)p[(int64_t)(c - cb) * ld] * cs[c];
+  }
+  y[i] = (T)(beta == 0.0 ? acc : beta * (double)y[i] + acc);
+}
+
+template <typename T>
+cr_status gemv_n(int64_t n, const Blocks<T>& A, const double* coef, double beta, T* y,
+                 hipStream_t st) {
+  if (n == 0) return CR_OK;
+  const int nc = A.ncols();
+  hipLaunchKernelGGL((k_gemv_n<T>), dim3((unsigned)((n + NT - 1) / NT)), dim3(NT),
+                     sizeof(double) * std::max(nc, 1), st, n, A, coef, beta, y);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ============================================================== gemm_tn
+// C = A^T B over n rows (split over gridDim.z), 64x64 output tiles, 256
+// threads with 4x4 register tiles, K staged through LDS in chunks of 32 rows.
+constexpr int TM = 64, KC = 32;
+
+template <typename T, bool MASK>
+__global__ __launch_bounds__(NT) void k_gemm_tn(int64_t n, Blocks<T> A, Blocks<T> B,
+                                                const uint32_t* __restrict__ bits,
+                                                const T* __restrict__ w, int p, int q,
+                                                int64_t kchunk, double* __restrict__ part) {
+  __shared__ double As[KC][TM + 1];
+  __shared__ double Bs[KC][TM + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int tp = blockIdx.x * TM, tq = blockIdx.y * TM;
+  const int64_t k0 = (int64_t)blockIdx.z * kchunk;
+  const int64_t k1 = std::min<int64_t>(n, k0 + kchunk);
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  // loader mapping: element e = tid + 256*m, row = e % KC, col = e / KC
+  const int lrow = tid % KC;
+  const int lcol = tid / KC;  // 0..7
+  const T* acol[8];
+  const T* bcol[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    int c = lcol + 8 * m;
+    acol[m] = (tp + c < p) ? A.col(tp + c) : nullptr;
+    bcol[m] = (!MASK && tq + c < q) ? B.col(tq + c) : nullptr;
+  }
+  for (int64_t kb = k0; kb < k1; kb += KC) {
+    const int64_t row = kb + lrow;
+    const bool rin = row < k1;
+    double wv = 0.0;
+    if (MASK && rin) wv = (double)w[row];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int c = lcol + 8 * m;
+      As[lrow][c] = (rin && acol[m]) ? (double)acol[m][row] : 0.0;
+      if (MASK) {
+        const int al = tq + c;
+        double v = 0.0;
+        if (rin && al < q) {
+          uint32_t word = bits[(int64_t)(al >> 5) * n + row];
+          v = ((word >> (al & 31)) & 1u) ? wv : 0.0;
+        }
+        Bs[lrow][c] = v;
+      } else {
+        Bs[lrow][c] = (rin && bcol[m]) ? (double)bcol[m][row] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < KC; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.z * p * q;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int i = tp + tx + 16 * a, j = tq + ty + 16 * b;
+      if (i < p && j < q) out[(int64_t)j * p + i] = acc[a][b];
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_reduce_split(int p, int q, int ks,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ C, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)p * q) return;
+  double s = 0.0;
+  for (int z = 0; z < ks; ++z) s += part[(int64_t)z * p * q + e];
+  const int64_t i = e % p, j = e / p;
+  C[j * ldc + i] = s;
+}
+
+template <typename T>
+cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint32_t* mask_bits,
+                  const T* w, int q_mask, double* C, int64_t ldc, double* part,
+                  int64_t part_cap, hipStream_t st) {
+  const int p = A.ncols();
+  const int q = mask_bits ? q_mask : B.ncols();
+  if (p == 0 || q == 0) return CR_OK;
+  if (n == 0) {
+    CR_HIP(hipMemset2DAsync(C, ldc * sizeof(double), 0, p * sizeof(double), q, st));
+    return CR_OK;
+  }
+  const int tiles = ((p + TM - 1) / TM) * ((q + TM - 1) / TM);
+  int64_t ks = std::max<int64_t>(1, 1024 / tiles);
+  ks = std::min<int64_t>(ks, std::max<int64_t>(1, (n + 4 * KC - 1) / (4 * KC)));
+  while (ks > 1 && ks * (int64_t)p * q > part_cap) --ks;
+  if (ks * (int64_t)p * q > part_cap) {
+    set_error("gemm_tn workspace too small");
+    return CR_EINVAL;
+  }
+  int64_t kchunk = (n + ks - 1) / ks;
+  kchunk = (kchunk + KC - 1) / KC * KC;
+  ks = std::max<int64_t>(1, (n + kchunk - 1) / kchunk);
+  dim3 grid((p + TM - 1) / TM, (q + TM - 1) / TM, (unsigned)ks);
+  if (mask_bits)
+    hipLaunchKernelGGL((k_gemm_tn<T, true>), grid, dim3(NT), 0, st, n, A, B, mask_bits, w, p, q,
+                       kchunk, part);
+  else
+    hipLaunchKernelGGL((k_gemm_tn<T, false>), grid, dim3(NT), 0, st, n, A, B, mask_bits, w, p,
+                       q, kchunk, part);
+  CR_HIP(hipGetLastError());
+  const int64_t pq = (int64_t)p * q;
+  hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((pq + NT - 1) / NT)), dim3(NT), 0, st, p,
+                     q, (int)ks, part, C, ldc);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ============================================================== masked tall GEMM
+// N[i,a] = OY[i,a] - omega_ia * sum_k U[i,k] T[k,a]   (or +omega*UT when OY null)
+// Workgroup: 64 rows x 128 columns; thread (row lane, column group g of 4)
+// accumulates 32 columns.  T staged through LDS in chunks of 32 rows.
+constexpr int MG_ROWS = 64, MG_CPT = 32, MG_KC = 32;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_masked_tall_gemm(
+    int64_t n, int r, int ninj, const T* __restrict__ U, int64_t ldu, const double* __restrict__ Tm,
+    int64_t ldt, const uint32_t* __restrict__ bits, const T* __restrict__ OY, int64_t ldoy,
+    T* __restrict__ N, int64_t ldn) {
+  __shared__ double Ts[MG_KC][4 * MG_CPT];
+  const int lane = threadIdx.x & 63;
+  const int grp = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * MG_ROWS + lane;
+  const int a0 = blockIdx.y * (4 * MG_CPT);
+  double acc[MG_CPT];
+#pragma unroll
+  for (int c = 0; c < MG_CPT; ++c) acc[c] = 0.0;
+  for (int k0 = 0; k0 < r; k0 += MG_KC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < MG_KC * 4 * MG_CPT; e += NT) {
+      int kk = e / (4 * MG_CPT), cc = e % (4 * MG_CPT);
+      int k = k0 + kk, a = a0 + cc;
+      Ts[kk][cc] = (k < r && a < ninj) ? Tm[(int64_t)a * ldt + k] : 0.0;
+    }
+    __syncthreads();
+    const int kn = std::min(MG_KC, r - k0);
+    if (i < n) {
+      for (int kk = 0; kk < kn; ++kk) {
+        const double u = (double)U[(int64_t)(k0 + kk) * ldu + i];
+#pragma unroll
+        for (int c = 0; c < MG_CPT; ++c) acc[c] += u * Ts[kk][grp * MG_CPT + c];
+      }
+    }
+  }
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < MG_CPT; ++c) {
+    const int a = a0 + grp * MG_CPT + c;
+    if (a < ninj) {
+      const uint32_t word = bits[(int64_t)(a >> 5) * n + i];
+      const double om = (double)((word >> (a & 31)) & 1u);
+      const double v = om * acc[c];
+      N[(int64_t)a * ldn + i] = OY ? (T)((double)OY[(int64_t)a * ldoy + i] - v) : (T)v;
+    }
+  }
+}
+
+template <typename T>
+cr_status masked_tall_gemm(int64_t n, int r, int ninj, const T* U, int64_t ldu, const double* Tm,
+                           int64_t ldt, const uint32_t* bits, const T* OY, int64_t ldoy, T* N,
+                           int64_t ldn, hipStream_t st) {
+  if (n == 0 || ninj == 0) return CR_OK;
+  dim3 grid((unsigned)((n + MG_ROWS - 1) / MG_ROWS), (ninj + 4 * MG_CPT - 1) / (4 * MG_CPT));
+  hipLaunchKernelGGL((k_masked_tall_gemm<T>), grid, dim3(NT), 0, st, n, r, ninj, U, ldu, Tm, ldt,
+                     bits, OY, ldoy, N, ldn);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ============================================================== masked reductions
+// d_i = sum_a omega_ia h_a^2 = sum_a h_a^2 - sum_{a: omega_ia = 0} h_a^2
+__global__ __launch_bounds__(NT) void k_hsq(int ninj, const double* __restrict__ h,
+                                            double* __restrict__ out) {
+  __shared__ double red[NT / WAVE];
+  double s = 0.0;
+  for (int a = threadIdx.x; a < ninj; a += NT) s += h[a] * h[a];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_masked_quad(int64_t n, int ninj,
+                                                    const uint32_t* __restrict__ bits,
+                                                    const double* __restrict__ h,
+                                                    const double* __restrict__ hsq_total,
+                                                    T* __restrict__ d) {
+  extern __shared__ double h2[];
+  for (int a = threadIdx.x; a < ninj; a += NT) h2[a] = h[a] * h[a];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  double s = hsq_total[0];
+  const int nw = (ninj + 31) / 32;
+  for (int wdx = 0; wdx < nw; ++wdx) {
+    uint32_t zero = ~bits[(int64_t)wdx * n + i];
+    const int valid = ninj - 32 * wdx;
+    if (valid < 32) zero &= (1u << valid) - 1u;
+    while (zero) {
+      const int b = __ffs(zero) - 1;
+      s -= h2[32 * wdx + b];
+      zero &= zero - 1u;
+    }
+  }
+  d[i] = (T)s;
+}
+
+template <typename T>
+cr_status masked_quad_ws(int64_t n, int ninj, const uint32_t* bits, const double* h, T* d,
+                         double* tmp, hipStream_t st) {
+  if (n == 0) return CR_OK;
+  hipLaunchKernelGGL(k_hsq, dim3(1), dim3(NT), 0, st, ninj, h, tmp);
+  CR_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_masked_quad<T>), dim3((unsigned)((n + NT - 1) / NT)), dim3(NT),
+                     sizeof(double) * std::max(ninj, 1), st, n, ninj, bits, h, tmp, d);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// g_a = sum_i omega_ia w_i^2: structure of k_gemv_t with the mask as matrix.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_masked_colsq(int64_t n, int ninj,
+                                                     const uint32_t* __restrict__ bits,
+                                                     const T* __restrict__ w,
+                                                     double* __restrict__ part, int nrb) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int64_t r0 = (int64_t)blockIdx.x * GT_RB + lane;
+  double xv[GT_RPL];
+#pragma unroll
+  for (int m = 0; m < GT_RPL; ++m) {
+    int64_t row = r0 + 64 * m;
+    double t = row < n ? (double)w[row] : 0.0;
+    xv[m] = t * t;
+  }
+  const int nw = (ninj + 31) / 32;
+  for (int wdx = 0; wdx < nw; ++wdx) {
+    uint32_t word[GT_RPL];
+#pragma unroll
+    for (int m = 0; m < GT_RPL; ++m) {
+      int64_t row = r0 + 64 * m;
+      word[m] = row < n ? bits[(int64_t)wdx * n + row] : 0u;
+    }
+    for (int b = wv; b < 32 && 32 * wdx + b < ninj; b += 4) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < GT_RPL; ++m) acc += ((word[m] >> b) & 1u) ? xv[m] : 0.0;
+      acc = wave_sum(acc);
+      if (lane == 0) part[(int64_t)(32 * wdx + b) * nrb + blockIdx.x] = acc;
+    }
+  }
+}
+
+template <typename T>
+cr_status masked_colsq(int64_t n, int ninj, const uint32_t* bits, const T* w, double* g,
+                       double* part, hipStream_t st) {
+  if (ninj == 0) return CR_OK;
+  const int nrb = (int)std::max<int64_t>(1, (n + GT_RB - 1) / GT_RB);
+  if (n == 0) {
+    CR_HIP(hipMemsetAsync(g, 0, sizeof(double) * ninj, st));
+    return CR_OK;
+  }
+  hipLaunchKernelGGL((k_masked_colsq<T>), dim3(nrb), dim3(NT), 0, st, n, ninj, bits, w, part,
+                     nrb);
+  CR_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_part, dim3((ninj + 3) / 4), dim3(NT), 0, st, ninj, nrb, part, g);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ============================================================== elementwise / small
+template <typename Td, typename Ts>
+__global__ __launch_bounds__(NT) void k_convert2d(int64_t rows, int64_t cols,
+                                                  const Ts* __restrict__ src, int64_t lds,
+                                                  Td* __restrict__ dst, int64_t ldd) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= rows) return;
+  for (int64_t c = blockIdx.y; c < cols; c += gridDim.y) dst[c * ldd + i] = (Td)src[c * lds + i];
+}
+
+template <typename Td, typename Ts>
+cr_status convert2d(int64_t rows, int64_t cols, const Ts* src, int64_t lds, Td* dst, int64_t ldd,
+                    hipStream_t st) {
+  if (rows == 0 || cols == 0) return CR_OK;
+  dim3 grid((unsigned)((rows + NT - 1) / NT), (unsigned)std::min<int64_t>(cols, 64));
+  hipLaunchKernelGGL((k_convert2d<Td, Ts>), grid, dim3(NT), 0, st, rows, cols, src, lds, dst, ldd);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+template <typename Td, typename Ts>
+cr_status convert(int64_t n, const Ts* src, Td* dst, hipStream_t st) {
+  return convert2d<Td, Ts>(n, 1, src, n, dst, n, st);
+}
+
+// out[i] = alpha * sum_k op(M)[i,k] v[k]; one workgroup (small sizes only)
+__global__ __launch_bounds__(NT) void k_small_gemv(int m, int kk, const double* __restrict__ M,
+                                                   int64_t ldm, int trans,
+                                                   const double* __restrict__ v, double alpha,
+                                                   double* __restrict__ out) {
+  for (int i = threadIdx.x + blockIdx.x * NT; i < m; i += NT * gridDim.x) {
+    double s = 0.0;
+    if (trans)
+      for (int k = 0; k < kk; ++k) s += M[(int64_t)i * ldm + k] * v[k];
+    else
+      for (int k = 0; k < kk; ++k) s += M[(int64_t)k * ldm + i] * v[k];
+    out[i] = alpha * s;
+  }
+}
+
+cr_status small_gemv(int m, int kk, const double* M, int64_t ldm, bool trans, const double* v,
+                     double alpha, double* out, hipStream_t st) {
+  if (m <= 0) return CR_OK;
+  hipLaunchKernelGGL(k_small_gemv, dim3((m + NT - 1) / NT), dim3(NT), 0, st, m, kk, M, ldm,
+                     trans ? 1 : 0, v, alpha, out);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+__global__ __launch_bounds__(NT) void k_small_gemm(int m, int n, int k, const double* __restrict__ A,
+                                                   int64_t lda, int ta, const double* __restrict__ B,
+                                                   int64_t ldb, int tb, double alpha,
+                                                   double* __restrict__ C, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)m * n) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  const int64_t sa_i = ta ? lda : 1, sa_t = ta ? 1 : lda;
+  const int64_t sb_t = tb ? ldb : 1, sb_j = tb ? 1 : ldb;
+  double s = 0.0;
+  for (int t = 0; t < k; ++t) s += A[i * sa_i + t * sa_t] * B[t * sb_t + j * sb_j];
+  C[(int64_t)j * ldc + i] = alpha * s;
+}
+
+cr_status small_gemm(int m, int n, int k, const double* A, int64_t lda, bool ta, const double* B,
+                     int64_t ldb, bool tb, double alpha, double* C, int64_t ldc, hipStream_t st) {
+  if (m <= 0 || n <= 0) return CR_OK;
+  const int64_t mn = (int64_t)m * n;
+  hipLaunchKernelGGL(k_small_gemm, dim3((unsigned)((mn + NT - 1) / NT)), dim3(NT), 0, st, m, n, k,
+                     A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, alpha, C, ldc);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_scale_inv_sqrt(int64_t n, T* __restrict__ x,
+                                                       const double* __restrict__ nrm2) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const double s = 1.0 / sqrt(nrm2[0]);
+  x[i] = (T)((double)x[i] * s);
+}
+
+template <typename T>
+cr_status scale_inv_sqrt(int64_t n, T* x, const double* nrm2, hipStream_t st) {
+  if (n == 0) return CR_OK;
+  hipLaunchKernelGGL((k_scale_inv_sqrt<T>), dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st,
+                     n, x, nrm2);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): output k >= 1 of the generator whose
+// state starts at seed ^ (stream * 0xD1B54A32D192ED03), top 53 bits mapped to
+// [-1, 1).
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_splitmix(int64_t n, uint64_t state, T* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t z = sm64_mix(state + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull);
+  q[i] = (T)((double)(z >> 11) * 0x1.0p-52 - 1.0);
+}
+
+template <typename T>
+cr_status splitmix_fill(int64_t n, uint64_t seed, uint64_t stream, T* q, hipStream_t st) {
+  if (n == 0) return CR_OK;
+  const uint64_t state = seed ^ (stream * 0xD1B54A32D192ED03ull);
+  hipLaunchKernelGGL((k_splitmix<T>), dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, n,
+                     state, q);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// out[c + a*ldo] -= sum_{i in hole_a} U[i,c] w[i]   (one workgroup per a)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_hole_gram_col(const int32_t* __restrict__ hptr,
+                                                      const int32_t* __restrict__ hidx, int r,
+                                                      const T* __restrict__ U, int64_t ldu,
+                                                      const T* __restrict__ w,
+                                                      double* __restrict__ out, int64_t ldo) {
+  __shared__ double red[NT / WAVE];
+  const int a = blockIdx.x;
+  const int b = hptr[a], e = hptr[a + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c = 0; c < r; ++c) {
+    double s = 0.0;
+    for (int k = b + threadIdx.x; k < e; k += NT) {
+      const int64_t i = hidx[k];
+      s += (double)U[(int64_t)c * ldu + i] * (double)w[i];
+    }
+    s = wave_sum(s);
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[(int64_t)a * ldo + c] -= red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+cr_status hole_gram_col(int ninj, const int32_t* hptr, const int32_t* hidx, int r, const T* U,
+                        int64_t ldu, const T* w, double* out, int64_t ldo, hipStream_t st) {
+  if (ninj == 0 || r == 0) return CR_OK;
+  hipLaunchKernelGGL((k_hole_gram_col<T>), dim3(ninj), dim3(NT), 0, st, hptr, hidx, r, U, ldu, w,
+                     out, ldo);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ============================================================== instantiations
+#define INST(T)                                                                                  \
+  template cr_status stencil<T>(const Geom&, int, const T*, int64_t, T*, int64_t, hipStream_t); \
+  template cr_status gemv_t<T>(int64_t, const Blocks<T>&, const T*, double*, double*,           \
+                               hipStream_t);                                                    \
+  template cr_status gemv_n<T>(int64_t, const Blocks<T>&, const double*, double, T*,            \
+                               hipStream_t);                                                    \
+  template cr_status gemm_tn<T>(int64_t, const Blocks<T>&, const Blocks<T>&, const uint32_t*,   \
+                                const T*, int, double*, int64_t, double*, int64_t,             \
+                                hipStream_t);                                                   \
+  template cr_status masked_tall_gemm<T>(int64_t, int, int, const T*, int64_t, const double*,   \
+                                         int64_t, const uint32_t*, const T*, int64_t, T*,       \
+                                         int64_t, hipStream_t);                                 \
+  template cr_status masked_quad_ws<T>(int64_t, int, const uint32_t*, const double*, T*,        \
+                                       double*, hipStream_t);                                   \
+  template cr_status masked_colsq<T>(int64_t, int, const uint32_t*, const T*, double*,          \
+                                     double*, hipStream_t);                                     \
+  template cr_status scale_inv_sqrt<T>(int64_t, T*, const double*, hipStream_t);                \
+  template cr_status splitmix_fill<T>(int64_t, uint64_t, uint64_t, T*, hipStream_t);            \
+  template cr_status hole_gram_col<T>(int, const int32_t*, const int32_t*, int, const T*,       \
+                                      int64_t, const T*, double*, int64_t, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+template cr_status gemv_tx<float, double>(int64_t, const Blocks<float>&, const double*, double*,
+                                          double*, hipStream_t);
+template cr_status convert2d<float, double>(int64_t, int64_t, const double*, int64_t, float*,
+                                            int64_t, hipStream_t);
+template cr_status convert2d<double, float>(int64_t, int64_t, const float*, int64_t, double*,
+                                            int64_t, hipStream_t);
+template cr_status convert2d<double, double>(int64_t, int64_t, const double*, int64_t, double*,
+                                             int64_t, hipStream_t);
+template cr_status convert2d<float, float>(int64_t, int64_t, const float*, int64_t, float*,
+                                           int64_t, hipStream_t);
+template cr_status convert<float, double>(int64_t, const double*, float*, hipStream_t);
+template cr_status convert<double, float>(int64_t, const float*, double*, hipStream_t);
+
+}  // namespace cr

@@ -1,0 +1,651 @@
+// Persistent (cooperative) conjugate-gradient kernels:
+//  * k_pcg      Jacobi-PCG on the ALS half-step systems (eqs. ALS_linsys and
+//               ALS_linsys_v), one launch per solve, three grid barriers per
+//               iteration;
+//  * k_galerkin matrix-valued CG on the projected equation (eq. Proj_Sylv)
+//               in FP64, four grid barriers per iteration.
+// Control flow is uniform over the grid: every workgroup reduces the same
+// partial sums in the same order, so all take identical branch decisions and
+// every grid barrier is reached by all workgroups; loops are bounded by maxit.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "cr_internal.hpp"
+
+namespace cgrp = cooperative_groups;
+
+namespace cr {
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// Sum of v over the workgroup; result returned to every thread.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wsum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < NT / WAVE; ++k) s += red[k];
+  return s;
+}
+
+// Grid total of slot `slot` of the partial array (part[slot*nwg + b]),
+// summed in the same order by every workgroup.
+__device__ __forceinline__ double grid_total(const double* part, int slot, int nwg, double* red) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nwg; b += NT) s += part[(int64_t)slot * nwg + b];
+  return block_sum(s, red);
+}
+
+constexpr int PCG_MAX_VPT = 8;
+constexpr int PCG_MAX_NINJ = 1024;
+// Partial-sum slots.  Every slot has one writer phase per use and is never
+// rewritten before a grid barrier separates the write from all reads: the
+// final phase, which may start while slower workgroups still read the slots
+// of the exit test, has a slot of its own.
+constexpr int PCG_SLOTS = 5;  // 0: p.q, 1: r.z, 2: r.r, 3: b.b, 4: x.x
+
+template <typename T, int K>
+__device__ __forceinline__ double lap(const T* __restrict__ w, const int32_t* __restrict__ nbr,
+                                      int64_t n, int64_t i) {
+  double s = (double)K * (double)w[i];
+#pragma unroll
+  for (int k = 0; k < K; ++k) s -= (double)w[nbr[(int64_t)k * n + i]];
+  return s;
+}
+
+// partial X^T z over this workgroup's voxels, z staged in LDS
+template <typename T>
+__device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, int64_t n, int nwg,
+                           double* lrpart) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int per = a.vpt * (NT / WAVE);  // rows per lane
+  for (int al = wv; al < a.ninj; al += NT / WAVE) {
+    const T* xc = a.Xm + (int64_t)al * a.ldx;
+    double acc = 0.0;
+    for (int k = 0; k < per; ++k) {
+      const int loc = lane + WAVE * k;
+      const int64_t i = lo + loc;
+      if (i < n) acc += (double)xc[i] * zs[loc];
+    }
+    acc = wsum(acc);
+    if (lane == 0) lrpart[(int64_t)al * nwg + blockIdx.x] = acc;
+  }
+}
+
+template <typename T, int K, bool LR>
+__global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
+  cgrp::grid_group grid = cgrp::this_grid();
+  __shared__ double red[NT / WAVE];
+  __shared__ double zs[NT * PCG_MAX_VPT];
+  __shared__ double slr[LR ? PCG_MAX_NINJ : 1];
+  const int64_t n = a.g.n;
+  const int32_t* __restrict__ nbr = a.g.nbr;
+  const int nwg = gridDim.x;
+  const int vpt = a.vpt;
+  const int64_t lo = (int64_t)blockIdx.x * NT * vpt;
+  double* part = a.part;
+  double* lrpart = a.part + PCG_SLOTS * nwg;
+  const double lam = a.lam;
+  const double c1 = a.coef[0], c0 = a.coef[1];
+
+  // ---- setup: x = 0, r = b, z = M^-1 r
+  double rz = 0.0, bb = 0.0;
+  for (int m = 0; m < vpt; ++m) {
+    const int loc = threadIdx.x + NT * m;
+    const int64_t i = lo + loc;
+    double zi = 0.0;
+    if (i < n) {
+      const double bi = (double)a.b[i];
+      zi = (double)a.minv[i] * bi;
+      a.x[i] = (T)0;
+      a.r[i] = (T)bi;
+      a.z[i] = (T)zi;
+      rz += bi * zi;
+      bb += bi * bi;
+    }
+    zs[loc] = (double)(T)zi;
+  }
+  __syncthreads();
+  if (LR) lr_partial(a, zs, lo, n, nwg, lrpart);
+  rz = block_sum(rz, red);
+  bb = block_sum(bb, red);
+  if (threadIdx.x == 0) {
+    part[1 * nwg + blockIdx.x] = rz;
+    part[3 * nwg + blockIdx.x] = bb;
+  }
+  grid.sync();
+  double rz_cur = grid_total(part, 1, nwg, red);
+  const double bnorm2 = grid_total(part, 3, nwg, red);
+  int status = 0, it = 0;
+  double rr = bnorm2;
+  const double tol2 = a.rtol * a.rtol * bnorm2;
+  if (!(bnorm2 > 0.0)) status = 2;  // zero or non-finite right-hand side
+
+  double beta = 0.0;
+  if (status == 0) {
+    // ---- p = z, t = L z, s = X^T z
+    for (int m = 0; m < vpt; ++m) {
+      const int64_t i = lo + threadIdx.x + NT * m;
+      if (i < n) {
+        a.p[i] = a.z[i];
+        a.t[i] = (T)lap<T, K>(a.z, nbr, n, i);
+      }
+    }
+    if (LR) {
+      for (int al = blockIdx.x; al < a.ninj; al += nwg) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nwg; b += NT) s += lrpart[(int64_t)al * nwg + b];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) a.sbuf[al] = s;
+      }
+    }
+    grid.sync();
+
+    for (it = 0; it < a.maxit; ++it) {
+      // ---- phase B: q = A p, partial p.q
+      if (LR) {
+        for (int al = threadIdx.x; al < a.ninj; al += NT) slr[al] = a.gw[al] * a.sbuf[al];
+        __syncthreads();
+      }
+      double pq = 0.0;
+      for (int m = 0; m < vpt; ++m) {
+        const int64_t i = lo + threadIdx.x + NT * m;
+        if (i < n) {
+          const double pi = (double)a.p[i];
+          const double ti = (double)a.t[i];
+          double qi = lam * (lap<T, K>(a.t, nbr, n, i) + c1 * ti + c0 * pi);
+          if (a.dvec) qi += (double)a.dvec[i] * pi;
+          if (LR) {
+            double s = 0.0;
+            for (int al = 0; al < a.ninj; ++al) s += (double)a.Xm[(int64_t)al * a.ldx + i] * slr[al];
+            qi += s;
+          }
+          a.q[i] = (T)qi;
+          pq += pi * (double)(T)qi;
+        }
+      }
+      pq = block_sum(pq, red);
+      if (threadIdx.x == 0) part[0 * nwg + blockIdx.x] = pq;
+      grid.sync();
+
+      // ---- phase C: x += alpha p, r -= alpha q, z = M^-1 r
+      const double pq_tot = grid_total(part, 0, nwg, red);
+      if (!(pq_tot > 0.0)) {
+        status = 2;
+        break;
+      }
+      const double alpha = rz_cur / pq_tot;
+      double rzn = 0.0, rrn = 0.0;
+      for (int m = 0; m < vpt; ++m) {
+        const int loc = threadIdx.x + NT * m;
+        const int64_t i = lo + loc;
+        double zi = 0.0;
+        if (i < n) {
+          const double pi = (double)a.p[i];
+          a.x[i] = (T)((double)a.x[i] + alpha * pi);
+          const double ri = (double)(T)((double)a.r[i] - alpha * (double)a.q[i]);
+          a.r[i] = (T)ri;
+          zi = (double)(T)((double)a.minv[i] * ri);
+          a.z[i] = (T)zi;
+          rzn += ri * zi;
+          rrn += ri * ri;
+        }
+        zs[loc] = zi;
+      }
+      __syncthreads();
+      if (LR) lr_partial(a, zs, lo, n, nwg, lrpart);
+      rzn = block_sum(rzn, red);
+      rrn = block_sum(rrn, red);
+      if (threadIdx.x == 0) {
+        part[1 * nwg + blockIdx.x] = rzn;
+        part[2 * nwg + blockIdx.x] = rrn;
+      }
+      grid.sync();
+
+      // ---- phase D: beta, convergence, p = z + beta p, t = L z + beta t
+      const double rz_new = grid_total(part, 1, nwg, red);
+      rr = grid_total(part, 2, nwg, red);
+      if (rr <= tol2) {
+        ++it;
+        break;
+      }
+      beta = rz_new / rz_cur;
+      rz_cur = rz_new;
+      for (int m = 0; m < vpt; ++m) {
+        const int64_t i = lo + threadIdx.x + NT * m;
+        if (i < n) {
+          a.p[i] = (T)((double)a.z[i] + beta * (double)a.p[i]);
+          a.t[i] = (T)(lap<T, K>(a.z, nbr, n, i) + beta * (double)a.t[i]);
+        }
+      }
+      if (LR) {
+        for (int al = blockIdx.x; al < a.ninj; al += nwg) {
+          double s = 0.0;
+          for (int b = threadIdx.x; b < nwg; b += NT) s += lrpart[(int64_t)al * nwg + b];
+          s = block_sum(s, red);
+          if (threadIdx.x == 0) a.sbuf[al] = s + beta * a.sbuf[al];
+        }
+      }
+      grid.sync();
+    }
+    if (status == 0 && !(rr <= tol2)) status = 1;
+  }
+
+  // ---- final: xout = x / ||x||
+  double xx = 0.0;
+  for (int m = 0; m < vpt; ++m) {
+    const int64_t i = lo + threadIdx.x + NT * m;
+    if (i < n) {
+      const double xi = (double)a.x[i];
+      xx += xi * xi;
+    }
+  }
+  xx = block_sum(xx, red);
+  if (threadIdx.x == 0) part[4 * nwg + blockIdx.x] = xx;
+  grid.sync();
+  const double xnorm2 = grid_total(part, 4, nwg, red);
+  const double xn = sqrt(xnorm2);
+  const double inv = xn > 0.0 ? 1.0 / xn : 0.0;
+  for (int m = 0; m < vpt; ++m) {
+    const int64_t i = lo + threadIdx.x + NT * m;
+    if (i < n) a.xout[i] = (T)((double)a.x[i] * inv);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal[0] = xn;
+    a.scal[1] = bnorm2 > 0.0 ? sqrt(rr / bnorm2) : 0.0;
+    a.scal[2] = (double)it;
+    a.scal[3] = (double)status;
+  }
+}
+
+template <typename T, int K, bool LR>
+static void* pcg_fn() {
+  return (void*)&k_pcg<T, K, LR>;
+}
+
+template <typename T>
+static void* pcg_select(int K, bool lr) {
+  switch (K) {
+#define CASE(KK) \
+  case KK:       \
+    return lr ? pcg_fn<T, KK, true>() : pcg_fn<T, KK, false>();
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default:
+      return nullptr;
+  }
+}
+
+template <typename T>
+int pcg_max_wg(const PcgArgs<T>& a) {
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr);
+  if (!fn) return 0;
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, NT, 0) != hipSuccess) return 0;
+  return per * ncu;
+}
+
+template <typename T>
+cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
+  if (a.vpt < 1 || a.vpt > PCG_MAX_VPT) {
+    set_error("pcg: voxels per thread out of range");
+    return CR_EINVAL;
+  }
+  if (a.Xm && a.ninj > PCG_MAX_NINJ) {
+    set_error("pcg: n_inj above the low-rank limit");
+    return CR_EINVAL;
+  }
+  if ((int64_t)nwg * NT * a.vpt < a.g.n) {
+    set_error("pcg: grid does not cover the voxels");
+    return CR_EINVAL;
+  }
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr);
+  if (!fn) {
+    set_error("pcg: unsupported stencil width");
+    return CR_EINVAL;
+  }
+  PcgArgs<T> arg = a;
+  void* params[] = {&arg};
+  CR_HIP(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(NT), params, 0, st));
+  return CR_OK;
+}
+
+// Jacobi inverse diagonal.  (L^2)_ii = deg_i^2 + deg_i for a unit-weight
+// graph Laplacian, (L)_ii = deg_i.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pcg_diag(int64_t n, const uint8_t* __restrict__ deg,
+                                                 double lam, const double* __restrict__ coef,
+                                                 const T* __restrict__ dvec,
+                                                 const T* __restrict__ Xm, int64_t ldx, int ninj,
+                                                 const double* __restrict__ gw,
+                                                 T* __restrict__ minv) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const double dg = (double)deg[i];
+  double v = lam * (dg * dg + dg + coef[0] * dg + coef[1]);
+  if (dvec) v += (double)dvec[i];
+  if (Xm)
+    for (int al = 0; al < ninj; ++al) {
+      const double x = (double)Xm[(int64_t)al * ldx + i];
+      v += gw[al] * x * x;
+    }
+  minv[i] = (T)(v > 0.0 ? 1.0 / v : 1.0);
+}
+
+template <typename T>
+cr_status pcg_diag(const Geom& g, double lam, const double* coef, const T* dvec, const T* Xm,
+                   int64_t ldx, int ninj, const double* gw, T* minv, hipStream_t st) {
+  if (g.n == 0) return CR_OK;
+  hipLaunchKernelGGL((k_pcg_diag<T>), dim3((unsigned)((g.n + NT - 1) / NT)), dim3(NT), 0, st, g.n,
+                     g.deg, lam, coef, dvec, Xm, ldx, ninj, gw, minv);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ================================================================ Galerkin CG
+// Partial-sum slots: 0 <P,Q>, 1 initial ||R||^2, 2 ||R||^2, 3 ||B||^2,
+// 4 <Z,B>, 5 <Z,R> (6 * nwg doubles).
+// A_p(P) = lam (P Bx2 + 2 By1 P Bx1 + By2 P) + sum_a G_a (P h_a) h_a^T, with
+// h_a = H[:,a] (H(k,a) stored as Ht[a + k*ninj]).  Column c of every r x r
+// matrix is owned by workgroup c mod nwg for element-wise updates.
+__device__ __forceinline__ double Hk(const GalerkinArgs& a, int k, int al) {
+  return a.H[(int64_t)k * a.ninj + al];
+}
+__device__ __forceinline__ double Sk(const GalerkinArgs& a, int k, int al) {
+  return a.S[(int64_t)k * a.ninj + al];
+}
+
+// phase 1: SG[:,a] = G_a (P h_a) for the workgroup's injections; Y2 = By1 P
+// for its columns.
+__device__ void gal_phase1(const GalerkinArgs& a, const double* Pm, double* tsh) {
+  const int r = a.r, ld = a.ldr;
+  for (int al = blockIdx.x; al < a.ninj; al += gridDim.x) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < r; i += NT) {
+      double s = 0.0;
+      for (int k = 0; k < r; ++k) s += Pm[(int64_t)k * ld + i] * Hk(a, k, al);
+      tsh[i] = s;
+    }
+    __syncthreads();
+    const double* Ga = a.G + (int64_t)al * ld * ld;
+    for (int i = threadIdx.x; i < r; i += NT) {
+      double s = 0.0;
+      for (int k = 0; k < r; ++k) s += Ga[(int64_t)k * ld + i] * tsh[k];
+      a.SG[(int64_t)al * ld + i] = s;
+    }
+  }
+  for (int c = blockIdx.x; c < r; c += gridDim.x) {
+    for (int i = threadIdx.x; i < r; i += NT) {
+      double s = 0.0;
+      for (int k = 0; k < r; ++k) s += a.By1[(int64_t)k * ld + i] * Pm[(int64_t)c * ld + k];
+      a.Y2[(int64_t)c * ld + i] = s;
+    }
+  }
+}
+
+// phase 2: Q[:,c] for the workgroup's columns; returns partial <Pm, Q>.
+__device__ double gal_phase2(const GalerkinArgs& a, const double* Pm) {
+  const int r = a.r, ld = a.ldr;
+  double dot = 0.0;
+  for (int c = blockIdx.x; c < r; c += gridDim.x) {
+    for (int i = threadIdx.x; i < r; i += NT) {
+      double s = 0.0;
+      for (int al = 0; al < a.ninj; ++al) s += a.SG[(int64_t)al * ld + i] * Hk(a, c, al);
+      double t = 0.0;
+      for (int k = 0; k < r; ++k)
+        t += Pm[(int64_t)k * ld + i] * a.Bx2[(int64_t)c * ld + k] +
+             a.By2[(int64_t)k * ld + i] * Pm[(int64_t)c * ld + k] +
+             2.0 * a.Y2[(int64_t)k * ld + i] * a.Bx1[(int64_t)c * ld + k];
+      const double q = s + a.lam * t;
+      a.Q[(int64_t)c * ld + i] = q;
+      dot += Pm[(int64_t)c * ld + i] * q;
+    }
+  }
+  return dot;
+}
+
+__global__ __launch_bounds__(NT) void k_galerkin(GalerkinArgs a) {
+  cgrp::grid_group grid = cgrp::this_grid();
+  __shared__ double red[NT / WAVE];
+  extern __shared__ double tsh[];
+  const int r = a.r, ld = a.ldr, nwg = gridDim.x;
+  double* part = a.part;
+
+  // ---- B = S H^T ; Q = A_p(Z)
+  gal_phase1(a, a.Z, tsh);
+  for (int c = blockIdx.x; c < r; c += nwg)
+    for (int i = threadIdx.x; i < r; i += NT) {
+      double s = 0.0;
+      for (int al = 0; al < a.ninj; ++al) s += Sk(a, i, al) * Hk(a, c, al);
+      a.Bm[(int64_t)c * ld + i] = s;
+    }
+  grid.sync();
+  gal_phase2(a, a.Z);
+  // R = B - Q, P = R (own columns); partial ||R||^2, ||B||^2
+  double rr = 0.0, bb = 0.0;
+  for (int c = blockIdx.x; c < r; c += nwg)
+    for (int i = threadIdx.x; i < r; i += NT) {
+      const int64_t e = (int64_t)c * ld + i;
+      const double b = a.Bm[e];
+      const double rv = b - a.Q[e];
+      a.R[e] = rv;
+      a.P[e] = rv;
+      rr += rv * rv;
+      bb += b * b;
+    }
+  rr = block_sum(rr, red);
+  bb = block_sum(bb, red);
+  if (threadIdx.x == 0) {
+    part[1 * nwg + blockIdx.x] = rr;
+    part[3 * nwg + blockIdx.x] = bb;
+  }
+  grid.sync();
+  rr = grid_total(part, 1, nwg, red);
+  bb = grid_total(part, 3, nwg, red);
+  const double tol2 = a.rtol * a.rtol * bb;
+  int it = 0, status = 0;
+  for (; it < a.maxit && rr > tol2; ++it) {
+    gal_phase1(a, a.P, tsh);
+    grid.sync();
+    double pq = gal_phase2(a, a.P);
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) part[0 * nwg + blockIdx.x] = pq;
+    grid.sync();
+    const double pq_tot = grid_total(part, 0, nwg, red);
+    if (!(pq_tot > 0.0)) {
+      status = 2;
+      break;
+    }
+    const double alpha = rr / pq_tot;
+    double rrn = 0.0;
+    for (int c = blockIdx.x; c < r; c += nwg)
+      for (int i = threadIdx.x; i < r; i += NT) {
+        const int64_t e = (int64_t)c * ld + i;
+        a.Z[e] += alpha * a.P[e];
+        const double rv = a.R[e] - alpha * a.Q[e];
+        a.R[e] = rv;
+        rrn += rv * rv;
+      }
+    rrn = block_sum(rrn, red);
+    if (threadIdx.x == 0) part[2 * nwg + blockIdx.x] = rrn;
+    grid.sync();
+    const double rr_new = grid_total(part, 2, nwg, red);
+    const double beta = rr_new / rr;
+    rr = rr_new;
+    if (rr <= tol2) {
+      ++it;
+      break;
+    }
+    for (int c = blockIdx.x; c < r; c += nwg)
+      for (int i = threadIdx.x; i < r; i += NT) {
+        const int64_t e = (int64_t)c * ld + i;
+        a.P[e] = a.R[e] + beta * a.P[e];
+      }
+    grid.sync();
+  }
+  if (status == 0 && rr > tol2) status = 1;
+  // energy pieces: <Z, B>, <Z, R>
+  double zb = 0.0, zr = 0.0;
+  for (int c = blockIdx.x; c < r; c += nwg)
+    for (int i = threadIdx.x; i < r; i += NT) {
+      const int64_t e = (int64_t)c * ld + i;
+      zb += a.Z[e] * a.Bm[e];
+      zr += a.Z[e] * a.R[e];
+    }
+  zb = block_sum(zb, red);
+  zr = block_sum(zr, red);
+  // slots 4, 5 are written only here (slower workgroups may still be reading
+  // slots 0..3 of the exit test)
+  if (threadIdx.x == 0) {
+    part[4 * nwg + blockIdx.x] = zb;
+    part[5 * nwg + blockIdx.x] = zr;
+  }
+  grid.sync();
+  zb = grid_total(part, 4, nwg, red);
+  zr = grid_total(part, 5, nwg, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal[0] = (double)it;
+    a.scal[1] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    a.scal[2] = (double)status;
+    a.scal[3] = -0.5 * zb - 0.5 * zr;  // 1/2 <Z, A_p Z> - <Z, B> with A_p Z = B - R
+  }
+}
+
+int galerkin_max_wg(int r) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (void*)k_galerkin, NT,
+                                                   sizeof(double) * std::max(r, 1)) != hipSuccess)
+    return 0;
+  return per * ncu;
+}
+
+cr_status galerkin_cg(const GalerkinArgs& a, int nwg, hipStream_t st) {
+  if (a.r <= 0) return CR_OK;
+  GalerkinArgs arg = a;
+  void* params[] = {&arg};
+  CR_HIP(hipLaunchCooperativeKernel((void*)k_galerkin, dim3(nwg), dim3(NT), params,
+                                    sizeof(double) * a.r, st));
+  return CR_OK;
+}
+
+// ------------------------------------------------------------ refinement helpers
+template <typename T, int K, bool LR>
+__global__ __launch_bounds__(NT) void k_als_resid(int64_t n, const int32_t* __restrict__ nbr,
+                                                  double lam, const double* __restrict__ coef,
+                                                  const T* __restrict__ dvec,
+                                                  const T* __restrict__ Xm, int64_t ldx, int ninj,
+                                                  const double* __restrict__ gw,
+                                                  const double* __restrict__ s,
+                                                  const T* __restrict__ b,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ t,
+                                                  double* __restrict__ r) {
+  __shared__ double gs[LR ? PCG_MAX_NINJ : 1];
+  if (LR) {
+    for (int al = threadIdx.x; al < ninj; al += NT) gs[al] = gw[al] * s[al];
+    __syncthreads();
+  }
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], ti = t[i];
+  double q = lam * (lap<double, K>(t, nbr, n, i) + coef[0] * ti + coef[1] * xi);
+  if (dvec) q += (double)dvec[i] * xi;
+  if (LR) {
+    double acc = 0.0;
+    for (int al = 0; al < ninj; ++al) acc += (double)Xm[(int64_t)al * ldx + i] * gs[al];
+    q += acc;
+  }
+  r[i] = (double)b[i] - q;
+}
+
+template <typename T>
+cr_status als_residual(const Geom& g, double lam, const double* coef, const T* dvec, const T* Xm,
+                       int64_t ldx, int ninj, const double* gw, const double* s, const T* b,
+                       const double* x, double* t, double* r, hipStream_t st) {
+  if (g.n == 0) return CR_OK;
+  CR_TRY(stencil<double>(g, 1, x, g.n, t, g.n, st));
+  const dim3 grid((unsigned)((g.n + NT - 1) / NT));
+  switch (g.K) {
+#define CASE(KK)                                                                                \
+  case KK:                                                                                      \
+    if (Xm)                                                                                     \
+      hipLaunchKernelGGL((k_als_resid<T, KK, true>), grid, dim3(NT), 0, st, g.n, g.nbr, lam,   \
+                         coef, dvec, Xm, ldx, ninj, gw, s, b, x, t, r);                        \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_als_resid<T, KK, false>), grid, dim3(NT), 0, st, g.n, g.nbr, lam,  \
+                         coef, dvec, Xm, ldx, ninj, gw, s, b, x, t, r);                        \
+    break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default:
+      set_error("unsupported stencil width");
+      return CR_EINVAL;
+  }
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_accumulate(int64_t n, const T* __restrict__ e,
+                                                   double* __restrict__ x, int init) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  x[i] = init ? (double)e[i] : x[i] + (double)e[i];
+}
+
+template <typename T>
+cr_status accumulate(int64_t n, const T* e, double* x, bool init, hipStream_t st) {
+  if (n == 0) return CR_OK;
+  hipLaunchKernelGGL((k_accumulate<T>), dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, n, e,
+                     x, init ? 1 : 0);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_normalize_out(int64_t n, const double* __restrict__ x,
+                                                      const double* __restrict__ nrm2,
+                                                      T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const double s = nrm2[0] > 0.0 ? 1.0 / sqrt(nrm2[0]) : 0.0;
+  out[i] = (T)(x[i] * s);
+}
+
+template <typename T>
+cr_status normalize_out(int64_t n, const double* x, const double* nrm2, T* out, hipStream_t st) {
+  if (n == 0) return CR_OK;
+  hipLaunchKernelGGL((k_normalize_out<T>), dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, st, n,
+                     x, nrm2, out);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+#define INST(T)                                                                              \
+  template cr_status als_residual<T>(const Geom&, double, const double*, const T*, const T*, \
+                                     int64_t, int, const double*, const double*, const T*,  \
+                                     const double*, double*, double*, hipStream_t);          \
+  template cr_status accumulate<T>(int64_t, const T*, double*, bool, hipStream_t);          \
+  template cr_status normalize_out<T>(int64_t, const double*, const double*, T*, hipStream_t); \
+  template cr_status pcg_solve<T>(const PcgArgs<T>&, int, hipStream_t);                     \
+  template int pcg_max_wg<T>(const PcgArgs<T>&);                                            \
+  template cr_status pcg_diag<T>(const Geom&, double, const double*, const T*, const T*,    \
+                                 int64_t, int, const double*, T*, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace cr

@@ -1,0 +1,29 @@
+"""The C-ABI library loads and exports every entry point that
+include/connreg.h declares (no compute call: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+from paper_1808_05510_amd import connreg
+
+
+def declared_functions(root):
+    src = open(os.path.join(root, "include", "connreg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_all_declared_symbols(root):
+    names = declared_functions(root)
+    assert len(names) >= 12
+    lib = ctypes.CDLL(connreg.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(connreg.EXPORTS) <= set(names)
+
+
+def test_struct_sizes_match_header(root):
+    lib = connreg.load()
+    o = connreg.default_opts()
+    assert o.max_rank == 20 and o.als_delta == 0.1 and o.als_max_sweeps == 10
+    assert lib.cr_version().startswith(b"libconnreg")
