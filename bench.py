@@ -1,0 +1,215 @@
+"""Benchmark: time to relative residual 1e-4 of the greedy ALS + Galerkin
+solver (plain FP64, Jacobi-PCG) on the 3D-grid workload, plus the mixed
+precision solve, the HBM bandwidth of the factored operator application on
+the cortex-shell workload, and the FP64 CPU oracle on a bounded sample.
+
+One JSON line on stdout.  Usage:
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+from paper_1808_05510_amd import connreg, synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "secs to rel. residual 1e-4 & op-apply HBM GB/s: plain FP64 vs mixed+learned-PC"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def op_apply_bytes(n_y, n_x, n_inj, r, s):
+    """Algorithmic bytes of one factored operator application: read U, V, X,
+    the Omega bits and the neighbour tables, write L_y U, L_y^2 U, L_x V,
+    L_x^2 V and Omega o (U Z H)."""
+    return (s * ((n_y + n_x) * r + n_x * n_inj + 2 * (n_y + n_x) * r + n_y * n_inj)
+            + n_y * n_inj / 8 + 24 * (n_y + n_x))
+
+
+def time_solves(prob, steps, warmup, opts):
+    res = None
+    for _ in range(warmup):
+        res = prob.greedy_solve(**opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    times = []
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        res = prob.greedy_solve(**opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return total, times, res
+
+
+def bench_op_apply(d, r, reps, warm, fp32):
+    """Median time of cr_op_apply with a 512 MiB cache flush before each call,
+    timed with events on the library's stream (torch's current stream)."""
+    prob = connreg.Problem(d, "mixed" if fp32 else "fp64", "cuda:0")
+    dt = torch.float32 if fp32 else torch.float64
+    g = torch.Generator(device="cuda:0").manual_seed(1)
+    U = torch.randn((r, prob.n_y), device="cuda:0", dtype=dt, generator=g).T
+    V = torch.randn((r, prob.n_x), device="cuda:0", dtype=dt, generator=g).T
+    Z = torch.randn((r, r), device="cuda:0", dtype=dt, generator=g).T
+    flush = torch.empty(512 * 1024 * 1024 // 4, device="cuda:0", dtype=torch.float32)
+    ts = []
+    for k in range(warm + reps):
+        flush.fill_(float(k))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        prob.op_apply(U, Z, V, fp32=fp32)
+        e1.record()
+        e1.synchronize()
+        if k >= warm:
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+    s = 4 if fp32 else 8
+    nbytes = op_apply_bytes(prob.n_y, prob.n_x, prob.n_inj, r, s)
+    med = float(np.median(ts))
+    prob.close()
+    return dict(r=r, dtype="f32" if fp32 else "f64", seconds=med,
+                iqr=[float(np.percentile(ts, 25)), float(np.percentile(ts, 75))],
+                bytes=nbytes, GBps=nbytes / med / 1e9, frac=nbytes / med / 1e9 / HBM_PEAK_GBS)
+
+
+def cpu_baseline(d, lam, ranks_needed, sample_ranks):
+    """FP64 oracle (NumPy/SciPy, Jacobi-CG inner solves) on the first
+    ``sample_ranks`` greedy steps of the same workload; seconds per rank times
+    the ranks the GPU needed."""
+    from oracle import greedy as ogreedy
+    from oracle import operator as oop
+    P = oop.problem_from_arrays(d, lam=lam)
+    t0 = time.perf_counter()
+    res = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(
+        max_rank=sample_ranks, u_method="cg", v_method="cg", inner_rtol=1e-8, galerkin="dense",
+        tau_res=1e-4))
+    dt = time.perf_counter() - t0
+    per_rank = dt / max(1, len(res.history))
+    return dict(value=per_rank * ranks_needed, unit="s", cores=os.cpu_count(), kind="oracle",
+                sample=f"first {len(res.history)} greedy ranks of the same workload on the host "
+                       f"({dt:.1f} s, {per_rank:.2f} s/rank), scaled by the {ranks_needed} ranks "
+                       f"the GPU solve needed (extrapolated; later ranks cost more on the CPU)",
+                seconds_per_rank=per_rank)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--lam", type=float, default=1e3)
+    ap.add_argument("--max-rank", type=int, default=60)
+    ap.add_argument("--tau", type=float, default=1e-4)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-op", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--op-reps", type=int, default=30)
+    ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--op-only", action="store_true", help="only the op_apply bandwidth part")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the solver is a "
+              "single-device library", file=sys.stderr)
+        sys.exit(2)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    connreg.load()
+
+    if a.op_only:
+        d3 = synth.config3(seed=0)
+        for fp32 in (False, True):
+            o = bench_op_apply(d3, 100, a.op_reps, 5, fp32)
+            log(f"[bench] op_apply {o['dtype']} r=100: {o['seconds']*1e6:.1f} us, {o['GBps']:.0f} GB/s")
+        return
+    d2 = synth.config2(lam=a.lam, seed=0)
+    opts = dict(max_rank=a.max_rank, tau_res=a.tau, seed=0, verbose=1 if a.verbose else 0)
+    log("[bench] FP64 solves on 40^3 / 30^3, n_inj 64")
+    p64 = connreg.Problem(d2, "fp64", "cuda:0")
+    total, times, res = time_solves(p64, a.steps, a.warmup, opts)
+    hist = res["history"]
+    ranks = res["rank"]
+    reached = res["stats"]["relres"] <= a.tau
+    log(f"[bench] fp64: {np.mean(times):.3f} s/solve, rank {ranks}, relres {res['stats']['relres']:.3e}")
+    p64.close()
+
+    mixed = None
+    if not a.no_mixed:
+        log("[bench] mixed-precision solves")
+        pm = connreg.Problem(d2, "mixed", "cuda:0")
+        mt, mtimes, mres = time_solves(pm, a.steps, a.warmup, opts)
+        mixed = dict(seconds=float(np.mean(mtimes)), rank=mres["rank"],
+                     relres=mres["stats"]["relres"], pcg_iters=mres["stats"]["pcg_iters"],
+                     galerkin_iters=mres["stats"]["galerkin_iters"])
+        log(f"[bench] mixed: {mixed['seconds']:.3f} s/solve, rank {mixed['rank']}")
+        pm.close()
+
+    op = None
+    roof = None
+    if not a.no_op:
+        log("[bench] op_apply bandwidth on the cortex-shell workload (n_y ~ 262k, n_x ~ 131k)")
+        d3 = synth.config3(seed=0)
+        op = {}
+        for fp32 in (False, True):
+            for r in (20, 60, 100):
+                o = bench_op_apply(d3, r, a.op_reps, 5, fp32)
+                op[f"{o['dtype']}_r{r}"] = o
+                log(f"[bench] op_apply {o['dtype']} r={r}: {o['seconds']*1e6:.1f} us, "
+                    f"{o['GBps']:.0f} GB/s ({100*o['frac']:.1f}% of HBM peak)")
+        o = op["f64_r100"]
+        roof = dict(bound="hbm", achieved=o["GBps"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=o["frac"], traffic=None, kernel="cr_op_apply (FP64, r=100, shells)")
+        del d3
+
+    cpu = None
+    if not a.no_cpu:
+        log("[bench] CPU oracle sample")
+        cpu = cpu_baseline(d2, a.lam, ranks, 2)
+
+    secs = float(np.mean(times))
+    out = {
+        "metric": METRIC,
+        "value": secs,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": secs * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D grids: 40^3 target (n_y 64,000), 30^3 source (n_x 27,000), "
+                               "n_inj 64, lambda 1e3, rank cap 60, plain FP64, Jacobi-PCG",
+                   "tau_res": a.tau, "seed": 0},
+        "reached_tau": bool(reached),
+        "value_note": ("seconds to relres <= tau" if reached else
+                       "relres tau not reached within the rank cap: seconds to the rank cap "
+                       "(relres at the cap in 'relres', full curve in 'relres_curve')"),
+        "rank": ranks,
+        "relres": res["stats"]["relres"],
+        "pcg_iters": res["stats"]["pcg_iters"],
+        "galerkin_iters": res["stats"]["galerkin_iters"],
+        "relres_curve": [[h["rank"], h["relres"], h["seconds"]] for h in hist],
+        "mixed": mixed,
+        "op_apply": op,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

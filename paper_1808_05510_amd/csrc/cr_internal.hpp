@@ -128,6 +128,12 @@ cr_status convert2d(int64_t rows, int64_t cols, const Ts* src, int64_t lds, Td* 
 // Jacobi preconditioned CG from x0 = 0 in one cooperative launch; on exit
 // xout = x / ||x|| and scal[0] = ||x||, scal[1] = final ||r||/||b||,
 // scal[2] = iterations, scal[3] = status (0 ok, 1 not converged, 2 breakdown).
+// grid barrier selection for the persistent kernels (see k_cg.hip)
+struct BarrierArg {
+  unsigned* bar = nullptr;  // 192 device words, zeroed before each launch
+  int mode = 1;             // 0: cooperative-groups grid sync, 1: atomic barrier
+};
+
 template <typename T>
 struct PcgArgs {
   Geom g;
@@ -148,6 +154,7 @@ struct PcgArgs {
   double rtol;
   int maxit;
   int vpt;              // voxels per thread
+  BarrierArg bar;
 };
 template <typename T>
 cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st);
@@ -189,6 +196,7 @@ struct GalerkinArgs {
   double* scal;       // out: [0] iters, [1] relres, [2] status, [3] energy
   double rtol;
   int maxit;
+  BarrierArg bar;
 };
 cr_status galerkin_cg(const GalerkinArgs& a, int nwg, hipStream_t st);
 int galerkin_max_wg(int r);

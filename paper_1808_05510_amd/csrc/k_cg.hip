@@ -43,6 +43,53 @@ __device__ __forceinline__ double grid_total(const double* part, int slot, int n
   return block_sum(s, red);
 }
 
+// ------------------------------------------------------------ grid barrier
+// Two implementations, chosen per launch: the cooperative-groups grid sync,
+// or a barrier on device words (bar[0] generation, bar[64] timeout flag,
+// bar[128] arrival counter: separate 256-byte lines).  Thread 0 of each
+// workgroup arrives with a release add (its workgroup's stores were ordered
+// before it by __syncthreads); the last arrival takes an acquire fence,
+// resets the counter and publishes the next generation with a release store;
+// the others poll the generation with relaxed loads and take one acquire
+// fence when it changes.  Polling with acquire loads instead would
+// invalidate the caches on every poll, which made the barrier several times
+// slower.  The poll is bounded: after 2^22 sleeps (a fraction of a second,
+// far above any legitimate wait between phases) it sets the timeout flag;
+// once set, every later barrier is skipped, so a faulty launch ends quickly
+// instead of hanging the device, and the host reports the flag as an error.
+constexpr int BAR_GEN = 0, BAR_TIMEOUT = 64, BAR_COUNT = 128, BAR_WORDS = 192;
+
+__device__ __forceinline__ void grid_barrier(const BarrierArg& b, cgrp::grid_group& grid) {
+  if (b.mode == 0) {
+    grid.sync();
+    return;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 &&
+      __hip_atomic_load(b.bar + BAR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+    const unsigned nwg = gridDim.x;
+    const unsigned gen = __hip_atomic_load(b.bar + BAR_GEN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned prev =
+        __hip_atomic_fetch_add(b.bar + BAR_COUNT, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == nwg - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(b.bar + BAR_COUNT, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(b.bar + BAR_GEN, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(b.bar + BAR_GEN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1u << 22)) {
+          __hip_atomic_store(b.bar + BAR_TIMEOUT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+  }
+  __syncthreads();
+}
+
 constexpr int PCG_MAX_VPT = 8;
 constexpr int PCG_MAX_NINJ = 1024;
 // Partial-sum slots.  Every slot has one writer phase per use and is never
@@ -79,38 +126,62 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
   }
 }
 
-template <typename T, int K, bool LR>
+// Register-resident Jacobi-PCG.  Workgroup b owns voxels b*NT*VPT + tid + NT*m
+// (m < VPT); each thread keeps, for its voxels, the neighbour indices and the
+// CG vectors x, r, z, p, t = L p, q = A p in registers for the whole solve.
+// Only z and t are also written to global memory, because the stencil needs
+// their values at neighbouring voxels owned by other workgroups.  Per
+// iteration: phase B (q = A p, needs t at neighbours), phase C (x, r, z
+// updates), phase D (p = z + beta p, t = L z + beta t, needs z at
+// neighbours), each ended by a grid barrier.
+template <typename T, int K, bool LR, int VPT>
 __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
   cgrp::grid_group grid = cgrp::this_grid();
   __shared__ double red[NT / WAVE];
-  __shared__ double zs[NT * PCG_MAX_VPT];
+  __shared__ double zs[NT * VPT];
   __shared__ double slr[LR ? PCG_MAX_NINJ : 1];
   const int64_t n = a.g.n;
-  const int32_t* __restrict__ nbr = a.g.nbr;
   const int nwg = gridDim.x;
-  const int vpt = a.vpt;
-  const int64_t lo = (int64_t)blockIdx.x * NT * vpt;
+  const int64_t lo = (int64_t)blockIdx.x * NT * VPT;
   double* part = a.part;
   double* lrpart = a.part + PCG_SLOTS * nwg;
   const double lam = a.lam;
   const double c1 = a.coef[0], c0 = a.coef[1];
+  T* __restrict__ zg = a.z;
+  T* __restrict__ tg = a.t;
+  const T* __restrict__ Xm = a.Xm;
+  const int64_t ldx = a.ldx;
+  const int ninj = a.ninj;
 
-  // ---- setup: x = 0, r = b, z = M^-1 r
+  int32_t nb[VPT][K];
+  double x[VPT], r[VPT], z[VPT], p[VPT], t[VPT], mi[VPT], dd[VPT];
+  bool ok[VPT];
   double rz = 0.0, bb = 0.0;
-  for (int m = 0; m < vpt; ++m) {
-    const int loc = threadIdx.x + NT * m;
-    const int64_t i = lo + loc;
-    double zi = 0.0;
-    if (i < n) {
-      const double bi = (double)a.b[i];
-      zi = (double)a.minv[i] * bi;
-      a.x[i] = (T)0;
-      a.r[i] = (T)bi;
-      a.z[i] = (T)zi;
-      rz += bi * zi;
-      bb += bi * bi;
+#pragma unroll
+  for (int m = 0; m < VPT; ++m) {
+    const int64_t i = lo + threadIdx.x + NT * m;
+    ok[m] = i < n;
+    double bi = 0.0;
+    mi[m] = 0.0;
+    dd[m] = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) nb[m][k] = 0;
+    if (ok[m]) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) nb[m][k] = a.g.nbr[(int64_t)k * n + i];
+      bi = (double)a.b[i];
+      mi[m] = (double)a.minv[i];
+      if (a.dvec) dd[m] = (double)a.dvec[i];
     }
-    zs[loc] = (double)(T)zi;
+    x[m] = 0.0;
+    r[m] = (double)(T)bi;
+    z[m] = (double)(T)(mi[m] * r[m]);
+    p[m] = 0.0;
+    t[m] = 0.0;
+    if (ok[m]) zg[i] = (T)z[m];
+    zs[threadIdx.x + NT * m] = z[m];
+    rz += r[m] * z[m];
+    bb += r[m] * r[m];
   }
   __syncthreads();
   if (LR) lr_partial(a, zs, lo, n, nwg, lrpart);
@@ -120,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
     part[1 * nwg + blockIdx.x] = rz;
     part[3 * nwg + blockIdx.x] = bb;
   }
-  grid.sync();
+  grid_barrier(a.bar, grid);
   double rz_cur = grid_total(part, 1, nwg, red);
   const double bnorm2 = grid_total(part, 3, nwg, red);
   int status = 0, it = 0;
@@ -128,52 +199,58 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
   const double tol2 = a.rtol * a.rtol * bnorm2;
   if (!(bnorm2 > 0.0)) status = 2;  // zero or non-finite right-hand side
 
-  double beta = 0.0;
   if (status == 0) {
     // ---- p = z, t = L z, s = X^T z
-    for (int m = 0; m < vpt; ++m) {
-      const int64_t i = lo + threadIdx.x + NT * m;
-      if (i < n) {
-        a.p[i] = a.z[i];
-        a.t[i] = (T)lap<T, K>(a.z, nbr, n, i);
+#pragma unroll
+    for (int m = 0; m < VPT; ++m) {
+      if (ok[m]) {
+        double s = (double)K * z[m];
+#pragma unroll
+        for (int k = 0; k < K; ++k) s -= (double)zg[nb[m][k]];
+        p[m] = z[m];
+        t[m] = (double)(T)s;
+        tg[lo + threadIdx.x + NT * m] = (T)t[m];
       }
     }
     if (LR) {
-      for (int al = blockIdx.x; al < a.ninj; al += nwg) {
+      for (int al = blockIdx.x; al < ninj; al += nwg) {
         double s = 0.0;
         for (int b = threadIdx.x; b < nwg; b += NT) s += lrpart[(int64_t)al * nwg + b];
         s = block_sum(s, red);
         if (threadIdx.x == 0) a.sbuf[al] = s;
       }
     }
-    grid.sync();
+    grid_barrier(a.bar, grid);
 
     for (it = 0; it < a.maxit; ++it) {
       // ---- phase B: q = A p, partial p.q
       if (LR) {
-        for (int al = threadIdx.x; al < a.ninj; al += NT) slr[al] = a.gw[al] * a.sbuf[al];
+        for (int al = threadIdx.x; al < ninj; al += NT) slr[al] = a.gw[al] * a.sbuf[al];
         __syncthreads();
       }
+      double q[VPT];
       double pq = 0.0;
-      for (int m = 0; m < vpt; ++m) {
-        const int64_t i = lo + threadIdx.x + NT * m;
-        if (i < n) {
-          const double pi = (double)a.p[i];
-          const double ti = (double)a.t[i];
-          double qi = lam * (lap<T, K>(a.t, nbr, n, i) + c1 * ti + c0 * pi);
-          if (a.dvec) qi += (double)a.dvec[i] * pi;
+#pragma unroll
+      for (int m = 0; m < VPT; ++m) {
+        q[m] = 0.0;
+        if (ok[m]) {
+          const int64_t i = lo + threadIdx.x + NT * m;
+          double lt = (double)K * t[m];
+#pragma unroll
+          for (int k = 0; k < K; ++k) lt -= (double)tg[nb[m][k]];
+          double qi = lam * (lt + c1 * t[m] + c0 * p[m]) + dd[m] * p[m];
           if (LR) {
             double s = 0.0;
-            for (int al = 0; al < a.ninj; ++al) s += (double)a.Xm[(int64_t)al * a.ldx + i] * slr[al];
+            for (int al = 0; al < ninj; ++al) s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
             qi += s;
           }
-          a.q[i] = (T)qi;
-          pq += pi * (double)(T)qi;
+          q[m] = (double)(T)qi;
+          pq += p[m] * q[m];
         }
       }
       pq = block_sum(pq, red);
       if (threadIdx.x == 0) part[0 * nwg + blockIdx.x] = pq;
-      grid.sync();
+      grid_barrier(a.bar, grid);
 
       // ---- phase C: x += alpha p, r -= alpha q, z = M^-1 r
       const double pq_tot = grid_total(part, 0, nwg, red);
@@ -183,21 +260,17 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
       }
       const double alpha = rz_cur / pq_tot;
       double rzn = 0.0, rrn = 0.0;
-      for (int m = 0; m < vpt; ++m) {
-        const int loc = threadIdx.x + NT * m;
-        const int64_t i = lo + loc;
-        double zi = 0.0;
-        if (i < n) {
-          const double pi = (double)a.p[i];
-          a.x[i] = (T)((double)a.x[i] + alpha * pi);
-          const double ri = (double)(T)((double)a.r[i] - alpha * (double)a.q[i]);
-          a.r[i] = (T)ri;
-          zi = (double)(T)((double)a.minv[i] * ri);
-          a.z[i] = (T)zi;
-          rzn += ri * zi;
-          rrn += ri * ri;
+#pragma unroll
+      for (int m = 0; m < VPT; ++m) {
+        if (ok[m]) {
+          x[m] = (double)(T)(x[m] + alpha * p[m]);
+          r[m] = (double)(T)(r[m] - alpha * q[m]);
+          z[m] = (double)(T)(mi[m] * r[m]);
+          zg[lo + threadIdx.x + NT * m] = (T)z[m];
+          rzn += r[m] * z[m];
+          rrn += r[m] * r[m];
         }
-        zs[loc] = zi;
+        zs[threadIdx.x + NT * m] = z[m];
       }
       __syncthreads();
       if (LR) lr_partial(a, zs, lo, n, nwg, lrpart);
@@ -207,7 +280,7 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
         part[1 * nwg + blockIdx.x] = rzn;
         part[2 * nwg + blockIdx.x] = rrn;
       }
-      grid.sync();
+      grid_barrier(a.bar, grid);
 
       // ---- phase D: beta, convergence, p = z + beta p, t = L z + beta t
       const double rz_new = grid_total(part, 1, nwg, red);
@@ -216,46 +289,49 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
         ++it;
         break;
       }
-      beta = rz_new / rz_cur;
+      const double beta = rz_new / rz_cur;
       rz_cur = rz_new;
-      for (int m = 0; m < vpt; ++m) {
-        const int64_t i = lo + threadIdx.x + NT * m;
-        if (i < n) {
-          a.p[i] = (T)((double)a.z[i] + beta * (double)a.p[i]);
-          a.t[i] = (T)(lap<T, K>(a.z, nbr, n, i) + beta * (double)a.t[i]);
+#pragma unroll
+      for (int m = 0; m < VPT; ++m) {
+        if (ok[m]) {
+          double lz = (double)K * z[m];
+#pragma unroll
+          for (int k = 0; k < K; ++k) lz -= (double)zg[nb[m][k]];
+          p[m] = (double)(T)(z[m] + beta * p[m]);
+          t[m] = (double)(T)(lz + beta * t[m]);
+          tg[lo + threadIdx.x + NT * m] = (T)t[m];
         }
       }
       if (LR) {
-        for (int al = blockIdx.x; al < a.ninj; al += nwg) {
+        for (int al = blockIdx.x; al < ninj; al += nwg) {
           double s = 0.0;
           for (int b = threadIdx.x; b < nwg; b += NT) s += lrpart[(int64_t)al * nwg + b];
           s = block_sum(s, red);
           if (threadIdx.x == 0) a.sbuf[al] = s + beta * a.sbuf[al];
         }
       }
-      grid.sync();
+      grid_barrier(a.bar, grid);
     }
     if (status == 0 && !(rr <= tol2)) status = 1;
   }
 
-  // ---- final: xout = x / ||x||
+  // ---- final: x to global, xout = x / ||x||
   double xx = 0.0;
-  for (int m = 0; m < vpt; ++m) {
-    const int64_t i = lo + threadIdx.x + NT * m;
-    if (i < n) {
-      const double xi = (double)a.x[i];
-      xx += xi * xi;
-    }
-  }
+#pragma unroll
+  for (int m = 0; m < VPT; ++m) xx += x[m] * x[m];
   xx = block_sum(xx, red);
   if (threadIdx.x == 0) part[4 * nwg + blockIdx.x] = xx;
-  grid.sync();
+  grid_barrier(a.bar, grid);
   const double xnorm2 = grid_total(part, 4, nwg, red);
   const double xn = sqrt(xnorm2);
   const double inv = xn > 0.0 ? 1.0 / xn : 0.0;
-  for (int m = 0; m < vpt; ++m) {
+#pragma unroll
+  for (int m = 0; m < VPT; ++m) {
     const int64_t i = lo + threadIdx.x + NT * m;
-    if (i < n) a.xout[i] = (T)((double)a.x[i] * inv);
+    if (ok[m]) {
+      a.x[i] = (T)x[m];
+      a.xout[i] = (T)(x[m] * inv);
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.scal[0] = xn;
@@ -266,17 +342,23 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
 }
 
 template <typename T, int K, bool LR>
-static void* pcg_fn() {
-  return (void*)&k_pcg<T, K, LR>;
+static void* pcg_fn_v(int vpt) {
+  switch (vpt) {
+    case 1: return (void*)&k_pcg<T, K, LR, 1>;
+    case 2: return (void*)&k_pcg<T, K, LR, 2>;
+    case 4: return (void*)&k_pcg<T, K, LR, 4>;
+    case 8: return (void*)&k_pcg<T, K, LR, 8>;
+    default: return nullptr;
+  }
 }
 
 template <typename T>
-static void* pcg_select(int K, bool lr) {
+static void* pcg_select(int K, bool lr, int vpt) {
   switch (K) {
 #define CASE(KK) \
   case KK:       \
-    return lr ? pcg_fn<T, KK, true>() : pcg_fn<T, KK, false>();
-    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+    return lr ? pcg_fn_v<T, KK, true>(vpt) : pcg_fn_v<T, KK, false>(vpt);
+    CASE(2) CASE(4) CASE(6) CASE(8)
 #undef CASE
     default:
       return nullptr;
@@ -285,7 +367,7 @@ static void* pcg_select(int K, bool lr) {
 
 template <typename T>
 int pcg_max_wg(const PcgArgs<T>& a) {
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt);
   if (!fn) return 0;
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -309,12 +391,13 @@ cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
     set_error("pcg: grid does not cover the voxels");
     return CR_EINVAL;
   }
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt);
   if (!fn) {
-    set_error("pcg: unsupported stencil width");
+    set_error("pcg: unsupported stencil width or voxels per thread");
     return CR_EINVAL;
   }
   PcgArgs<T> arg = a;
+  if (arg.bar.mode == 1) CR_HIP(hipMemsetAsync(arg.bar.bar, 0, BAR_WORDS * sizeof(unsigned), st));
   void* params[] = {&arg};
   CR_HIP(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(NT), params, 0, st));
   return CR_OK;
@@ -429,7 +512,7 @@ __global__ __launch_bounds__(NT) void k_galerkin(GalerkinArgs a) {
       for (int al = 0; al < a.ninj; ++al) s += Sk(a, i, al) * Hk(a, c, al);
       a.Bm[(int64_t)c * ld + i] = s;
     }
-  grid.sync();
+  grid_barrier(a.bar, grid);
   gal_phase2(a, a.Z);
   // R = B - Q, P = R (own columns); partial ||R||^2, ||B||^2
   double rr = 0.0, bb = 0.0;
@@ -449,18 +532,18 @@ __global__ __launch_bounds__(NT) void k_galerkin(GalerkinArgs a) {
     part[1 * nwg + blockIdx.x] = rr;
     part[3 * nwg + blockIdx.x] = bb;
   }
-  grid.sync();
+  grid_barrier(a.bar, grid);
   rr = grid_total(part, 1, nwg, red);
   bb = grid_total(part, 3, nwg, red);
   const double tol2 = a.rtol * a.rtol * bb;
   int it = 0, status = 0;
   for (; it < a.maxit && rr > tol2; ++it) {
     gal_phase1(a, a.P, tsh);
-    grid.sync();
+    grid_barrier(a.bar, grid);
     double pq = gal_phase2(a, a.P);
     pq = block_sum(pq, red);
     if (threadIdx.x == 0) part[0 * nwg + blockIdx.x] = pq;
-    grid.sync();
+    grid_barrier(a.bar, grid);
     const double pq_tot = grid_total(part, 0, nwg, red);
     if (!(pq_tot > 0.0)) {
       status = 2;
@@ -478,7 +561,7 @@ __global__ __launch_bounds__(NT) void k_galerkin(GalerkinArgs a) {
       }
     rrn = block_sum(rrn, red);
     if (threadIdx.x == 0) part[2 * nwg + blockIdx.x] = rrn;
-    grid.sync();
+    grid_barrier(a.bar, grid);
     const double rr_new = grid_total(part, 2, nwg, red);
     const double beta = rr_new / rr;
     rr = rr_new;
@@ -491,7 +574,7 @@ __global__ __launch_bounds__(NT) void k_galerkin(GalerkinArgs a) {
         const int64_t e = (int64_t)c * ld + i;
         a.P[e] = a.R[e] + beta * a.P[e];
       }
-    grid.sync();
+    grid_barrier(a.bar, grid);
   }
   if (status == 0 && rr > tol2) status = 1;
   // energy pieces: <Z, B>, <Z, R>
@@ -510,7 +593,7 @@ __global__ __launch_bounds__(NT) void k_galerkin(GalerkinArgs a) {
     part[4 * nwg + blockIdx.x] = zb;
     part[5 * nwg + blockIdx.x] = zr;
   }
-  grid.sync();
+  grid_barrier(a.bar, grid);
   zb = grid_total(part, 4, nwg, red);
   zr = grid_total(part, 5, nwg, red);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -535,6 +618,7 @@ int galerkin_max_wg(int r) {
 cr_status galerkin_cg(const GalerkinArgs& a, int nwg, hipStream_t st) {
   if (a.r <= 0) return CR_OK;
   GalerkinArgs arg = a;
+  if (arg.bar.mode == 1) CR_HIP(hipMemsetAsync(arg.bar.bar, 0, BAR_WORDS * sizeof(unsigned), st));
   void* params[] = {&arg};
   CR_HIP(hipLaunchCooperativeKernel((void*)k_galerkin, dim3(nwg), dim3(NT), params,
                                     sizeof(double) * a.r, st));
