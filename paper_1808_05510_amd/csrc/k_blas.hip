@@ -16,21 +16,51 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ============================================================== stencil
 // (L w)_i = K w_i - sum_k w[nbr_k(i)] : with self-padded absent neighbours
 // this equals deg_i w_i - sum_{j adjacent} w_j, the graph Laplacian row.
+// Workgroups are dispatched round-robin over the 8 XCDs (physical block b
+// runs on XCD b % 8); the logical voxel block is remapped so that each XCD
+// sweeps one contiguous eighth of the voxels and finds neighbouring planes
+// in its own L2.  Each thread handles SCOL columns with independent loads.
+constexpr int NXCD = 8;
+constexpr int SCOL = 8;
+
+__device__ __forceinline__ int64_t xcd_block(unsigned b, unsigned nb_log) {
+  const unsigned per = (nb_log + NXCD - 1) / NXCD;
+  return (int64_t)(b % NXCD) * per + b / NXCD;
+}
+
 template <typename T, int K>
 __global__ __launch_bounds__(NT) void k_stencil(int64_t n, const int32_t* __restrict__ nbr,
                                                 int ncols, const T* __restrict__ w, int64_t ldw,
-                                                T* __restrict__ out, int64_t ldo) {
-  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+                                                T* __restrict__ out, int64_t ldo,
+                                                unsigned nb_log) {
+  const int64_t lb = xcd_block(blockIdx.x, nb_log);
+  if (lb >= nb_log) return;
+  const int64_t i = lb * NT + threadIdx.x;
   if (i >= n) return;
   int32_t nb[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) nb[k] = nbr[(int64_t)k * n + i];
-  for (int c = blockIdx.y; c < ncols; c += gridDim.y) {
-    const T* wc = w + (int64_t)c * ldw;
-    T s = (T)K * wc[i];
+  const int c0 = blockIdx.y * SCOL;
+  if (c0 + SCOL <= ncols) {
+    T s[SCOL];
 #pragma unroll
-    for (int k = 0; k < K; ++k) s -= wc[nb[k]];
-    out[(int64_t)c * ldo + i] = s;
+    for (int c = 0; c < SCOL; ++c) {
+      const T* wc = w + (int64_t)(c0 + c) * ldw;
+      T v = (T)K * wc[i];
+#pragma unroll
+      for (int k = 0; k < K; ++k) v -= wc[nb[k]];
+      s[c] = v;
+    }
+#pragma unroll
+    for (int c = 0; c < SCOL; ++c) out[(int64_t)(c0 + c) * ldo + i] = s[c];
+  } else {
+    for (int c = c0; c < ncols; ++c) {
+      const T* wc = w + (int64_t)c * ldw;
+      T v = (T)K * wc[i];
+#pragma unroll
+      for (int k = 0; k < K; ++k) v -= wc[nb[k]];
+      out[(int64_t)c * ldo + i] = v;
+    }
   }
 }
 
@@ -38,12 +68,14 @@ template <typename T>
 cr_status stencil(const Geom& g, int ncols, const T* w, int64_t ldw, T* out, int64_t ldo,
                   hipStream_t st) {
   if (ncols <= 0 || g.n == 0) return CR_OK;
-  dim3 grid((unsigned)((g.n + NT - 1) / NT), (unsigned)std::min(ncols, 16));
+  const unsigned nb_log = (unsigned)((g.n + NT - 1) / NT);
+  const unsigned nb_phys = (nb_log + NXCD - 1) / NXCD * NXCD;
+  dim3 grid(nb_phys, (unsigned)((ncols + SCOL - 1) / SCOL));
   switch (g.K) {
 #define CASE(KK)                                                                         \
   case KK:                                                                               \
     hipLaunchKernelGGL((k_stencil<T, KK>), grid, dim3(NT), 0, st, g.n, g.nbr, ncols, w, \
-                       ldw, out, ldo);                                                   \
+                       ldw, out, ldo, nb_log);                                           \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -192,6 +224,15 @@ cr_status gemv_n(int64_t n, const Blocks<T>& A, const double* coef, double beta,
 // threads with 4x4 register tiles, K staged through LDS in chunks of 32 rows.
 constexpr int TM = 64, KC = 32;
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// FP64 MFMA 16x16x4 on gfx950 (layouts checked on the device): lane l
+// supplies A(row l%16, k l/16) and B(k l/16, col l%16); result element i of
+// lane l is D(row l/16 + 4 i, col l%16).
+__device__ __forceinline__ dbl4 mfma64(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 template <typename T, bool MASK>
 __global__ __launch_bounds__(NT) void k_gemm_tn(int64_t n, Blocks<T> A, Blocks<T> B,
                                                 const uint32_t* __restrict__ bits,
@@ -200,15 +241,17 @@ __global__ __launch_bounds__(NT) void k_gemm_tn(int64_t n, Blocks<T> A, Blocks<T
   __shared__ double As[KC][TM + 1];
   __shared__ double Bs[KC][TM + 1];
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int lane = tid & 63, wv = tid >> 6;
   const int tp = blockIdx.x * TM, tq = blockIdx.y * TM;
   const int64_t k0 = (int64_t)blockIdx.z * kchunk;
   const int64_t k1 = std::min<int64_t>(n, k0 + kchunk);
-  double acc[4][4];
+  // wave wv computes the 32 x 32 sub-tile (rows 32*(wv%2), cols 32*(wv/2))
+  const int wp = 32 * (wv & 1), wq = 32 * (wv >> 1);
+  dbl4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
   // loader mapping: element e = tid + 256*m, row = e % KC, col = e / KC
   const int lrow = tid % KC;
   const int lcol = tid / KC;  // 0..7
@@ -220,61 +263,92 @@ __global__ __launch_bounds__(NT) void k_gemm_tn(int64_t n, Blocks<T> A, Blocks<T
     acol[m] = (tp + c < p) ? A.col(tp + c) : nullptr;
     bcol[m] = (!MASK && tq + c < q) ? B.col(tq + c) : nullptr;
   }
-  for (int64_t kb = k0; kb < k1; kb += KC) {
+  const int fr = lane & 15, fk = lane >> 4;
+  // register double buffer: the next chunk's loads are in flight while the
+  // MFMAs consume the current chunk from LDS
+  double ra[8], rb[8];
+  auto load_chunk = [&](int64_t kb) {
     const int64_t row = kb + lrow;
     const bool rin = row < k1;
-    double wv = 0.0;
-    if (MASK && rin) wv = (double)w[row];
+    double wv_ = 0.0;
+    if (MASK && rin) wv_ = (double)w[row];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int c = lcol + 8 * m;
-      As[lrow][c] = (rin && acol[m]) ? (double)acol[m][row] : 0.0;
+      ra[m] = (rin && acol[m]) ? (double)acol[m][row] : 0.0;
       if (MASK) {
         const int al = tq + c;
         double v = 0.0;
         if (rin && al < q) {
           uint32_t word = bits[(int64_t)(al >> 5) * n + row];
-          v = ((word >> (al & 31)) & 1u) ? wv : 0.0;
+          v = ((word >> (al & 31)) & 1u) ? wv_ : 0.0;
         }
-        Bs[lrow][c] = v;
+        rb[m] = v;
       } else {
-        Bs[lrow][c] = (rin && bcol[m]) ? (double)bcol[m][row] : 0.0;
+        rb[m] = (rin && bcol[m]) ? (double)bcol[m][row] : 0.0;
       }
     }
+  };
+  if (k0 < k1) load_chunk(k0);
+  for (int64_t kb = k0; kb < k1; kb += KC) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      As[lrow][lcol + 8 * m] = ra[m];
+      Bs[lrow][lcol + 8 * m] = rb[m];
+    }
     __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < KC; ++kk) {
-      double av[4], bv[4];
+    if (kb + KC < k1) load_chunk(kb + KC);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
+    for (int kk = 0; kk < KC; kk += 4) {
+      double av[2], bv[2];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][ty + 16 * b];
+      for (int a = 0; a < 2; ++a) av[a] = As[kk + fk][wp + 16 * a + fr];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + fk][wq + 16 * b + fr];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();
   }
   double* out = part + (int64_t)blockIdx.z * p * q;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int i = tp + tx + 16 * a, j = tq + ty + 16 * b;
-      if (i < p && j < q) out[(int64_t)j * p + i] = acc[a][b];
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = tp + wp + 16 * a + fk + 4 * e;
+        const int j = tq + wq + 16 * b + fr;
+        if (i < p && j < q) out[(int64_t)j * p + i] = acc[a][b][e];
+      }
 }
 
+// C = sum over the ks split partials; 64 outputs per workgroup, the four
+// waves sum interleaved quarters of the splits, then combine in a fixed order.
 __global__ __launch_bounds__(NT) void k_reduce_split(int p, int q, int ks,
                                                      const double* __restrict__ part,
                                                      double* __restrict__ C, int64_t ldc) {
-  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (e >= (int64_t)p * q) return;
-  double s = 0.0;
-  for (int z = 0; z < ks; ++z) s += part[(int64_t)z * p * q + e];
-  const int64_t i = e % p, j = e / p;
-  C[j * ldc + i] = s;
+  __shared__ double red[NT / WAVE][WAVE];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t pq = (int64_t)p * q;
+  const int64_t e = (int64_t)blockIdx.x * WAVE + lane;
+  double s0 = 0.0, s1 = 0.0;
+  if (e < pq) {
+    int z = wv;
+    for (; z + 4 < ks; z += 8) {
+      s0 += part[(int64_t)z * pq + e];
+      s1 += part[(int64_t)(z + 4) * pq + e];
+    }
+    for (; z < ks; z += 4) s0 += part[(int64_t)z * pq + e];
+  }
+  red[wv][lane] = s0 + s1;
+  __syncthreads();
+  if (wv == 0 && e < pq) {
+    const double s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    C[(e / p) * ldc + e % p] = s;
+  }
 }
 
 template <typename T>
@@ -289,8 +363,9 @@ cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint3
     return CR_OK;
   }
   const int tiles = ((p + TM - 1) / TM) * ((q + TM - 1) / TM);
-  int64_t ks = std::max<int64_t>(1, 1024 / tiles);
-  ks = std::min<int64_t>(ks, std::max<int64_t>(1, (n + 4 * KC - 1) / (4 * KC)));
+  // about 512 workgroups, each at least 16 LDS chunks deep
+  int64_t ks = std::max<int64_t>(1, 512 / tiles);
+  ks = std::min<int64_t>(ks, std::max<int64_t>(1, (n + 16 * KC - 1) / (16 * KC)));
   while (ks > 1 && ks * (int64_t)p * q > part_cap) --ks;
   if (ks * (int64_t)p * q > part_cap) {
     set_error("gemm_tn workspace too small");
@@ -308,58 +383,85 @@ cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint3
                        q, kchunk, part);
   CR_HIP(hipGetLastError());
   const int64_t pq = (int64_t)p * q;
-  hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((pq + NT - 1) / NT)), dim3(NT), 0, st, p,
-                     q, (int)ks, part, C, ldc);
+  hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((pq + WAVE - 1) / WAVE)), dim3(NT), 0, st,
+                     p, q, (int)ks, part, C, ldc);
   CR_HIP(hipGetLastError());
   return CR_OK;
 }
 
 // ============================================================== masked tall GEMM
 // N[i,a] = OY[i,a] - omega_ia * sum_k U[i,k] T[k,a]   (or +omega*UT when OY null)
-// Workgroup: 64 rows x 128 columns; thread (row lane, column group g of 4)
-// accumulates 32 columns.  T staged through LDS in chunks of 32 rows.
-constexpr int MG_ROWS = 64, MG_CPT = 32, MG_KC = 32;
+// computed transposed, N^T = T^T U^T, with FP64 MFMA: in the result layout
+// each group of 16 lanes then holds 16 consecutive voxels of one injection,
+// so the mask, OY reads and N writes are coalesced.  Workgroup: 128 voxels x
+// 64 injections; wave wv owns voxels 32 wv .. 32 wv + 31 (two 16-wide MFMA
+// columns) and all 64 injections (four 16-high MFMA rows).  T^T is staged
+// through LDS in chunks of 32 k; U fragments are read straight from memory
+// (16 consecutive voxels per 16 lanes).  Voxel blocks are remapped per XCD.
+constexpr int MG_ROWS = 128, MG_COLS = 64, MG_KC = 32;
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_masked_tall_gemm(
     int64_t n, int r, int ninj, const T* __restrict__ U, int64_t ldu, const double* __restrict__ Tm,
     int64_t ldt, const uint32_t* __restrict__ bits, const T* __restrict__ OY, int64_t ldoy,
-    T* __restrict__ N, int64_t ldn) {
-  __shared__ double Ts[MG_KC][4 * MG_CPT];
-  const int lane = threadIdx.x & 63;
-  const int grp = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * MG_ROWS + lane;
-  const int a0 = blockIdx.y * (4 * MG_CPT);
-  double acc[MG_CPT];
+    T* __restrict__ N, int64_t ldn, unsigned nb_log) {
+  __shared__ double Ts[MG_KC][MG_COLS + 1];  // Ts[k][a] = T[k0 + k, a0 + a]
+  const int64_t lb = xcd_block(blockIdx.x, nb_log);
+  if (lb >= nb_log) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  const int a0 = blockIdx.y * MG_COLS;
+  const int64_t v0 = lb * MG_ROWS + 32 * wv;  // first voxel of this wave
+  dbl4 acc[4][2];
 #pragma unroll
-  for (int c = 0; c < MG_CPT; ++c) acc[c] = 0.0;
+  for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+    for (int tv = 0; tv < 2; ++tv) acc[ta][tv] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int64_t vrow0 = v0 + fr, vrow1 = v0 + 16 + fr;
+  const bool ok0 = vrow0 < n, ok1 = vrow1 < n;
   for (int k0 = 0; k0 < r; k0 += MG_KC) {
     __syncthreads();
-    for (int e = threadIdx.x; e < MG_KC * 4 * MG_CPT; e += NT) {
-      int kk = e / (4 * MG_CPT), cc = e % (4 * MG_CPT);
-      int k = k0 + kk, a = a0 + cc;
-      Ts[kk][cc] = (k < r && a < ninj) ? Tm[(int64_t)a * ldt + k] : 0.0;
+    for (int e = threadIdx.x; e < MG_KC * MG_COLS; e += NT) {
+      const int kk = e % MG_KC, cc = e / MG_KC;
+      const int k = k0 + kk, al = a0 + cc;
+      Ts[kk][cc] = (k < r && al < ninj) ? Tm[(int64_t)al * ldt + k] : 0.0;
     }
     __syncthreads();
-    const int kn = std::min(MG_KC, r - k0);
-    if (i < n) {
-      for (int kk = 0; kk < kn; ++kk) {
-        const double u = (double)U[(int64_t)(k0 + kk) * ldu + i];
+    double b0[MG_KC / 4], b1[MG_KC / 4];
 #pragma unroll
-        for (int c = 0; c < MG_CPT; ++c) acc[c] += u * Ts[kk][grp * MG_CPT + c];
+    for (int s4 = 0; s4 < MG_KC / 4; ++s4) {
+      const int k = k0 + 4 * s4 + fk;
+      const bool kin = k < r;
+      b0[s4] = (kin && ok0) ? (double)U[(int64_t)k * ldu + vrow0] : 0.0;
+      b1[s4] = (kin && ok1) ? (double)U[(int64_t)k * ldu + vrow1] : 0.0;
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < MG_KC / 4; ++s4) {
+#pragma unroll
+      for (int ta = 0; ta < 4; ++ta) {
+        const double av = Ts[4 * s4 + fk][16 * ta + fr];
+        acc[ta][0] = mfma64(av, b0[s4], acc[ta][0]);
+        acc[ta][1] = mfma64(av, b1[s4], acc[ta][1]);
       }
     }
   }
-  if (i >= n) return;
+  // epilogue: element e of lane l is (injection 16 ta + fk + 4 e, voxel 16 tv + fr)
 #pragma unroll
-  for (int c = 0; c < MG_CPT; ++c) {
-    const int a = a0 + grp * MG_CPT + c;
-    if (a < ninj) {
-      const uint32_t word = bits[(int64_t)(a >> 5) * n + i];
-      const double om = (double)((word >> (a & 31)) & 1u);
-      const double v = om * acc[c];
-      N[(int64_t)a * ldn + i] = OY ? (T)((double)OY[(int64_t)a * ldoy + i] - v) : (T)v;
-    }
+  for (int tv = 0; tv < 2; ++tv) {
+    const int64_t i = v0 + 16 * tv + fr;
+    if (i >= n) continue;
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int al = a0 + 16 * ta + fk + 4 * e;
+        if (al < ninj) {
+          const uint32_t word = bits[(int64_t)(al >> 5) * n + i];
+          const double om = (double)((word >> (al & 31)) & 1u);
+          const double v = om * acc[ta][tv][e];
+          N[(int64_t)al * ldn + i] = OY ? (T)((double)OY[(int64_t)al * ldoy + i] - v) : (T)v;
+        }
+      }
   }
 }
 
@@ -368,9 +470,11 @@ cr_status masked_tall_gemm(int64_t n, int r, int ninj, const T* U, int64_t ldu, 
                            int64_t ldt, const uint32_t* bits, const T* OY, int64_t ldoy, T* N,
                            int64_t ldn, hipStream_t st) {
   if (n == 0 || ninj == 0) return CR_OK;
-  dim3 grid((unsigned)((n + MG_ROWS - 1) / MG_ROWS), (ninj + 4 * MG_CPT - 1) / (4 * MG_CPT));
+  const unsigned nb_log = (unsigned)((n + MG_ROWS - 1) / MG_ROWS);
+  const unsigned nb_phys = (nb_log + NXCD - 1) / NXCD * NXCD;
+  dim3 grid(nb_phys, (ninj + MG_COLS - 1) / MG_COLS);
   hipLaunchKernelGGL((k_masked_tall_gemm<T>), grid, dim3(NT), 0, st, n, r, ninj, U, ldu, Tm, ldt,
-                     bits, OY, ldoy, N, ldn);
+                     bits, OY, ldoy, N, ldn, nb_log);
   CR_HIP(hipGetLastError());
   return CR_OK;
 }
@@ -535,9 +639,18 @@ __global__ __launch_bounds__(NT) void k_small_gemm(int m, int n, int k, const do
   const int i = (int)(e % m), j = (int)(e / m);
   const int64_t sa_i = ta ? lda : 1, sa_t = ta ? 1 : lda;
   const int64_t sb_t = tb ? ldb : 1, sb_j = tb ? 1 : ldb;
-  double s = 0.0;
-  for (int t = 0; t < k; ++t) s += A[i * sa_i + t * sa_t] * B[t * sb_t + j * sb_j];
-  C[(int64_t)j * ldc + i] = alpha * s;
+  const double* a = A + i * sa_i;
+  const double* b = B + j * sb_j;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int t = 0;
+  for (; t + 4 <= k; t += 4) {
+    s0 += a[t * sa_t] * b[t * sb_t];
+    s1 += a[(t + 1) * sa_t] * b[(t + 1) * sb_t];
+    s2 += a[(t + 2) * sa_t] * b[(t + 2) * sb_t];
+    s3 += a[(t + 3) * sa_t] * b[(t + 3) * sb_t];
+  }
+  for (; t < k; ++t) s0 += a[t * sa_t] * b[t * sb_t];
+  C[(int64_t)j * ldc + i] = alpha * ((s0 + s1) + (s2 + s3));
 }
 
 cr_status small_gemm(int m, int n, int k, const double* A, int64_t lda, bool ta, const double* B,
