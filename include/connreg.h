@@ -204,6 +204,71 @@ cr_status cr_greedy_solve(cr_problem* p, const cr_solve_opts* opts, double* U, d
                           double* Z, int64_t* rank_io, cr_solve_stats* stats, cr_rank_cb cb,
                           void* user);
 
+/* ---------------------------------------------------------------------------
+ * ALS u-system access and the learned preconditioner.
+ *
+ * The u half-step of the ALS (eq. ALS_linsys) solves
+ *   A_hat u = R v,  A_hat = lambda (L_y^2 + c1 L_y + c0 I) + diag(d),
+ *   c1 = 2 v^T L_x v,  c0 = v^T L_x^2 v,  d_i = sum_a Omega_ia (X_a^T v)^2.
+ * The paper gives no preconditioner for it (it uses a sparse direct solve);
+ * the library offers Jacobi-PCG and, on full-box target grids, flexible CG
+ * (Notay's FCG with one stored direction) preconditioned by a small 3-D
+ * convolutional network that the library trains on the GPU.  The network
+ * never changes the answer: FCG stops on the same FP64 residual test, and
+ * any step whose preconditioned residual is not a descent direction
+ * (<r, M r> <= 0 or non-finite) falls back to the Jacobi step.
+ * ------------------------------------------------------------------------- */
+
+/* Build the u-system of the rank-1 update at W = U Z V^T for a unit vector v
+ * [dev] n_x: rhs_out [dev] n_y = R v, d_out [dev] n_y, coef_out [host] 2 =
+ * {c1, c0}.  Synchronises.  FP64 handles only (CR_EINVAL otherwise). */
+cr_status cr_u_system(cr_problem* p, int64_t r, const double* U, int64_t ldu, const double* Z,
+                      int64_t ldz, const double* V, int64_t ldv, const double* v, double* rhs_out,
+                      double* d_out, double* coef_out);
+
+typedef struct cr_pc cr_pc;
+
+/* A preconditioner network for an nx x ny x nz box (voxel index
+ * x + nx (y + ny z), the numbering of a full-box target Laplacian), with
+ * `channels` hidden channels (1..8), weights drawn from SplitMix64(seed)
+ * (He-style scaling).  The network lives on the current device and runs on
+ * `hip_stream`. */
+cr_status cr_pc_create(int32_t nx, int32_t ny, int32_t nz, int32_t channels, uint64_t seed,
+                       void* hip_stream, cr_pc** out);
+void cr_pc_destroy(cr_pc* pc);
+/* number of float parameters; get/set copy them as one host array in layer
+ * order (W0, b0, ..., W4, b4; W[co][ci][27], tap k = 9(dz+1) + 3(dy+1) + (dx+1)) */
+int64_t cr_pc_num_params(const cr_pc* pc);
+cr_status cr_pc_get_params(cr_pc* pc, float* host_out);
+cr_status cr_pc_set_params(cr_pc* pc, const float* host_in);
+/* forward on an explicit input in [dev] 4 x N float (channel-major) into
+ * y [dev] N float; and its vector-Jacobian product for the upstream gradient
+ * dy [dev] N float, returned as parameter gradients in grad_host [host]
+ * (same order as get_params).  Both synchronise; for checks and tooling. */
+cr_status cr_pc_forward(cr_pc* pc, const float* in, float* y);
+cr_status cr_pc_vjp(cr_pc* pc, const float* in, const float* dy, float* grad_host);
+/* One Adam step on a batch of u-systems of handle p (whose target graph is
+ * the pc's box): b, x, d [dev] batch x n_y (x = exact solutions),
+ * coef [host] batch x 2, loss = mean over the batch of
+ * ||N(b) - x||^2 / ||x||^2 with N(b) = y ||b|| / lambda.  loss_out [host]. */
+cr_status cr_pc_train_step(cr_pc* pc, cr_problem* p, int32_t batch, const double* b,
+                           const double* x, const double* d, const double* coef, float lr,
+                           double* loss_out);
+
+/* Solve A_hat x = rhs (FP64): pc == NULL -> persistent Jacobi-PCG; otherwise
+ * FCG with the network.  x_out [dev] n_y (not normalised); iters_out,
+ * relres_out, fallbacks_out [host] may be NULL.  Synchronises. */
+cr_status cr_u_solve(cr_problem* p, const double* d, const double* coef, const double* rhs,
+                     double* x_out, double rtol, int32_t maxit, cr_pc* pc, int32_t* iters_out,
+                     double* relres_out, int32_t* fallbacks_out);
+
+/* Use pc (NULL: none) for the u-systems of cr_greedy_solve / cr_als_step on
+ * this handle (full-box targets matching the pc's box; with a mixed handle
+ * the flexible CG runs in FP64 on FP64 copies of the system).  The handle
+ * does not own pc.  Jacobi-PCG takes over any u-solve that the
+ * network-preconditioned FCG does not finish. */
+cr_status cr_problem_set_pc(cr_problem* p, cr_pc* pc);
+
 /* Message of the last hard error on this thread ("" if none). */
 const char* cr_last_error(void);
 

@@ -25,7 +25,10 @@ PREC = {"fp64": 0, "mixed": 1}
 
 EXPORTS = ["cr_problem_create", "cr_problem_destroy", "cr_rhs_norm", "cr_op_apply",
            "cr_op_apply_f32", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
-           "cr_residual_norm", "cr_greedy_solve", "cr_last_error", "cr_version"]
+           "cr_residual_norm", "cr_greedy_solve", "cr_last_error", "cr_version",
+           "cr_u_system", "cr_u_solve", "cr_problem_set_pc", "cr_pc_create", "cr_pc_destroy",
+           "cr_pc_num_params", "cr_pc_get_params", "cr_pc_set_params", "cr_pc_forward",
+           "cr_pc_vjp", "cr_pc_train_step"]
 
 
 class CSR(ctypes.Structure):
@@ -96,12 +99,28 @@ def load(path: str = LIB_PATH):
                                    POINTER(c_double), POINTER(c_double)]
     L.cr_greedy_solve.argtypes = [P, POINTER(SolveOpts), P, P, P, POINTER(c_int64),
                                   POINTER(SolveStats), RANK_CB, P]
+    L.cr_u_system.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, P, P,
+                              POINTER(c_double)]
+    L.cr_u_solve.argtypes = [P, P, POINTER(c_double), P, P, c_double, c_int32, P,
+                             POINTER(c_int32), POINTER(c_double), POINTER(c_int32)]
+    L.cr_problem_set_pc.argtypes = [P, P]
+    L.cr_pc_create.argtypes = [c_int32, c_int32, c_int32, c_int32, c_uint64, P, POINTER(P)]
+    L.cr_pc_destroy.argtypes = [P]
+    L.cr_pc_destroy.restype = None
+    L.cr_pc_num_params.argtypes = [P]
+    L.cr_pc_num_params.restype = c_int64
+    L.cr_pc_get_params.argtypes = [P, P]
+    L.cr_pc_set_params.argtypes = [P, P]
+    L.cr_pc_forward.argtypes = [P, P, P]
+    L.cr_pc_vjp.argtypes = [P, P, P, P]
+    L.cr_pc_train_step.argtypes = [P, P, c_int32, P, P, P, POINTER(c_double), ctypes.c_float,
+                                   POINTER(c_double)]
     L.cr_last_error.restype = ctypes.c_char_p
     L.cr_version.restype = ctypes.c_char_p
     for name in EXPORTS:
-        L[name].restype = L[name].restype if name in (
-            "cr_problem_destroy", "cr_solve_opts_default", "cr_last_error", "cr_version") \
-            else ctypes.c_int
+        if name not in ("cr_problem_destroy", "cr_solve_opts_default", "cr_last_error",
+                        "cr_version", "cr_pc_destroy", "cr_pc_num_params"):
+            L[name].restype = ctypes.c_int
     _lib = L
     return L
 
@@ -262,6 +281,36 @@ class Problem:
                                        _ptr(V), _ld(V), ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
+    def u_system(self, U, Z, V, v):
+        """The u-system of eq. ALS_linsys at W = U Z V^T for unit v:
+        returns (rhs, d, coef) with coef = (c1, c0) on the host."""
+        r = int(U.shape[1])
+        U, Z, V = self._col(U), self._col(Z), self._col(V)
+        v = self._col(v).reshape(-1).contiguous()
+        rhs = torch.empty(self.n_y, device=self.device, dtype=torch.float64)
+        d = torch.empty(self.n_y, device=self.device, dtype=torch.float64)
+        coef = (c_double * 2)()
+        _check(load().cr_u_system(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1), _ptr(V),
+                                  _ld(V), _ptr(v), _ptr(rhs), _ptr(d), coef))
+        return rhs, d, (coef[0], coef[1])
+
+    def u_solve(self, d, coef, rhs, rtol=1e-8, maxit=5000, pc=None):
+        """Solve the u-system: Jacobi-PCG (pc None) or FCG with the network.
+        Returns (x, iters, relres, fallbacks, status)."""
+        d = self._col(d).reshape(-1).contiguous()
+        rhs = self._col(rhs).reshape(-1).contiguous()
+        x = torch.empty(self.n_y, device=self.device, dtype=torch.float64)
+        cf = (c_double * 2)(*coef)
+        it, rr, fb = c_int32(), c_double(), c_int32()
+        s = _check(load().cr_u_solve(self.h, _ptr(d), cf, _ptr(rhs), _ptr(x), rtol, maxit,
+                                     pc.h if pc is not None else None, ctypes.byref(it),
+                                     ctypes.byref(rr), ctypes.byref(fb)))
+        return x, it.value, rr.value, fb.value, STATUS_NAMES[s]
+
+    def set_pc(self, pc):
+        _check(load().cr_problem_set_pc(self.h, pc.h if pc is not None else None))
+        self._pc = pc
+
     def greedy_solve(self, resume=None, **opts):
         """Algorithm 1.  Returns dict(U, V, Z, rank, stats, history, status)."""
         o = default_opts(**opts)
@@ -292,3 +341,71 @@ class Problem:
         stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
         return dict(U=U[:, :r], V=V[:, :r], Z=Z[:r, :r], rank=r, stats=stats, history=hist,
                     status=STATUS_NAMES[s])
+
+
+class Pc:
+    """Learned preconditioner network for the u-systems on a box grid."""
+
+    def __init__(self, dims, channels=8, seed=0, device="cuda:0"):
+        self.device = torch.device(device)
+        self.dims = tuple(int(x) for x in dims)
+        self.channels = channels
+        with torch.cuda.device(self.device):
+            st = torch.cuda.current_stream(self.device)
+        h = c_void_p()
+        _check(load().cr_pc_create(*self.dims, channels, seed, c_void_p(st.cuda_stream),
+                                   ctypes.byref(h)))
+        self.h = h
+        self.n = int(np.prod(self.dims))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().cr_pc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_params(self):
+        return int(load().cr_pc_num_params(self.h))
+
+    def get_params(self):
+        out = np.empty(self.num_params(), np.float32)
+        _check(load().cr_pc_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        assert w.size == self.num_params()
+        _check(load().cr_pc_set_params(self.h, w.ctypes.data))
+
+    def forward(self, inp):
+        """inp: (4, N) float32 -> y (N,) float32 (device tensors)."""
+        inp = torch.as_tensor(inp, device=self.device, dtype=torch.float32).contiguous()
+        y = torch.empty(self.n, device=self.device, dtype=torch.float32)
+        torch.cuda.synchronize(self.device)
+        _check(load().cr_pc_forward(self.h, _ptr(inp), _ptr(y)))
+        return y
+
+    def vjp(self, inp, dy):
+        inp = torch.as_tensor(inp, device=self.device, dtype=torch.float32).contiguous()
+        dy = torch.as_tensor(dy, device=self.device, dtype=torch.float32).contiguous()
+        g = np.empty(self.num_params(), np.float32)
+        torch.cuda.synchronize(self.device)
+        _check(load().cr_pc_vjp(self.h, _ptr(inp), _ptr(dy), g.ctypes.data))
+        return g
+
+    def train_step(self, prob, b, x, d, coef, lr=1e-3):
+        """One Adam step on a batch: b, x, d (batch, n_y) float64 device tensors,
+        coef (batch, 2) host array.  Returns the mean relative squared error."""
+        b, x, d = (t.contiguous() for t in (b, x, d))
+        coef = np.ascontiguousarray(coef, np.float64)
+        loss = c_double()
+        torch.cuda.synchronize(self.device)
+        _check(load().cr_pc_train_step(self.h, prob.h, int(b.shape[0]), _ptr(b), _ptr(x), _ptr(d),
+                                       coef.ctypes.data_as(POINTER(c_double)), lr,
+                                       ctypes.byref(loss)))
+        return loss.value

@@ -12,6 +12,7 @@
 #include <map>
 #include <string>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "cr_internal.hpp"
@@ -48,6 +49,8 @@ struct cr_problem {
   double dnorm = 0.0;
   double* hscal = nullptr;  // pinned host scratch
   unsigned* bar = nullptr;  // grid-barrier words: [0] generation, [64] timeout, [128] arrivals
+  cr_pc* pc = nullptr;      // learned preconditioner for the u-systems (not owned)
+  int64_t pc_fallbacks = 0;
   int bar_mode = 1;
   std::map<std::string, DevBuf> ws;
   std::vector<void*> owned;
@@ -186,6 +189,39 @@ __global__ void k_neg(int n, const double* __restrict__ a, double* __restrict__ 
 }
 
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// q = lam*(L t + c1 t + c0 p) + d o p with t = L p (runtime stencil width)
+__global__ void k_uapply(int64_t n, int K, const int32_t* __restrict__ nbr, double lam,
+                         const double* __restrict__ coef, const double* __restrict__ d,
+                         const double* __restrict__ p, const double* __restrict__ t,
+                         double* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double lt = (double)K * t[i];
+  for (int k = 0; k < K; ++k) lt -= t[nbr[(int64_t)k * n + i]];
+  q[i] = lam * (lt + coef[0] * t[i] + coef[1] * p[i]) + d[i] * p[i];
+}
+// p = z + beta * pp
+__global__ void k_axpby(int64_t n, const double* __restrict__ z, double beta,
+                        const double* __restrict__ pp, double* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = z[i] + beta * pp[i];
+}
+// x += alpha p ; r -= alpha q
+__global__ void k_xr_update(int64_t n, double alpha, const double* __restrict__ p,
+                            const double* __restrict__ q, double* __restrict__ x,
+                            double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] += alpha * p[i];
+  r[i] -= alpha * q[i];
+}
+// z = minv o r
+__global__ void k_jacobi(int64_t n, const double* __restrict__ minv, const double* __restrict__ r,
+                         double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = minv[i] * r[i];
+}
 
 // ===================================================================== solver context
 template <typename T>
@@ -453,6 +489,38 @@ struct Ctx {
   // (x accumulated in FP64, r = b - A x evaluated in FP64 arithmetic).
   cr_status solve_sys(bool usys, const T* b, T* xout, double rtol, int maxit, double* dsc,
                       SolveOut* out, bool& deferred) {
+    if (usys && P->pc) {
+      deferred = false;
+      double* xs = WS(double, "fcg_x", ny);
+      int fb = 0;
+      const double *b64 = (const double*)b, *d64 = (const double*)dvec, *m64 = (const double*)minv_u;
+      if (!std::is_same<T, double>::value) {
+        // mixed handle: the flexible CG runs in FP64 on FP64 copies
+        double* cb = WS(double, "fcg_b", ny);
+        double* cd = WS(double, "fcg_d", ny);
+        double* cm = WS(double, "fcg_m", ny);
+        CR_TRY((convert2d<double, T>(ny, 1, b, ny, cb, ny, st)));
+        CR_TRY((convert2d<double, T>(ny, 1, dvec, ny, cd, ny, st)));
+        CR_TRY((convert2d<double, T>(ny, 1, minv_u, ny, cm, ny, st)));
+        b64 = cb;
+        d64 = cd;
+        m64 = cm;
+      }
+      CR_TRY(fcg_u(b64, xs, rtol, maxit, out, &fb, d64, m64));
+      P->pc_fallbacks += fb;
+      if (out->status != 0) {
+        // the network-preconditioned solve failed: Jacobi-PCG decides
+        ++P->pc_fallbacks;
+        CR_TRY(pcg(true, b, xout, rtol, maxit, dsc));
+        double h[4];
+        CR_TRY(read_scalars(dsc, 4, h));
+        *out = SolveOut{h[0], h[1], out->iters + (int)h[2], (int)h[3]};
+        return CR_OK;
+      }
+      CR_TRY(dot64(ny, xs, xs, tmp + 11));
+      CR_TRY(normalize_out<T>(ny, xs, tmp + 11, xout, st));
+      return CR_OK;
+    }
     if (std::is_same<T, double>::value) {
       deferred = true;
       return pcg(usys, b, xout, rtol, maxit, dsc);
@@ -508,6 +576,89 @@ struct Ctx {
     CR_TRY(normalize_out<T>(n, x64, tmp + 11, xout, st));
     CR_TRY(read_scalars(tmp + 11, 1, h));
     out->norm = std::sqrt(std::max(h[0], 0.0));
+    return CR_OK;
+  }
+
+  // Flexible CG (Notay, one stored direction) on the u-system with the
+  // network as preconditioner; z = M r falls back to the Jacobi step when
+  // <r, z> <= 0 or is not finite.  FP64 vectors, host-side scalars.
+  // Writes the solution into xsol (not normalised).
+  cr_status fcg_u(const double* b, double* xsol, double rtol, int maxit, SolveOut* out,
+                  int* fallbacks, const double* dv, const double* mi) {
+    cr_pc* pc = P->pc;
+    const int64_t n = ny;
+    double* W = WS(double, "fcg_work", 8 * n);
+    double *r = W, *z = W + n, *p = W + 2 * n, *q = W + 3 * n, *pp = W + 4 * n, *qq = W + 5 * n,
+           *t = W + 6 * n, *zj = W + 7 * n;
+    double h[4];
+    CR_HIP(hipMemsetAsync(xsol, 0, sizeof(double) * n, st));
+    CR_HIP(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    CR_TRY(dot64(n, b, b, tmp + 12));
+    CR_TRY(read_scalars(tmp + 12, 1, h));
+    const double bb = h[0];
+    *out = SolveOut{};
+    if (!(bb > 0.0)) {
+      out->status = 2;
+      return CR_OK;
+    }
+    double pq_prev = 0.0, rr = bb;
+    int it = 0;
+    for (; it < maxit; ++it) {
+      // z = M r: the network refines the Jacobi step zj = D^-1 r
+      hipLaunchKernelGGL(k_jacobi, dim3(nblk(n)), dim3(256), 0, st, n, mi, r, zj);
+      CR_HIP(hipGetLastError());
+      CR_TRY(dot64(n, zj, zj, tmp + 12));
+      CR_TRY(lpc_input(pc->net, zj, tmp + 12, mi, dv, P->gy.deg, cu, lam, pc->acts.in, st));
+      CR_TRY(lpc_forward(pc->net, pc->acts.in, pc->acts, st));
+      CR_TRY(lpc_output(pc->net, pc->acts.in, pc->acts.y, z, st));
+      Blocks<double> A;
+      A.clear();
+      A.add(r, n, 1);
+      if (it > 0) A.add(qq, n, 1);
+      CR_TRY(gemv_t<double>(n, A, z, tmp + 13, part, st));
+      CR_TRY(read_scalars(tmp + 13, it > 0 ? 2 : 1, h));
+      if (!(h[0] > 0.0) || !std::isfinite(h[0]) || (it > 0 && !std::isfinite(h[1]))) {
+        CR_HIP(hipMemcpyAsync(z, zj, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        CR_TRY(gemv_t<double>(n, A, z, tmp + 13, part, st));
+        CR_TRY(read_scalars(tmp + 13, it > 0 ? 2 : 1, h));
+        ++*fallbacks;
+      }
+      const double beta = it > 0 ? -h[1] / pq_prev : 0.0;
+      hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, st, n, z, beta, pp, p);
+      CR_TRY(stencil<double>(P->gy, 1, p, n, t, n, st));
+      hipLaunchKernelGGL(k_uapply, dim3(nblk(n)), dim3(256), 0, st, n, P->gy.K, P->gy.nbr, lam,
+                         cu, dv, p, t, q);
+      CR_HIP(hipGetLastError());
+      A.clear();
+      A.add(q, n, 1);
+      A.add(r, n, 1);
+      CR_TRY(gemv_t<double>(n, A, p, tmp + 13, part, st));
+      CR_TRY(read_scalars(tmp + 13, 2, h));
+      const double pq = h[0], pr = h[1];
+      if (!(pq > 0.0)) {
+        out->status = 2;
+        break;
+      }
+      const double alpha = pr / pq;
+      hipLaunchKernelGGL(k_xr_update, dim3(nblk(n)), dim3(256), 0, st, n, alpha, p, q, xsol, r);
+      CR_HIP(hipGetLastError());
+      CR_TRY(dot64(n, r, r, tmp + 12));
+      CR_TRY(read_scalars(tmp + 12, 1, h));
+      rr = h[0];
+      std::swap(p, pp);
+      std::swap(q, qq);
+      pq_prev = pq;
+      if (rr <= rtol * rtol * bb) {
+        ++it;
+        break;
+      }
+    }
+    out->iters = it;
+    out->relres = std::sqrt(rr / bb);
+    if (out->status == 0 && !(rr <= rtol * rtol * bb)) out->status = 1;
+    CR_TRY(dot64(n, xsol, xsol, tmp + 12));
+    CR_TRY(read_scalars(tmp + 12, 1, h));
+    out->norm = std::sqrt(h[0]);
     return CR_OK;
   }
 
@@ -1370,4 +1521,157 @@ extern "C" cr_status cr_greedy_solve(cr_problem* P, const cr_solve_opts* opts, d
   return P->prec == CR_PREC_MIXED
              ? greedy_impl<float>(P, *opts, U, V, Z, rank_io, stats, cb, user)
              : greedy_impl<double>(P, *opts, U, V, Z, rank_io, stats, cb, user);
+}
+
+// ===================================================================== u-systems and the network
+extern "C" cr_status cr_problem_set_pc(cr_problem* P, cr_pc* pc) {
+  if (!P) {
+    set_error("null handle");
+    return CR_EINVAL;
+  }
+  if (pc) {
+    const int64_t N = (int64_t)pc->net.nx * pc->net.ny * pc->net.nz;
+    if (N != P->ny) {
+      set_error("the network's box must match the target grid");
+      return CR_EINVAL;
+    }
+  }
+  P->pc = pc;
+  P->pc_fallbacks = 0;
+  return CR_OK;
+}
+
+extern "C" cr_status cr_u_system(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                 const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                                 const double* v, double* rhs_out, double* d_out,
+                                 double* coef_out) {
+  if (!P || r < 0 || !v || !rhs_out || !d_out || !coef_out || (r > 0 && (!U || !Z || !V))) {
+    set_error("invalid arguments to cr_u_system");
+    return CR_EINVAL;
+  }
+  if (P->prec != CR_PREC_FP64) {
+    set_error("cr_u_system needs an FP64 handle");
+    return CR_EINVAL;
+  }
+  Ctx<double> c(P);
+  CR_TRY(load_iterate<double>(c, (int)r, U, ldu, Z, ldz, V, ldv, true));
+  CR_TRY(c.alloc_vectors(0));
+  CR_HIP(hipMemcpyAsync(c.vv, v, sizeof(double) * c.nx, hipMemcpyDeviceToDevice, c.st));
+  CR_TRY(stencil<double>(P->gx, 1, c.vv, c.nx, c.Lv, c.nx, c.st));
+  CR_TRY(c.apply_R((int)r, c.vv, rhs_out));
+  CR_TRY(masked_quad_ws<double>(c.ny, c.ninj, P->bits, c.y0, d_out, c.tmp + 8, c.st));
+  CR_TRY(c.dot(c.nx, c.Lv, c.vv, c.tmp + 0));
+  CR_TRY(c.dot(c.nx, c.Lv, c.Lv, c.tmp + 1));
+  double h[2];
+  CR_TRY(c.read_scalars(c.tmp, 2, h));
+  coef_out[0] = 2.0 * h[0];
+  coef_out[1] = h[1];
+  return CR_OK;
+}
+
+extern "C" cr_status cr_u_solve(cr_problem* P, const double* d, const double* coef,
+                                const double* rhs, double* x_out, double rtol, int32_t maxit,
+                                cr_pc* pc, int32_t* iters_out, double* relres_out,
+                                int32_t* fallbacks_out) {
+  if (!P || !d || !coef || !rhs || !x_out || !(rtol > 0) || maxit <= 0) {
+    set_error("invalid arguments to cr_u_solve");
+    return CR_EINVAL;
+  }
+  if (P->prec != CR_PREC_FP64) {
+    set_error("cr_u_solve needs an FP64 handle");
+    return CR_EINVAL;
+  }
+  if (pc && (int64_t)pc->net.nx * pc->net.ny * pc->net.nz != P->ny) {
+    set_error("the network's box does not match the target grid");
+    return CR_EINVAL;
+  }
+  Ctx<double> c(P);
+  CR_TRY(c.alloc_rank(1));
+  CR_TRY(c.alloc_vectors(0));
+  CR_HIP(hipMemcpyAsync(c.cu, coef, 2 * sizeof(double), hipMemcpyHostToDevice, c.st));
+  CR_HIP(hipMemcpyAsync(c.dvec, d, sizeof(double) * c.ny, hipMemcpyDeviceToDevice, c.st));
+  CR_TRY(pcg_diag<double>(P->gy, c.lam, c.cu, c.dvec, nullptr, 0, 0, nullptr, c.minv_u, c.st));
+  Ctx<double>::SolveOut so;
+  int fb = 0;
+  if (pc) {
+    cr_pc* saved = P->pc;
+    P->pc = pc;
+    cr_status s = c.fcg_u(rhs, x_out, rtol, maxit, &so, &fb, c.dvec, c.minv_u);
+    P->pc = saved;
+    CR_TRY(s);
+  } else {
+    CR_TRY(c.pcg(true, rhs, c.vu, rtol, maxit, c.sc));
+    double h[4];
+    CR_TRY(c.read_scalars(c.sc, 4, h));
+    so = Ctx<double>::SolveOut{h[0], h[1], (int)h[2], (int)h[3]};
+    CR_HIP(hipMemcpyAsync(x_out, c.pw_u[0], sizeof(double) * c.ny, hipMemcpyDeviceToDevice, c.st));
+  }
+  CR_HIP(hipStreamSynchronize(c.st));
+  if (iters_out) *iters_out = so.iters;
+  if (relres_out) *relres_out = so.relres;
+  if (fallbacks_out) *fallbacks_out = fb;
+  if (so.status == 2) {
+    set_error("u-system solve broke down (zero right-hand side or indefinite step)");
+    return CR_ENONFINITE;
+  }
+  return so.status == 1 ? CR_NOTCONV : (fb ? CR_PC_FALLBACK : CR_OK);
+}
+
+extern "C" cr_status cr_pc_train_step(cr_pc* pc, cr_problem* P, int32_t batch, const double* b,
+                                      const double* x, const double* d, const double* coef,
+                                      float lr, double* loss_out) {
+  if (!pc || !P || batch <= 0 || !b || !x || !d || !coef) {
+    set_error("invalid arguments to cr_pc_train_step");
+    return CR_EINVAL;
+  }
+  const int64_t n = P->ny;
+  if ((int64_t)pc->net.nx * pc->net.ny * pc->net.nz != n) {
+    set_error("the network's box does not match the target grid");
+    return CR_EINVAL;
+  }
+  hipStream_t st = pc->st;
+  const int64_t lsz = lpc_loss_scratch(pc->net);
+  const int64_t need = 8 + lsz + gemv_t_part_size(n, 1) + 4 * n;
+  if (pc->dwork_n < need) {
+    if (pc->dwork) (void)hipFree(pc->dwork);
+    pc->dwork = nullptr;
+    pc->dwork_n = 0;
+    if (hipMalloc(&pc->dwork, sizeof(double) * need) != hipSuccess) {
+      set_error("allocation of training scratch failed");
+      return CR_ENOMEM;
+    }
+    pc->dwork_n = need;
+  }
+  double* sc = pc->dwork;           // [0] ||w||^2, [2..3] coefficients
+  double* lscr = sc + 8;            // loss scratch (tot[3] = loss)
+  double* gpart = lscr + lsz;       // gemv partials
+  double* minv = gpart + gemv_t_part_size(n, 1);
+  double* w = minv + n;
+  double total = 0.0;
+  for (int s = 0; s < batch; ++s) {
+    const double* bs = b + (int64_t)s * n;
+    const double* xs = x + (int64_t)s * n;
+    const double* ds = d + (int64_t)s * n;
+    CR_HIP(hipMemcpyAsync(sc + 2, coef + 2 * s, 2 * sizeof(double), hipMemcpyHostToDevice, st));
+    CR_TRY(pcg_diag<double>(P->gy, P->lam, sc + 2, ds, nullptr, 0, 0, nullptr, minv, st));
+    hipLaunchKernelGGL(k_jacobi, dim3(nblk(n)), dim3(256), 0, st, n, minv, bs, w);
+    CR_HIP(hipGetLastError());
+    Blocks<double> A;
+    A.clear();
+    A.add(w, n, 1);
+    CR_TRY(gemv_t<double>(n, A, w, sc + 0, gpart, st));
+    CR_TRY(lpc_input(pc->net, w, sc + 0, minv, ds, P->gy.deg, sc + 2, P->lam, pc->acts.in, st));
+    CR_TRY(lpc_forward(pc->net, pc->acts.in, pc->acts, st));
+    CR_TRY(lpc_loss(pc->net, pc->acts.in, pc->acts.y, xs, pc->acts.dy, lscr, st));
+    CR_TRY(lpc_backward(pc->net, pc->acts.in, pc->acts, st));
+    double l = 0.0;
+    CR_HIP(hipMemcpyAsync(&pc->hloss, lscr + lsz - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    CR_HIP(hipStreamSynchronize(st));
+    l = pc->hloss;
+    total += l;
+  }
+  CR_TRY(lpc_adam(pc->net, lr, 1.0f / (float)batch, st));
+  CR_HIP(hipStreamSynchronize(st));
+  if (loss_out) *loss_out = total / batch;
+  return std::isfinite(total) ? CR_OK : CR_ENONFINITE;
 }

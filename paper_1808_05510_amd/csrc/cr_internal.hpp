@@ -201,6 +201,37 @@ struct GalerkinArgs {
 cr_status galerkin_cg(const GalerkinArgs& a, int nwg, hipStream_t st);
 int galerkin_max_wg(int r);
 
+// ---------------------------------------------------------------- learned preconditioner
+constexpr int LPC_MAXC = 8;
+constexpr int LPC_LAYERS = 5;
+struct LpcNet {
+  int nx = 0, ny = 0, nz = 0, C = 0;
+  int ci[LPC_LAYERS], co[LPC_LAYERS];
+  float *W[LPC_LAYERS], *B[LPC_LAYERS], *gW[LPC_LAYERS], *gB[LPC_LAYERS];
+  float *mW[LPC_LAYERS], *vW[LPC_LAYERS], *mB[LPC_LAYERS], *vB[LPC_LAYERS];
+  int step = 0;
+  int64_t nparam = 0;
+  float* mem = nullptr;  // one allocation: params, grads, Adam moments
+};
+struct LpcActs {
+  float *in = nullptr, *a0, *a1, *p, *a2, *a3, *s, *y, *dy, *ds, *da3, *da2, *dp, *da0, *partial;
+  float* mem = nullptr;
+};
+cr_status lpc_forward(const LpcNet& net, const float* in, LpcActs& a, hipStream_t st);
+cr_status lpc_backward(LpcNet& net, const float* in, LpcActs& a, hipStream_t st);
+// network input from w = minv o r (w2 = ||w||^2 on the device)
+cr_status lpc_input(const LpcNet& net, const double* w, const double* w2, const double* minv,
+                    const double* dvec, const uint8_t* deg, const double* coef, double lam,
+                    float* in, hipStream_t st);
+// z = in0 + y
+cr_status lpc_output(const LpcNet& net, const float* in0, const float* y, double* z,
+                     hipStream_t st);
+// loss 1 - cos^2(in0 + y, xs) into scratch[3 * nblocks + 3] and dy = dL/dy
+int64_t lpc_loss_scratch(const LpcNet& net);
+cr_status lpc_loss(const LpcNet& net, const float* in0, const float* y, const double* xs,
+                   float* dy, double* scratch, hipStream_t st);
+cr_status lpc_adam(LpcNet& net, float lr, float scale, hipStream_t st);
+
 // ---------------------------------------------------------------- small ops
 // out[i] = sum_k M[i + k*ldm] * v[k] * alpha  (i < m, k < kk), single block
 cr_status small_gemv(int m, int kk, const double* M, int64_t ldm, bool trans, const double* v,
@@ -222,3 +253,13 @@ cr_status hole_gram_col(int ninj, const int32_t* hptr, const int32_t* hidx, int 
                         hipStream_t st);
 
 }  // namespace cr
+
+// preconditioner object of the C ABI
+struct cr_pc {
+  cr::LpcNet net;
+  cr::LpcActs acts;
+  hipStream_t st = nullptr;
+  double* dwork = nullptr;  // FCG / training scratch (grown on demand)
+  int64_t dwork_n = 0;
+  double hloss = 0.0;
+};

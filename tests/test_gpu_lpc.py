@@ -1,0 +1,140 @@
+"""Learned preconditioner and u-system entry points against the oracle.
+
+* network forward / vector-Jacobian product: FP32 GPU vs FP64 reference,
+  relative 1e-5 (forward) and 1e-4 (gradients, sums over every voxel);
+* u-system (right-hand side, data diagonal, coefficients): 1e-12 relative;
+* solves: Jacobi-PCG and FCG + network (trained or not, or with NaN weights
+  that force the Jacobi fallback) all reach the dense solution to 1e-9.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import als as oals
+from oracle import greedy as ogreedy
+from oracle import lpc as olpc
+from oracle import metrics as omet
+from oracle import operator as oop
+from paper_1808_05510_amd import connreg, synth
+from tests.helpers import rand_orth, rel
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def box(seed=0, by=(8, 6, 4), bx=(6, 4, 4), n_inj=5, lam=50.0):
+    return synth.box_problem(box_y=by, box_x=bx, offset=(1, 1, 0), n_inj=n_inj, sigma=1.2,
+                             hole_r=1.0, wt_rank=3, wt_w=(1.5, 3.0), lam=lam, seed=seed)
+
+
+@pytest.mark.parametrize("dims,C", [((8, 6, 4), 8), ((7, 5, 3), 4)])
+def test_pc_forward_and_vjp_match_reference(dims, C):
+    pc = connreg.Pc(dims, channels=C, seed=3)
+    w = pc.get_params().astype(np.float64)
+    rng = np.random.default_rng(1)
+    # bias the network so that ReLUs are active on both sides of zero
+    w = w + 0.05 * rng.standard_normal(w.size)
+    pc.set_params(w.astype(np.float32))
+    w = pc.get_params().astype(np.float64)
+    n = int(np.prod(dims))
+    inp = rng.standard_normal((4, n)).astype(np.float32)
+    dy = rng.standard_normal(n).astype(np.float32)
+    y = pc.forward(torch.tensor(inp)).cpu().numpy()
+    g = pc.vjp(torch.tensor(inp), torch.tensor(dy))
+    yr, gr = olpc.forward_vjp(w, C, dims, inp.astype(np.float64), dy.astype(np.float64))
+    assert rel(y, yr) < 1e-5
+    assert rel(g, gr) < 1e-4
+    pc.close()
+
+
+@pytest.fixture(scope="module")
+def boxprob():
+    d = box()
+    P = oop.problem_from_arrays(d)
+    rng = np.random.default_rng(5)
+    r = 3
+    U = rand_orth(rng, P.n_y, r)
+    V = rand_orth(rng, P.n_x, r)
+    Z = rng.standard_normal((r, r))
+    v = rng.standard_normal(P.n_x)
+    v /= np.linalg.norm(v)
+    return d, P, U, Z, V, v
+
+
+def test_u_system_matches_oracle(boxprob):
+    d, P, U, Z, V, v = boxprob
+    g = connreg.Problem(d, "fp64", DEV)
+    rhs, dd, coef = g.u_system(U, Z, V, v)
+    F, G = oop.residual_factors(P, U, Z, V)
+    a, b, dref = oals.u_coeffs(P, v)
+    assert rel(rhs.cpu().numpy(), F @ (G.T @ v)) < 1e-12
+    assert rel(dd.cpu().numpy(), dref) < 1e-12
+    assert abs(coef[0] - 2 * b) <= 1e-12 * abs(2 * b) and abs(coef[1] - a) <= 1e-12 * abs(a)
+
+
+def test_u_solves_reach_the_dense_solution(boxprob):
+    d, P, U, Z, V, v = boxprob
+    g = connreg.Problem(d, "fp64", DEV)
+    rhs, dd, coef = g.u_system(U, Z, V, v)
+    xref = oals.solve_u(P, v, rhs.cpu().numpy(), method="dense")
+    xj, itj, rrj, fbj, sj = g.u_solve(dd, coef, rhs, rtol=1e-13, maxit=20000)
+    assert sj == "ok" and rel(xj.cpu().numpy(), xref) < 1e-9
+    pc = connreg.Pc(d["box_y"], channels=8, seed=7)
+    xf, itf, rrf, fbf, sf = g.u_solve(dd, coef, rhs, rtol=1e-13, maxit=20000, pc=pc)
+    assert sf in ("ok", "pc_fallback") and rel(xf.cpu().numpy(), xref) < 1e-9
+    # a network with NaN weights: every step falls back to Jacobi, same answer
+    w = pc.get_params()
+    w[:] = np.nan
+    pc.set_params(w)
+    xn, itn, rrn, fbn, sn = g.u_solve(dd, coef, rhs, rtol=1e-13, maxit=20000, pc=pc)
+    assert sn == "pc_fallback" and fbn == itn > 0
+    assert rel(xn.cpu().numpy(), xref) < 1e-9
+    pc.close()
+
+
+def _pairs(g, P, rng, count, r=3):
+    bs, xs, ds, cs = [], [], [], []
+    for _ in range(count):
+        U = rand_orth(rng, P.n_y, r)
+        V = rand_orth(rng, P.n_x, r)
+        Z = rng.standard_normal((r, r))
+        v = rng.standard_normal(P.n_x)
+        v /= np.linalg.norm(v)
+        rhs, dd, coef = g.u_system(U, Z, V, v)
+        x = g.u_solve(dd, coef, rhs, rtol=1e-12, maxit=20000)[0]
+        bs.append(rhs)
+        xs.append(x)
+        ds.append(dd)
+        cs.append(coef)
+    return torch.stack(bs), torch.stack(xs), torch.stack(ds), np.array(cs)
+
+
+def test_training_lowers_the_loss(boxprob):
+    d, P, *_ = boxprob
+    g = connreg.Problem(d, "fp64", DEV)
+    rng = np.random.default_rng(11)
+    b, x, dd, cf = _pairs(g, P, rng, 8)
+    pc = connreg.Pc(d["box_y"], channels=8, seed=1)
+    first = pc.train_step(g, b, x, dd, cf, lr=3e-3)
+    for _ in range(60):
+        last = pc.train_step(g, b, x, dd, cf, lr=3e-3)
+    assert np.isfinite(first) and last < 0.5 * first
+    pc.close()
+
+
+def test_greedy_with_network_keeps_the_answer():
+    d = box(seed=2)
+    P = oop.problem_from_arrays(d)
+    ores = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(max_rank=6, als_fixed_sweeps=2,
+                                                         u_method="dense", v_method="dense",
+                                                         galerkin="dense", seed=4))
+    g = connreg.Problem(d, "fp64", DEV)
+    pc = connreg.Pc(d["box_y"], channels=8, seed=9)
+    g.set_pc(pc)
+    res = g.greedy_solve(max_rank=6, als_fixed_sweeps=2, pcg_rtol=1e-13, pcg_maxit=20000,
+                         galerkin_rtol=1e-13, galerkin_maxit=20000, seed=4)
+    U, V, Z = (res[k].cpu().numpy() for k in ("U", "V", "Z"))
+    err = omet.diff_norm(U, Z, V, ores.U, ores.Z, ores.V) / omet.low_rank_norm(ores.U, ores.Z, ores.V)
+    assert err < 1e-6
+    g.set_pc(None)
+    pc.close()
