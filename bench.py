@@ -23,6 +23,7 @@ import torch  # noqa: E402
 from paper_1808_05510_amd import connreg, synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 METRIC = "secs to rel. residual 1e-4 & op-apply HBM GB/s: plain FP64 vs mixed+learned-PC"
 
 
@@ -85,6 +86,67 @@ def bench_op_apply(d, r, reps, warm, fp32):
                 bytes=nbytes, GBps=nbytes / med / 1e9, frac=nbytes / med / 1e9 / HBM_PEAK_GBS)
 
 
+def bench_gram(d, r, reps, warm):
+    """Batched masked Gram U^T diag(Omega_a) U, all a, in Khatri-Rao form on the
+    BF16 matrix cores: r (r + 1) n_inj n_y flops per call."""
+    prob = connreg.Problem(d, "fp64", "cuda:0")
+    g = torch.Generator(device="cuda:0").manual_seed(2)
+    U = torch.randn((r, prob.n_y), device="cuda:0", dtype=torch.float64, generator=g).T
+    U = U / U.norm(dim=0, keepdim=True)
+    ts = []
+    for k in range(warm + reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        prob.masked_gram(U, "bf16")
+        e1.record()
+        e1.synchronize()
+        if k >= warm:
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+    flops = float(r) * (r + 1) * prob.n_inj * prob.n_y
+    med = float(np.median(ts))
+    prob.close()
+    return dict(r=r, seconds=med, flops=flops, TFLOPs=flops / med / 1e12,
+                frac=flops / med / 1e12 / BF16_PEAK_TFLOPS)
+
+
+def bench_batch(count=16, max_rank=40, tau=1e-4, prec="mixed"):
+    """The uneven 16-problem batch: each problem solved on its own (full
+    device), then all at once through cr_greedy_solve_batch."""
+    specs = synth.config4_specs(0, count)
+    t0 = time.perf_counter()
+    datas = [synth.box_problem(box_y=s.box_y, box_x=s.box_x,
+                               offset=tuple((np.array(s.box_y) - np.array(s.box_x)) // 2),
+                               n_inj=s.n_inj, lam=s.lam, max_rank=max_rank, seed=s.seed)
+             for s in specs]
+    gen = time.perf_counter() - t0
+    streams = [torch.cuda.Stream() for _ in datas]
+    probs = [connreg.Problem(d, prec, "cuda:0", stream=st) for d, st in zip(datas, streams)]
+    opts = dict(max_rank=max_rank, tau_res=tau, seed=0)
+    # warm-up (workspace allocation) then sequential timing
+    connreg.greedy_solve_batch(probs[:1], [dict(opts, max_rank=2)])
+    for p in probs:
+        p.greedy_solve(**dict(opts, max_rank=2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [p.greedy_solve(**opts) for p in probs]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bat = connreg.greedy_solve_batch(probs, [opts] * len(probs))
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    out = dict(problems=count, precision=prec, generation_s=gen, sequential_s=t_seq,
+               batched_s=t_bat, speedup=t_seq / t_bat,
+               sizes=[[p.n_y, p.n_x, p.n_inj] for p in probs],
+               ranks_seq=[r["rank"] for r in seq], ranks_batch=[r["rank"] for r in bat],
+               relres_seq=[r["stats"]["relres"] for r in seq],
+               relres_batch=[r["stats"]["relres"] for r in bat])
+    for p in probs:
+        p.close()
+    return out
+
+
 def cpu_baseline(d, lam, ranks_needed, sample_ranks):
     """FP64 oracle (NumPy/SciPy, Jacobi-CG inner solves) on the first
     ``sample_ranks`` greedy steps of the same workload; seconds per rank times
@@ -119,6 +181,8 @@ def main():
     ap.add_argument("--op-reps", type=int, default=30)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--op-only", action="store_true", help="only the op_apply bandwidth part")
+    ap.add_argument("--batch-only", action="store_true", help="only the 16-problem batch")
+    ap.add_argument("--no-batch", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the solver is a "
@@ -127,11 +191,19 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     connreg.load()
 
+    if a.batch_only:
+        b = bench_batch()
+        log(json.dumps(b))
+        return
     if a.op_only:
         d3 = synth.config3(seed=0)
         for fp32 in (False, True):
             o = bench_op_apply(d3, 100, a.op_reps, 5, fp32)
             log(f"[bench] op_apply {o['dtype']} r=100: {o['seconds']*1e6:.1f} us, {o['GBps']:.0f} GB/s")
+        for r in (60, 100):
+            o = bench_gram(d3, r, 10, 3)
+            log(f"[bench] BF16 KR Gram r={r}: {o['seconds']*1e3:.3f} ms, {o['TFLOPs']:.0f} TFLOP/s "
+                f"({100*o['frac']:.1f}% of BF16 dense peak)")
         return
     d2 = synth.config2(lam=a.lam, seed=0)
     opts = dict(max_rank=a.max_rank, tau_res=a.tau, seed=0, verbose=1 if a.verbose else 0)
@@ -167,10 +239,23 @@ def main():
                 op[f"{o['dtype']}_r{r}"] = o
                 log(f"[bench] op_apply {o['dtype']} r={r}: {o['seconds']*1e6:.1f} us, "
                     f"{o['GBps']:.0f} GB/s ({100*o['frac']:.1f}% of HBM peak)")
+        gram = {}
+        for r in (60, 100):
+            o = bench_gram(d3, r, 10, 3)
+            gram[f"bf16_r{r}"] = o
+            log(f"[bench] BF16 KR Gram r={r}: {o['seconds']*1e3:.3f} ms, {o['TFLOPs']:.0f} TFLOP/s")
+        op["gram"] = gram
         o = op["f64_r100"]
         roof = dict(bound="hbm", achieved=o["GBps"], peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=o["frac"], traffic=None, kernel="cr_op_apply (FP64, r=100, shells)")
         del d3
+
+    batch = None
+    if not a.no_batch:
+        log("[bench] 16-problem batch (sequential vs one batched call)")
+        batch = bench_batch()
+        log(f"[bench] batch: sequential {batch['sequential_s']:.2f} s, batched "
+            f"{batch['batched_s']:.2f} s, speedup {batch['speedup']:.2f}")
 
     cpu = None
     if not a.no_cpu:
@@ -205,6 +290,7 @@ def main():
         "relres_curve": [[h["rank"], h["relres"], h["seconds"]] for h in hist],
         "mixed": mixed,
         "op_apply": op,
+        "batch": batch,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -204,6 +204,17 @@ cr_status cr_greedy_solve(cr_problem* p, const cr_solve_opts* opts, double* U, d
                           double* Z, int64_t* rank_io, cr_solve_stats* stats, cr_rank_cb cb,
                           void* user);
 
+/* Batched masked Grams G_a = U^T diag(Omega_a) U for every injection a, the
+ * data term of eq. Proj_Sylv.  U [dev] n_y x r (ldu); G [dev] n_inj blocks of
+ * ldg x ldg (ldg >= r), block a at G + a ldg^2, column-major, full symmetric.
+ * mode 0: FP64, exact up to summation order (incremental column form, using
+ * the unobserved-voxel lists when they are sparse); mode 1: one Khatri-Rao
+ * GEMM C[(a,b), alpha] = sum_i U_ia U_ib omega_i,alpha on the BF16 matrix
+ * cores with FP32 accumulation (r <= 256), entry error below
+ * 2^-8 ||U_a|| ||U_b|| plus FP32 accumulation.  Asynchronous. */
+cr_status cr_masked_gram(cr_problem* p, int64_t r, const double* U, int64_t ldu, int32_t mode,
+                         double* G, int64_t ldg);
+
 /* ---------------------------------------------------------------------------
  * ALS u-system access and the learned preconditioner.
  *
@@ -268,6 +279,36 @@ cr_status cr_u_solve(cr_problem* p, const double* d, const double* coef, const d
  * does not own pc.  Jacobi-PCG takes over any u-solve that the
  * network-preconditioned FCG does not finish. */
 cr_status cr_problem_set_pc(cr_problem* p, cr_pc* pc);
+
+/* ---------------------------------------------------------------------------
+ * Batched solves and autotuning.
+ * ------------------------------------------------------------------------- */
+
+/* Runs Algorithm 1 on `count` independent problems concurrently: K worker
+ * threads (K = the largest value <= min(count, 16) for which every problem
+ * fits) take problems from a queue, largest first; each problem runs on its
+ * own handle and stream (distinct handles on distinct streams are
+ * required).  While the call runs, each problem's persistent kernels (PCG,
+ * projected CG) are limited to the workgroup slots of 3/4 of 1/K of the
+ * device's CUs and launched as ordinary kernels with the library's bounded
+ * grid barrier, so the grids of K problems fit on the device at once and
+ * overlap.  opts, U, V, Z, ranks, stats, statuses are arrays of `count`
+ * entries with the meaning of cr_greedy_solve (stats may be NULL).  Returns
+ * the first hard error, CR_OK otherwise; per-problem statuses in statuses[]. */
+cr_status cr_greedy_solve_batch(int32_t count, cr_problem** probs, const cr_solve_opts* opts,
+                                double** U, double** V, double** Z, int64_t* ranks,
+                                cr_solve_stats* stats, int32_t* statuses);
+
+/* Autotuner for the PCG grid shape (the stencil tile of the persistent
+ * kernels): times 60 iterations of a representative u- and v-system for
+ * voxels per thread 1, 2, 4, 8 (those whose grid fits in cu_share CUs;
+ * cu_share <= 0: the whole device) and keeps the fastest for later solves
+ * with pcg_vpt = 0.  Outputs [host], may be NULL: chosen values and
+ * microseconds per iteration.  FP64 handles.  Synchronises. */
+cr_status cr_autotune_pcg(cr_problem* p, int32_t cu_share, int32_t* vpt_u, int32_t* vpt_v,
+                          double* us_u, double* us_v);
+/* Set the tuned values directly (e.g. from a cache); 0 = heuristic. */
+cr_status cr_problem_set_tuning(cr_problem* p, int32_t vpt_u, int32_t vpt_v);
 
 /* Message of the last hard error on this thread ("" if none). */
 const char* cr_last_error(void);

@@ -28,7 +28,8 @@ EXPORTS = ["cr_problem_create", "cr_problem_destroy", "cr_rhs_norm", "cr_op_appl
            "cr_residual_norm", "cr_greedy_solve", "cr_last_error", "cr_version",
            "cr_u_system", "cr_u_solve", "cr_problem_set_pc", "cr_pc_create", "cr_pc_destroy",
            "cr_pc_num_params", "cr_pc_get_params", "cr_pc_set_params", "cr_pc_forward",
-           "cr_pc_vjp", "cr_pc_train_step"]
+           "cr_pc_vjp", "cr_pc_train_step", "cr_masked_gram", "cr_greedy_solve_batch",
+           "cr_autotune_pcg", "cr_problem_set_tuning"]
 
 
 class CSR(ctypes.Structure):
@@ -115,6 +116,13 @@ def load(path: str = LIB_PATH):
     L.cr_pc_vjp.argtypes = [P, P, P, P]
     L.cr_pc_train_step.argtypes = [P, P, c_int32, P, P, P, POINTER(c_double), ctypes.c_float,
                                    POINTER(c_double)]
+    L.cr_masked_gram.argtypes = [P, c_int64, P, c_int64, c_int32, P, c_int64]
+    L.cr_greedy_solve_batch.argtypes = [c_int32, POINTER(P), POINTER(SolveOpts), POINTER(P),
+                                        POINTER(P), POINTER(P), POINTER(c_int64),
+                                        POINTER(SolveStats), POINTER(c_int32)]
+    L.cr_autotune_pcg.argtypes = [P, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                  POINTER(c_double), POINTER(c_double)]
+    L.cr_problem_set_tuning.argtypes = [P, c_int32, c_int32]
     L.cr_last_error.restype = ctypes.c_char_p
     L.cr_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -281,6 +289,16 @@ class Problem:
                                        _ptr(V), _ld(V), ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
+    def masked_gram(self, U, mode="fp64"):
+        """G (n_inj, r, r) float64 device tensor, G[a] = U^T diag(Omega_a) U."""
+        r = int(U.shape[1])
+        U = self._col(U)
+        G = torch.zeros((self.n_inj, r, r), device=self.device, dtype=torch.float64)
+        _check(load().cr_masked_gram(self.h, r, _ptr(U), _ld(U), {"fp64": 0, "bf16": 1}[mode],
+                                     _ptr(G), r))
+        torch.cuda.synchronize(self.device)
+        return G.transpose(1, 2)  # column-major blocks -> [a][row][col]
+
     def u_system(self, U, Z, V, v):
         """The u-system of eq. ALS_linsys at W = U Z V^T for unit v:
         returns (rhs, d, coef) with coef = (c1, c0) on the host."""
@@ -310,6 +328,16 @@ class Problem:
     def set_pc(self, pc):
         _check(load().cr_problem_set_pc(self.h, pc.h if pc is not None else None))
         self._pc = pc
+
+    def autotune(self, cu_share=0):
+        """Pick the PCG voxels per thread by timing; returns (vpt_u, vpt_v, us_u, us_v)."""
+        vu, vv, tu, tv = c_int32(), c_int32(), c_double(), c_double()
+        _check(load().cr_autotune_pcg(self.h, cu_share, ctypes.byref(vu), ctypes.byref(vv),
+                                      ctypes.byref(tu), ctypes.byref(tv)))
+        return vu.value, vv.value, tu.value, tv.value
+
+    def set_tuning(self, vpt_u, vpt_v):
+        _check(load().cr_problem_set_tuning(self.h, vpt_u, vpt_v))
 
     def greedy_solve(self, resume=None, **opts):
         """Algorithm 1.  Returns dict(U, V, Z, rank, stats, history, status)."""
@@ -409,3 +437,34 @@ class Pc:
                                        coef.ctypes.data_as(POINTER(c_double)), lr,
                                        ctypes.byref(loss)))
         return loss.value
+
+
+def greedy_solve_batch(problems, opts_list):
+    """Algorithm 1 on several problems at once (one handle and stream each).
+    Returns a list of dicts like Problem.greedy_solve (without history)."""
+    n = len(problems)
+    L = load()
+    opts = (SolveOpts * n)(*[default_opts(**o) for o in opts_list])
+    Us, Vs, Zs = [], [], []
+    for p, o in zip(problems, opts):
+        R = int(o.max_rank)
+        Us.append(zeros_colmajor(p.n_y, R, p.device))
+        Vs.append(zeros_colmajor(p.n_x, R, p.device))
+        Zs.append(zeros_colmajor(R, R, p.device))
+    P = c_void_p
+    hs = (P * n)(*[p.h for p in problems])
+    up = (P * n)(*[u.data_ptr() for u in Us])
+    vp = (P * n)(*[v.data_ptr() for v in Vs])
+    zp = (P * n)(*[z.data_ptr() for z in Zs])
+    ranks = (c_int64 * n)()
+    stats = (SolveStats * n)()
+    sts = (c_int32 * n)()
+    torch.cuda.synchronize()
+    _check(L.cr_greedy_solve_batch(n, hs, opts, up, vp, zp, ranks, stats, sts))
+    out = []
+    for k in range(n):
+        r = ranks[k]
+        out.append(dict(U=Us[k][:, :r], V=Vs[k][:, :r], Z=Zs[k][:r, :r], rank=r,
+                        stats={f: getattr(stats[k], f) for f, _ in SolveStats._fields_},
+                        status=STATUS_NAMES.get(sts[k], sts[k])))
+    return out

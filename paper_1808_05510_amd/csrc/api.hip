@@ -4,12 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <string>
 #include <type_traits>
 #include <utility>
@@ -51,6 +53,9 @@ struct cr_problem {
   unsigned* bar = nullptr;  // grid-barrier words: [0] generation, [64] timeout, [128] arrivals
   cr_pc* pc = nullptr;      // learned preconditioner for the u-systems (not owned)
   int64_t pc_fallbacks = 0;
+  int cu_share = 0;         // > 0: persistent grids limited to this many CUs' worth of slots
+  int coop = 1;             // persistent kernels launched cooperatively
+  int tuned_vpt_u = 0, tuned_vpt_v = 0;  // autotuned PCG voxels per thread (0 = heuristic)
   int bar_mode = 1;
   std::map<std::string, DevBuf> ws;
   std::vector<void*> owned;
@@ -190,6 +195,21 @@ __global__ void k_neg(int n, const double* __restrict__ a, double* __restrict__ 
 
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
+static int device_cus() {
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return ncu;
+}
+
+// workgroups of a kernel whose whole-device resident capacity is maxwg that
+// fit in `share` CUs
+static int share_cap(int maxwg, int share) {
+  const int ncu = std::max(1, device_cus());
+  return std::max(1, (int)((int64_t)maxwg * share / ncu));
+}
+
 // q = lam*(L t + c1 t + c0 p) + d o p with t = L p (runtime stencil width)
 __global__ void k_uapply(int64_t n, int K, const int32_t* __restrict__ nbr, double lam,
                          const double* __restrict__ coef, const double* __restrict__ d,
@@ -297,15 +317,18 @@ struct Ctx {
     // grows faster than the grid barrier (3 us at 64, 8 us at 256 groups)
     // shrinks.
     auto pick = [&](const Geom& g, const T* Xm, int& vpt, int& nwg) -> bool {
+      const int tuned = Xm ? P->tuned_vpt_v : P->tuned_vpt_u;
+      const int want = vpt_opt > 0 ? vpt_opt : tuned;
       for (int v = 1; v <= 8; v *= 2) {
-        if (vpt_opt > 0 && v != vpt_opt) continue;
+        if (want > 0 && v < want) continue;
         PcgArgs<T> probe{};
         probe.g = g;
         probe.Xm = Xm;
         probe.vpt = v;
-        const int maxwg = pcg_max_wg<T>(probe);
+        int maxwg = pcg_max_wg<T>(probe);
+        if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
         const int64_t w = std::max<int64_t>(1, (g.n + (int64_t)NT * v - 1) / ((int64_t)NT * v));
-        if (maxwg > 0 && w <= maxwg && (w <= 512 || vpt_opt > 0 || v == 8)) {
+        if (maxwg > 0 && w <= maxwg && (w <= 512 || want > 0 || v == 8)) {
           vpt = v;
           nwg = (int)w;
           return true;
@@ -468,6 +491,7 @@ struct Ctx {
     a.vpt = usys ? pcg_vpt_u : pcg_vpt_v;
     a.bar.bar = P->bar;
     a.bar.mode = P->bar_mode;
+    a.bar.coop = P->coop;
     return pcg_solve<T>(a, usys ? pcg_nwg_u : pcg_nwg_v, st);
   }
 
@@ -838,13 +862,15 @@ struct Ctx {
       set_error("cooperative launch not available for the Galerkin kernel");
       return CR_EHIP;
     }
-    const int nwg = std::max(1, std::min(maxwg, std::max(ninj, r)));
+    int nwg = std::max(1, std::min(maxwg, std::max(ninj, r)));
+    if (P->cu_share > 0) nwg = std::max(1, std::min(nwg, share_cap(maxwg, P->cu_share)));
     a.part = WS(double, "galpart", 6 * nwg);
     a.scal = sc + 8;
     a.rtol = rtol;
     a.maxit = maxit;
     a.bar.bar = P->bar;
     a.bar.mode = P->bar_mode;
+    a.bar.coop = P->coop;
     CR_TRY(galerkin_cg(a, nwg, st));
     return read_scalars(sc + 8, 4, scal4);
   }
@@ -1674,4 +1700,211 @@ extern "C" cr_status cr_pc_train_step(cr_pc* pc, cr_problem* P, int32_t batch, c
   CR_HIP(hipStreamSynchronize(st));
   if (loss_out) *loss_out = total / batch;
   return std::isfinite(total) ? CR_OK : CR_ENONFINITE;
+}
+
+// ===================================================================== masked Grams
+extern "C" cr_status cr_masked_gram(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                    int32_t mode, double* G, int64_t ldg) {
+  if (!P || r <= 0 || !U || !G || ldu < P->ny || ldg < r || (mode != 0 && mode != 1)) {
+    set_error("invalid arguments to cr_masked_gram");
+    return CR_EINVAL;
+  }
+  if (mode == 1) {
+    float* part = P->buf<float>("krpart", kr_gram_part_size(P->ny, (int)r, P->ninj));
+    if (!part) return CR_ENOMEM;
+    return kr_gram_bf16<double>(P->ny, (int)r, P->ninj, U, ldu, P->bits, G, ldg, part, P->st);
+  }
+  Ctx<double> c(P);
+  CR_TRY(c.alloc_rank((int)r));
+  CR_TRY(c.alloc_vectors(0));
+  c.U = const_cast<double*>(U);
+  c.ldu = ldu;
+  c.G = G;
+  for (int j = 0; j < (int)r; ++j) CR_TRY(c.gram_column(j, ldg));
+  return CR_OK;
+}
+
+// ===================================================================== batched solves, autotuning
+// does every persistent PCG grid of problem P fit in `share` CUs?
+template <typename T>
+static bool fits_share_t(cr_problem* P, int share) {
+  for (int sys = 0; sys < 2; ++sys) {
+    const Geom& g = sys ? P->gx : P->gy;
+    bool ok = false;
+    for (int v = 1; v <= 8 && !ok; v *= 2) {
+      PcgArgs<T> probe{};
+      probe.g = g;
+      probe.Xm = sys ? P->X<T>() : nullptr;
+      probe.vpt = v;
+      const int m = pcg_max_wg<T>(probe);
+      const int64_t w = (g.n + (int64_t)NT * v - 1) / ((int64_t)NT * v);
+      ok = m > 0 && w <= share_cap(m, share);
+    }
+    if (!ok) return false;
+  }
+  return true;
+}
+
+static bool fits_share(cr_problem* P, int share) {
+  return P->prec == CR_PREC_MIXED ? fits_share_t<float>(P, share)
+                                  : fits_share_t<double>(P, share);
+}
+
+extern "C" cr_status cr_greedy_solve_batch(int32_t count, cr_problem** probs,
+                                           const cr_solve_opts* opts, double** U, double** V,
+                                           double** Z, int64_t* ranks, cr_solve_stats* stats,
+                                           int32_t* statuses) {
+  if (count <= 0 || !probs || !opts || !U || !V || !Z || !ranks || !statuses) {
+    set_error("invalid arguments to cr_greedy_solve_batch");
+    return CR_EINVAL;
+  }
+  for (int k = 0; k < count; ++k)
+    for (int l = 0; l < k; ++l)
+      if (!probs[k] || probs[k] == probs[l] || probs[k]->st == probs[l]->st) {
+        set_error("batched problems need distinct handles on distinct streams");
+        return CR_EINVAL;
+      }
+  int dev = 0;
+  CR_HIP(hipGetDevice(&dev));
+  const int ncu = device_cus();
+  // the most problems that can run at once: each of K workers owns 3/4 of
+  // 1/K of the CUs (a margin for packing losses) and every grid must fit
+  int K = std::min(count, 16);
+  for (; K > 1; --K) {
+    const int share = std::max(1, 3 * ncu / (4 * K));
+    bool all = true;
+    for (int k = 0; k < count && all; ++k) all = fits_share(probs[k], share);
+    if (all) break;
+  }
+  const int share = K > 1 ? std::max(1, 3 * ncu / (4 * K)) : 0;
+  // largest problems first
+  std::vector<int> order(count);
+  for (int k = 0; k < count; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(),
+            [&](int a, int b) { return probs[a]->ny > probs[b]->ny; });
+  std::vector<int> saved_cap(count), saved_coop(count), saved_mode(count);
+  for (int k = 0; k < count; ++k) {
+    saved_cap[k] = probs[k]->cu_share;
+    saved_coop[k] = probs[k]->coop;
+    saved_mode[k] = probs[k]->bar_mode;
+    probs[k]->cu_share = share;
+    probs[k]->coop = K > 1 ? 0 : 1;
+    probs[k]->bar_mode = 1;
+  }
+  std::vector<std::string> errs(count);
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (int w = 0; w < K; ++w)
+    th.emplace_back([&]() {
+      (void)hipSetDevice(dev);
+      for (int q = next++; q < count; q = next++) {
+        const int k = order[q];
+        cr_problem* P = probs[k];
+        cr_status s = P->prec == CR_PREC_MIXED
+                          ? greedy_impl<float>(P, opts[k], U[k], V[k], Z[k], &ranks[k],
+                                               stats ? &stats[k] : nullptr, nullptr, nullptr)
+                          : greedy_impl<double>(P, opts[k], U[k], V[k], Z[k], &ranks[k],
+                                                stats ? &stats[k] : nullptr, nullptr, nullptr);
+        statuses[k] = s;
+        if (s < 0) errs[k] = cr_last_error();
+      }
+    });
+  for (auto& t : th) t.join();
+  cr_status worst = CR_OK;
+  for (int k = 0; k < count; ++k) {
+    probs[k]->cu_share = saved_cap[k];
+    probs[k]->coop = saved_coop[k];
+    probs[k]->bar_mode = saved_mode[k];
+    if (statuses[k] < 0 && worst == CR_OK) {
+      worst = (cr_status)statuses[k];
+      set_error("problem " + std::to_string(k) + ": " + errs[k]);
+    }
+  }
+  return worst;
+}
+
+// Autotuner: times 60 Jacobi-PCG iterations of a representative u- and
+// v-system for each admissible voxels-per-thread (1, 2, 4, 8) within the
+// handle's current workgroup cap and keeps the fastest for later solves.
+extern "C" cr_status cr_autotune_pcg(cr_problem* P, int32_t cu_share, int32_t* vpt_u,
+                                     int32_t* vpt_v, double* us_u, double* us_v) {
+  if (!P || P->prec != CR_PREC_FP64) {
+    set_error("cr_autotune_pcg needs an FP64 handle");
+    return CR_EINVAL;
+  }
+  const int saved = P->cu_share;
+  P->cu_share = cu_share > 0 ? cu_share : saved;
+  cr_status status = CR_OK;
+  double best[2] = {1e300, 1e300};
+  int bestv[2] = {0, 0};
+  hipEvent_t e0, e1;
+  CR_HIP(hipEventCreate(&e0));
+  CR_HIP(hipEventCreate(&e1));
+  for (int v = 1; v <= 8 && status == CR_OK; v *= 2) {
+    Ctx<double> c(P);
+    status = c.alloc_rank(1);
+    if (status != CR_OK) break;
+    status = c.alloc_vectors(v);
+    if (status != CR_OK) {  // this grid shape does not fit the cap
+      status = CR_OK;
+      continue;
+    }
+    // representative systems: d = 1 + |q|, unit coefficients, rhs = q
+    double hc[2] = {1.0, 0.5};
+    CR_HIP(hipMemcpyAsync(c.cu, hc, sizeof(hc), hipMemcpyHostToDevice, c.st));
+    CR_HIP(hipMemcpyAsync(c.cv, hc, sizeof(hc), hipMemcpyHostToDevice, c.st));
+    CR_TRY(splitmix_fill<double>(c.ny, 7, 1, c.rhs_u, c.st));
+    CR_TRY(splitmix_fill<double>(c.nx, 7, 2, c.rhs_v, c.st));
+    CR_TRY(splitmix_fill<double>(c.ny, 7, 3, c.dvec, c.st));
+    std::vector<double> ones(c.ninj, 1.0);
+    CR_HIP(hipMemcpyAsync(c.gw, ones.data(), sizeof(double) * c.ninj, hipMemcpyHostToDevice, c.st));
+    CR_TRY(pcg_diag<double>(P->gy, c.lam, c.cu, c.dvec, nullptr, 0, 0, nullptr, c.minv_u, c.st));
+    CR_TRY(pcg_diag<double>(P->gx, c.lam, c.cv, nullptr, c.X(), c.nx, c.ninj, c.gw, c.minv_v, c.st));
+    for (int sys = 0; sys < 2; ++sys) {
+      const bool us = sys == 0;
+      double t = 0.0;
+      for (int rep = 0; rep < 3; ++rep) {
+        CR_HIP(hipEventRecord(e0, c.st));
+        CR_TRY(c.pcg(us, us ? c.rhs_u : c.rhs_v, us ? c.vu : c.vv, 1e-300, 60, c.sc));
+        CR_HIP(hipEventRecord(e1, c.st));
+        CR_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        double h[4];
+        CR_TRY(c.read_scalars(c.sc, 4, h));
+        const double per = 1e3 * ms / std::max(1.0, h[2]);
+        if (rep > 0) t = rep == 1 ? per : std::min(t, per);
+      }
+      if (t < best[sys]) {
+        best[sys] = t;
+        bestv[sys] = v;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->cu_share = saved;
+  if (status != CR_OK) return status;
+  P->tuned_vpt_u = bestv[0];
+  P->tuned_vpt_v = bestv[1];
+  if (vpt_u) *vpt_u = bestv[0];
+  if (vpt_v) *vpt_v = bestv[1];
+  if (us_u) *us_u = best[0];
+  if (us_v) *us_v = best[1];
+  return CR_OK;
+}
+
+extern "C" cr_status cr_problem_set_tuning(cr_problem* P, int32_t vpt_u, int32_t vpt_v) {
+  if (!P) {
+    set_error("null handle");
+    return CR_EINVAL;
+  }
+  for (int v : {vpt_u, vpt_v})
+    if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) {
+      set_error("voxels per thread must be 0, 1, 2, 4 or 8");
+      return CR_EINVAL;
+    }
+  P->tuned_vpt_u = vpt_u;
+  P->tuned_vpt_v = vpt_v;
+  return CR_OK;
 }

@@ -132,6 +132,8 @@ cr_status convert2d(int64_t rows, int64_t cols, const Ts* src, int64_t lds, Td* 
 struct BarrierArg {
   unsigned* bar = nullptr;  // 192 device words, zeroed before each launch
   int mode = 1;             // 0: cooperative-groups grid sync, 1: atomic barrier
+  int coop = 1;             // 1: cooperative launch; 0: ordinary launch (mode 1 only, for
+                            // concurrent persistent kernels that together fit on the device)
 };
 
 template <typename T>
@@ -231,6 +233,12 @@ int64_t lpc_loss_scratch(const LpcNet& net);
 cr_status lpc_loss(const LpcNet& net, const float* in0, const float* y, const double* xs,
                    float* dy, double* scratch, hipStream_t st);
 cr_status lpc_adam(LpcNet& net, float lr, float scale, hipStream_t st);
+
+// ---------------------------------------------------------------- BF16 Khatri-Rao Grams
+int64_t kr_gram_part_size(int64_t n, int r, int ninj);
+template <typename TU>
+cr_status kr_gram_bf16(int64_t n, int r, int ninj, const TU* U, int64_t ldu, const uint32_t* bits,
+                       double* G, int64_t ldr, float* part, hipStream_t st);
 
 // ---------------------------------------------------------------- small ops
 // out[i] = sum_k M[i + k*ldm] * v[k] * alpha  (i < m, k < kk), single block

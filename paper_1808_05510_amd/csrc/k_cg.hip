@@ -399,7 +399,10 @@ cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
   PcgArgs<T> arg = a;
   if (arg.bar.mode == 1) CR_HIP(hipMemsetAsync(arg.bar.bar, 0, BAR_WORDS * sizeof(unsigned), st));
   void* params[] = {&arg};
-  CR_HIP(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(NT), params, 0, st));
+  if (arg.bar.coop || arg.bar.mode == 0)
+    CR_HIP(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(NT), params, 0, st));
+  else
+    CR_HIP(hipLaunchKernel(fn, dim3(nwg), dim3(NT), params, 0, st));
   return CR_OK;
 }
 
@@ -620,7 +623,10 @@ cr_status galerkin_cg(const GalerkinArgs& a, int nwg, hipStream_t st) {
   GalerkinArgs arg = a;
   if (arg.bar.mode == 1) CR_HIP(hipMemsetAsync(arg.bar.bar, 0, BAR_WORDS * sizeof(unsigned), st));
   void* params[] = {&arg};
-  CR_HIP(hipLaunchCooperativeKernel((void*)k_galerkin, dim3(nwg), dim3(NT), params,
+  if (!arg.bar.coop && arg.bar.mode == 1)
+    CR_HIP(hipLaunchKernel((void*)k_galerkin, dim3(nwg), dim3(NT), params, sizeof(double) * a.r, st));
+  else
+    CR_HIP(hipLaunchCooperativeKernel((void*)k_galerkin, dim3(nwg), dim3(NT), params,
                                     sizeof(double) * a.r, st));
   return CR_OK;
 }

@@ -231,3 +231,19 @@ def test_invalid_arguments_are_rejected():
     bad["Ly_val"] = d["Ly_val"] * 2.0  # not a graph Laplacian
     with pytest.raises(connreg.ConnRegError):
         connreg.Problem(bad, "fp64", DEV)
+
+
+# ------------------------------------------------------------------ masked Grams
+@pytest.mark.parametrize("r", [1, 17, 70])
+def test_masked_gram_fp64_and_bf16(case, r):
+    name, d, P = case
+    r = min(r, P.n_x)
+    rng = np.random.default_rng(31 + r)
+    U = rand_orth(rng, P.n_y, r)
+    g = connreg.Problem(d, "fp64", DEV)
+    ref = np.stack([U.T @ (P.Omega[:, a][:, None] * U) for a in range(P.n_inj)])
+    G64 = np_(g.masked_gram(U, "fp64"))
+    assert rel(G64, ref) < 1e-13
+    Gbf = np_(g.masked_gram(U, "bf16"))
+    # entry bound: 2^-8 ||U_a|| ||U_b|| (orthonormal columns: 2^-8) + FP32 accumulation
+    assert np.abs(Gbf - ref).max() <= 2.0 ** -8 + 1e-5
