@@ -34,6 +34,9 @@ struct DevBuf {
 
 struct cr_problem {
   hipStream_t st = nullptr;
+  hipStream_t aux = nullptr;  // library-owned second stream (default priority) for fork/join
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool op_fork = true;  // op_apply's data term on the auxiliary stream (CONNREG_OP_FORK=0: serial)
   cr_precision prec = CR_PREC_FP64;
   int64_t ny = 0, nx = 0;
   int ninj = 0;
@@ -1020,6 +1023,10 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
                              cr_problem* P) {
   P->st = (hipStream_t)stream;
   P->prec = prec;
+  CR_HIP(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
+  CR_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+  CR_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+  if (const char* e = std::getenv("CONNREG_OP_FORK")) P->op_fork = std::atoi(e) != 0;
   P->ny = d->Ly.n;
   P->nx = d->Lx.n;
   P->ninj = (int)d->n_inj;
@@ -1156,6 +1163,12 @@ extern "C" void cr_problem_destroy(cr_problem* P) {
   if (P->gx.nbr) (void)hipFree(P->gx.nbr);
   if (P->gx.deg) (void)hipFree(P->gx.deg);
   if (P->hscal) (void)hipHostFree(P->hscal);
+  if (P->aux) {
+    (void)hipStreamSynchronize(P->aux);
+    (void)hipStreamDestroy(P->aux);
+  }
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   delete P;
 }
 
@@ -1207,26 +1220,43 @@ static cr_status op_apply_impl(cr_problem* P, int64_t r, const T* U, int64_t ldu
   }
   hipStream_t st = P->st;
   const int rr = (int)r;
-  CR_TRY(stencil<T>(P->gy, rr, U, ldu, F, ldf, st));
-  CR_TRY(stencil<T>(P->gy, rr, F, ldf, F + r * ldf, ldf, st));
-  CR_TRY(stencil<T>(P->gx, rr, V, ldv, G, ldg, st));
-  CR_TRY(stencil<T>(P->gx, rr, G, ldg, G + r * ldg, ldg, st));
+  // workspace first (allocation may synchronise), then fork: the data term
+  // (H^T = X^T V, T = Z H, the masked product, MFMA-heavy) runs on the
+  // auxiliary stream while the four stencil sweeps (gather-heavy) run on the
+  // caller's stream; the caller's stream then waits for both.
   double* Tm = WS(double, "Tm_op", std::max<int64_t>(r, 1) * ninj);
-  if (r > 0) {
-    double* Ht = WS(double, "Ht_op", (int64_t)ninj * r);
-    double* Zd = WS(double, "Zd_op", r * r);
-    double* gpart = WS(double, "gpart", gemm_part_cap(P));
-    Blocks<T> A, B;
-    A.clear();
-    B.clear();
-    A.add(P->X<T>(), nx, ninj);
-    B.add(V, ldv, rr);
-    CR_TRY(gemm_tn<T>(nx, A, B, nullptr, nullptr, 0, Ht, ninj, gpart, gemm_part_cap(P), st));
-    CR_TRY((convert2d<double, T>(r, r, Z, ldz, Zd, r, st)));
-    CR_TRY(small_gemm(rr, ninj, rr, Zd, r, false, Ht, ninj, true, 1.0, Tm, r, st));
+  double* Ht = WS(double, "Ht_op", (int64_t)ninj * std::max<int64_t>(r, 1));
+  double* Zd = WS(double, "Zd_op", std::max<int64_t>(r * r, 1));
+  double* gpart = WS(double, "gpart", gemm_part_cap(P));
+  CR_HIP(hipEventRecord(P->ev_fork, st));
+  CR_HIP(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
+  auto data_term = [&]() -> cr_status {
+    hipStream_t as = P->op_fork ? P->aux : st;
+    if (r > 0) {
+      Blocks<T> A, B;
+      A.clear();
+      B.clear();
+      A.add(P->X<T>(), nx, ninj);
+      B.add(V, ldv, rr);
+      CR_TRY(gemm_tn<T>(nx, A, B, nullptr, nullptr, 0, Ht, ninj, gpart, gemm_part_cap(P), as));
+      CR_TRY((convert2d<double, T>(r, r, Z, ldz, Zd, r, as)));
+      CR_TRY(small_gemm(rr, ninj, rr, Zd, r, false, Ht, ninj, true, 1.0, Tm, r, as));
+    }
+    return masked_tall_gemm<T>(ny, rr, ninj, U, ldu, Tm, std::max<int64_t>(r, 1), P->bits,
+                               (const T*)nullptr, 0, F + 2 * r * ldf, ldf, as);
+  };
+  const cr_status sd = data_term();
+  cr_status ss = CR_OK;
+  if (sd == CR_OK) {
+    ss = stencil<T>(P->gy, rr, U, ldu, F, ldf, st);
+    if (ss == CR_OK) ss = stencil<T>(P->gy, rr, F, ldf, F + r * ldf, ldf, st);
+    if (ss == CR_OK) ss = stencil<T>(P->gx, rr, V, ldv, G, ldg, st);
+    if (ss == CR_OK) ss = stencil<T>(P->gx, rr, G, ldg, G + r * ldg, ldg, st);
   }
-  return masked_tall_gemm<T>(ny, rr, ninj, U, ldu, Tm, std::max<int64_t>(r, 1), P->bits,
-                             (const T*)nullptr, 0, F + 2 * r * ldf, ldf, st);
+  // always join, so that nothing the caller's stream owns is left in flight
+  CR_HIP(hipEventRecord(P->ev_join, P->aux));
+  CR_HIP(hipStreamWaitEvent(st, P->ev_join, 0));
+  return sd != CR_OK ? sd : ss;
 }
 
 extern "C" cr_status cr_op_apply(cr_problem* P, int64_t r, const double* U, int64_t ldu,

@@ -325,6 +325,82 @@ __global__ __launch_bounds__(NT) void k_gemm_tn(int64_t n, Blocks<T> A, Blocks<T
       }
 }
 
+// C = A^T B for p, q <= 128 (e.g. H^T = X^T V): every workgroup computes the
+// whole p x q product over its slab of rows, so A and B are each read once
+// (a grid of 64 x 64 tiles would read every A tile once per B tile).  Rows are
+// staged through LDS in chunks of 16 with the next chunk's loads in flight;
+// wave wv owns output rows 32 wv .. 32 wv + 31 against all column tiles
+// (16 FP64 MFMA accumulators).  Split-K partials go to `part` as in k_gemm_tn.
+constexpr int GW_KC = 32, GW_LD = 144, GW_NT = 512;
+
+template <typename T>
+__global__ __launch_bounds__(GW_NT) void k_gemm_tn_wide(int64_t n, Blocks<T> A, Blocks<T> B, int p,
+                                                        int q, int64_t kchunk,
+                                                        double* __restrict__ part) {
+  __shared__ double As[GW_KC][GW_LD];
+  __shared__ double Bs[GW_KC][GW_LD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;  // 8 waves
+  const int fr = lane & 15, fk = lane >> 4;
+  const int64_t k0 = (int64_t)blockIdx.x * kchunk;
+  const int64_t k1 = min(n, k0 + kchunk);
+  // loader: element e = tid + 512 m (m < 16): row e % 32, column e / 32 of the
+  // concatenation [A (128 columns) | B (128 columns)]; a column's 32 rows are
+  // one 256-byte segment
+  const int lrow = tid % GW_KC;
+  const int lc0 = tid / GW_KC;  // 0..15
+  const T* src[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int c = lc0 + 16 * m;  // 0..255
+    src[m] = c < 128 ? (c < p ? A.col(c) : nullptr) : (c - 128 < q ? B.col(c - 128) : nullptr);
+  }
+  T rg[16];
+  auto load = [&](int64_t kb) {
+    const int64_t row = kb + lrow;
+    const bool in = row < k1;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) rg[m] = (in && src[m]) ? src[m][row] : (T)0;
+  };
+  dbl4 acc[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) acc[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int ntq = (q + 15) / 16;
+  const bool rows_live = 16 * wv < p;
+  if (k0 < k1) load(k0);
+  for (int64_t kb = k0; kb < k1; kb += GW_KC) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int c = lc0 + 16 * m;
+      if (c < 128)
+        As[lrow][c] = (double)rg[m];
+      else
+        Bs[lrow][c - 128] = (double)rg[m];
+    }
+    __syncthreads();
+    if (kb + GW_KC < k1) load(kb + GW_KC);
+    if (rows_live) {
+#pragma unroll
+      for (int kk = 0; kk < GW_KC; kk += 4) {
+        const double av = As[kk + fk][16 * wv + fr];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          if (b < ntq) acc[b] = mfma64(av, Bs[kk + fk][16 * b + fr], acc[b]);
+      }
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.x * p * q;
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * wv + fk + 4 * e;
+      const int j = 16 * b + fr;
+      if (i < p && j < q) out[(int64_t)j * p + i] = acc[b][e];
+    }
+}
+
 // C = sum over the ks split partials; 64 outputs per workgroup, the four
 // waves sum interleaved quarters of the splits, then combine in a fixed order.
 __global__ __launch_bounds__(NT) void k_reduce_split(int p, int q, int ks,
@@ -362,6 +438,28 @@ cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint3
     CR_HIP(hipMemset2DAsync(C, ldc * sizeof(double), 0, p * sizeof(double), q, st));
     return CR_OK;
   }
+  if (sizeof(T) == 4 && !mask_bits && p <= 128 && q <= 128) {
+    // FP32 operands: one slab of at least 512 rows per workgroup, at most about
+    // 512 slabs (measured faster than the 64 x 64 tiles below for FP32 data,
+    // slower for FP64 data, whose tiled form keeps more loads in flight)
+    int64_t ks = std::max<int64_t>(1, std::min<int64_t>(512, n / 512));
+    while (ks > 1 && ks * (int64_t)p * q > part_cap) --ks;
+    if (ks * (int64_t)p * q > part_cap) {
+      set_error("gemm_tn workspace too small");
+      return CR_EINVAL;
+    }
+    int64_t kchunk = (n + ks - 1) / ks;
+    kchunk = (kchunk + GW_KC - 1) / GW_KC * GW_KC;
+    ks = std::max<int64_t>(1, (n + kchunk - 1) / kchunk);
+    hipLaunchKernelGGL((k_gemm_tn_wide<T>), dim3((unsigned)ks), dim3(GW_NT), 0, st, n, A, B, p, q,
+                       kchunk, part);
+    CR_HIP(hipGetLastError());
+    const int64_t pq = (int64_t)p * q;
+    hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((pq + WAVE - 1) / WAVE)), dim3(NT), 0, st,
+                       p, q, (int)ks, part, C, ldc);
+    CR_HIP(hipGetLastError());
+    return CR_OK;
+  }
   const int tiles = ((p + TM - 1) / TM) * ((q + TM - 1) / TM);
   // about 512 workgroups, each at least 16 LDS chunks deep
   int64_t ks = std::max<int64_t>(1, 512 / tiles);
@@ -390,78 +488,206 @@ cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint3
 }
 
 // ============================================================== masked tall GEMM
-// N[i,a] = OY[i,a] - omega_ia * sum_k U[i,k] T[k,a]   (or +omega*UT when OY null)
-// computed transposed, N^T = T^T U^T, with FP64 MFMA: in the result layout
-// each group of 16 lanes then holds 16 consecutive voxels of one injection,
-// so the mask, OY reads and N writes are coalesced.  Workgroup: 128 voxels x
-// 64 injections; wave wv owns voxels 32 wv .. 32 wv + 31 (two 16-wide MFMA
-// columns) and all 64 injections (four 16-high MFMA rows).  T^T is staged
-// through LDS in chunks of 32 k; U fragments are read straight from memory
-// (16 consecutive voxels per 16 lanes).  Voxel blocks are remapped per XCD.
-constexpr int MG_ROWS = 128, MG_COLS = 64, MG_KC = 32;
+// N[i,a] = OY[i,a] - omega_ia (U T)[i,a]   (or + omega (U T) when OY is null)
+// computed transposed on the matrix cores, N^T = T^T U^T, with injections as
+// MFMA rows and voxels as MFMA columns: each group of 16 lanes then holds 16
+// consecutive voxels of one injection, so the mask, OY reads and N writes are
+// coalesced.  Workgroup: 128 voxels x up to 128 injections (every injection
+// tile in one pass, so U is read once); wave wv owns voxels 32 wv .. 32 wv + 31
+// (two 16-wide column tiles) and all injection tiles.  T^T is staged through
+// LDS in chunks of 32 k; the U fragments of the next chunk are in flight while
+// the current chunk's MFMAs run.  FP64 operands use v_mfma_f64_16x16x4f64,
+// FP32 operands v_mfma_f32_16x16x4f32 (FP32 accumulation).  Voxel blocks are
+// remapped per XCD.
+typedef float flt4v __attribute__((ext_vector_type(4)));
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_masked_tall_gemm(
+struct Mfma16;
+template <>
+struct Mfma16<double> {
+  typedef dbl4 acc_t;
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // result element e of a lane in lane group fk (= lane / 16) sits in row:
+  __device__ static int row(int fk, int e) { return fk + 4 * e; }
+};
+template <>
+struct Mfma16<float> {
+  typedef flt4v acc_t;
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int fk, int e) { return 4 * fk + e; }
+};
+
+constexpr int MG_ROWS = 64, MG_COLS = 128, MG_KC = 32, MG_LD = 144;
+
+// NTA = injection tiles of 16 per workgroup (1, 2, 4 or 8): the smallest that
+// covers min(n_inj, 128), so that no MFMA sits behind a run-time condition.
+template <typename T, int NTA>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_masked_tall_gemm(
     int64_t n, int r, int ninj, const T* __restrict__ U, int64_t ldu, const double* __restrict__ Tm,
     int64_t ldt, const uint32_t* __restrict__ bits, const T* __restrict__ OY, int64_t ldoy,
     T* __restrict__ N, int64_t ldn, unsigned nb_log) {
-  __shared__ double Ts[MG_KC][MG_COLS + 1];  // Ts[k][a] = T[k0 + k, a0 + a]
+  typedef typename Mfma16<T>::acc_t acc_t;
+  constexpr int NC = 16 * NTA;    // injection columns staged per chunk
+  __shared__ T Ts[MG_KC][MG_LD];  // Ts[k][a] = T[k0 + k, a0 + a]; row stride 16 mod 64 banks
   const int64_t lb = xcd_block(blockIdx.x, nb_log);
   if (lb >= nb_log) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fr = lane & 15, fk = lane >> 4;
   const int a0 = blockIdx.y * MG_COLS;
-  const int64_t v0 = lb * MG_ROWS + 32 * wv;  // first voxel of this wave
-  dbl4 acc[4][2];
+  const int na = min(NC, ninj - a0);
+  const int64_t v0 = lb * MG_ROWS + 16 * wv;  // the 16 voxels of this wave
+  acc_t acc[NTA];
 #pragma unroll
-  for (int ta = 0; ta < 4; ++ta)
-#pragma unroll
-    for (int tv = 0; tv < 2; ++tv) acc[ta][tv] = dbl4{0.0, 0.0, 0.0, 0.0};
-  const int64_t vrow0 = v0 + fr, vrow1 = v0 + 16 + fr;
-  const bool ok0 = vrow0 < n, ok1 = vrow1 < n;
-  for (int k0 = 0; k0 < r; k0 += MG_KC) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < MG_KC * MG_COLS; e += NT) {
-      const int kk = e % MG_KC, cc = e / MG_KC;
-      const int k = k0 + kk, al = a0 + cc;
-      Ts[kk][cc] = (k < r && al < ninj) ? Tm[(int64_t)al * ldt + k] : 0.0;
-    }
-    __syncthreads();
-    double b0[MG_KC / 4], b1[MG_KC / 4];
+  for (int ta = 0; ta < NTA; ++ta) acc[ta] = acc_t{0, 0, 0, 0};
+  const int64_t vrow = v0 + fr;
+  const bool ok = vrow < n;
+  const int64_t vcl = ok ? vrow : n - 1;  // clamped, so every load below is in bounds
+  T b0[MG_KC / 4], n0[MG_KC / 4];
+  auto loadB = [&](int k0, T* x0) {
 #pragma unroll
     for (int s4 = 0; s4 < MG_KC / 4; ++s4) {
       const int k = k0 + 4 * s4 + fk;
-      const bool kin = k < r;
-      b0[s4] = (kin && ok0) ? (double)U[(int64_t)k * ldu + vrow0] : 0.0;
-      b1[s4] = (kin && ok1) ? (double)U[(int64_t)k * ldu + vrow1] : 0.0;
+      const T v = U[(int64_t)min(k, r - 1) * ldu + vcl];
+      x0[s4] = (k < r && ok) ? v : (T)0;
     }
+  };
+  if (r > 0) loadB(0, b0);
+  for (int k0 = 0; k0 < r; k0 += MG_KC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < MG_KC * NC; e += NT) {
+      const int kk = e % MG_KC, cc = e / MG_KC;
+      const int k = k0 + kk, al = a0 + cc;
+      Ts[kk][cc] = (k < r && al < ninj) ? (T)Tm[(int64_t)al * ldt + k] : (T)0;
+    }
+    __syncthreads();
+    const bool more = k0 + MG_KC < r;
+    if (more) loadB(k0 + MG_KC, n0);
 #pragma unroll
     for (int s4 = 0; s4 < MG_KC / 4; ++s4) {
 #pragma unroll
-      for (int ta = 0; ta < 4; ++ta) {
-        const double av = Ts[4 * s4 + fk][16 * ta + fr];
-        acc[ta][0] = mfma64(av, b0[s4], acc[ta][0]);
-        acc[ta][1] = mfma64(av, b1[s4], acc[ta][1]);
+      for (int ta = 0; ta < NTA; ++ta)
+        acc[ta] = Mfma16<T>::mma(Ts[4 * s4 + fk][16 * ta + fr], b0[s4], acc[ta]);
+    }
+    if (more) {
+#pragma unroll
+      for (int s4 = 0; s4 < MG_KC / 4; ++s4) b0[s4] = n0[s4];
+    }
+  }
+  // epilogue: element e of lane l is (injection 16 ta + row(fk, e), voxel fr)
+  if (!ok) return;
+  uint32_t wd[(NC + 31) / 32];
+#pragma unroll
+  for (int q = 0; q < (NC + 31) / 32; ++q)
+    wd[q] = (32 * q < na) ? bits[(int64_t)((a0 >> 5) + q) * n + vrow] : 0u;
+#pragma unroll
+  for (int ta = 0; ta < NTA; ++ta) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int al_loc = 16 * ta + Mfma16<T>::row(fk, e);
+      if (al_loc < na) {
+        const int64_t al = a0 + al_loc;
+        // 16 ta <= al_loc < 16 ta + 16, so the mask word is wd[ta / 2]
+        const T om = (T)((wd[ta >> 1] >> (al_loc & 31)) & 1u);
+        const T v = om * acc[ta][e];
+        N[al * ldn + vrow] = OY ? OY[al * ldoy + vrow] - v : v;
       }
     }
   }
-  // epilogue: element e of lane l is (injection 16 ta + fk + 4 e, voxel 16 tv + fr)
+}
+
+// Register-resident variant for r <= 112: wave w of a workgroup owns
+// injection tiles 2w, 2w + 1 (32 injections) and keeps their T^T fragments for
+// every k in registers, loaded once; the workgroup then walks 16-voxel tiles
+// (grid-stride), each wave streaming the tile's U fragments (the next tile's
+// are in flight while the current tile's MFMAs run).  No LDS, no barriers: T
+// is read once per workgroup instead of once per voxel tile, and the MFMA
+// chain of a tile is 2 KS back-to-back instructions.  KS = k steps of 4
+// (r <= 4 KS); the mask word of a wave's 32 injections is a single bits word.
+template <typename T, int KS>
+__global__ __launch_bounds__(NT) void k_masked_gemm_rt(
+    int64_t n, int r, int ninj, const T* __restrict__ U, int64_t ldu, const double* __restrict__ Tm,
+    int64_t ldt, const uint32_t* __restrict__ bits, const T* __restrict__ OY, int64_t ldoy,
+    T* __restrict__ N, int64_t ldn) {
+  typedef typename Mfma16<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  const int a0 = blockIdx.y * MG_COLS + 32 * wv;  // first injection of this wave
+  if (a0 >= ninj) return;                         // whole wave idle (no barriers below)
+  T a[2][KS];
 #pragma unroll
-  for (int tv = 0; tv < 2; ++tv) {
-    const int64_t i = v0 + 16 * tv + fr;
-    if (i >= n) continue;
+  for (int t = 0; t < 2; ++t) {
+    const int al = a0 + 16 * t + fr;
 #pragma unroll
-    for (int ta = 0; ta < 4; ++ta)
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + fk;
+      a[t][ks] = (k < r && al < ninj) ? (T)Tm[(int64_t)al * ldt + k] : (T)0;
+    }
+  }
+  const int64_t ntile = (n + 15) / 16;
+  const int64_t stride = gridDim.x;
+  int64_t tile = blockIdx.x;
+  if (tile >= ntile) return;
+  // FP64 at large KS: no second fragment buffer (register budget of two waves
+  // per SIMD); the other wave on the SIMD covers the load latency instead
+  constexpr bool PF = sizeof(T) == 4 || KS <= 16;
+  T b[KS], bn[PF ? KS : 1];
+  // the k part of an address is uniform (scalar); the lane part is one 32-bit
+  // offset fk ldu + voxel (the host checks that it fits).  Columns k >= r are
+  // clamped to r - 1: their T^T fragments are zero, so any finite value works.
+  auto loadB = [&](int64_t tl, T* x) {
+    const int64_t v = tl * 16 + fr;
+    const int32_t vc = (int32_t)(v < n ? v : n - 1);
+    const int32_t off = fk * (int32_t)ldu + vc;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int al = a0 + 16 * ta + fk + 4 * e;
-        if (al < ninj) {
-          const uint32_t word = bits[(int64_t)(al >> 5) * n + i];
-          const double om = (double)((word >> (al & 31)) & 1u);
-          const double v = om * acc[ta][tv][e];
-          N[(int64_t)al * ldn + i] = OY ? (T)((double)OY[(int64_t)al * ldoy + i] - v) : (T)v;
+    for (int ks = 0; ks < KS; ++ks) {
+      if (4 * ks + 3 < r) {
+        x[ks] = U[(int64_t)(4 * ks) * ldu + off];
+      } else {
+        const int k = min(4 * ks + fk, r - 1);
+        x[ks] = U[(int64_t)k * ldu + vc];
+      }
+    }
+  };
+  loadB(tile, b);
+  const uint32_t* wbits = bits + (int64_t)(a0 >> 5) * n;
+  for (; tile < ntile; tile += stride) {
+    const bool more = tile + stride < ntile;
+    if (PF && more) loadB(tile + stride, bn);
+    acc_t acc0 = acc_t{0, 0, 0, 0}, acc1 = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      acc0 = Mfma16<T>::mma(a[0][ks], b[ks], acc0);
+      acc1 = Mfma16<T>::mma(a[1][ks], b[ks], acc1);
+    }
+    const int64_t v = tile * 16 + fr;
+    if (v < n) {
+      const uint32_t wd = wbits[v];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int al_loc = 16 * t + Mfma16<T>::row(fk, e);  // < 32
+          const int64_t al = a0 + al_loc;
+          if (al < ninj) {
+            const T om = (T)((wd >> al_loc) & 1u);
+            const T val = om * (t ? acc1[e] : acc0[e]);
+            N[al * ldn + v] = OY ? OY[al * ldoy + v] - val : val;
+          }
         }
       }
+    }
+    if (more) {
+      if (PF) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
+      } else {
+        loadB(tile + stride, b);
+      }
+    }
   }
 }
 
@@ -470,11 +696,41 @@ cr_status masked_tall_gemm(int64_t n, int r, int ninj, const T* U, int64_t ldu, 
                            int64_t ldt, const uint32_t* bits, const T* OY, int64_t ldoy, T* N,
                            int64_t ldn, hipStream_t st) {
   if (n == 0 || ninj == 0) return CR_OK;
+  if (r >= 1 && r <= 112 && 4 * ldu + n < INT32_MAX) {
+    // one wave per 32 injections of a 128-injection block; about 4 workgroups per CU
+    const int na = std::min(ninj, MG_COLS);
+    const int waves = (na + 31) / 32;
+    const int64_t ntile = (n + 15) / 16;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t want = (int64_t)ncu * 16 / waves;
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min(ntile, want)), (ninj + MG_COLS - 1) / MG_COLS);
+    const int ks = (r + 3) / 4;
+#define RT_CASE(K)                                                                             \
+  if (ks <= K) {                                                                               \
+    hipLaunchKernelGGL((k_masked_gemm_rt<T, K>), grid, dim3(64 * waves), 0, st, n, r, ninj, U, \
+                       ldu, Tm, ldt, bits, OY, ldoy, N, ldn);                                  \
+    CR_HIP(hipGetLastError());                                                                 \
+    return CR_OK;                                                                              \
+  }
+    RT_CASE(4) RT_CASE(8) RT_CASE(12) RT_CASE(16) RT_CASE(20) RT_CASE(24) RT_CASE(28)
+#undef RT_CASE
+  }
   const unsigned nb_log = (unsigned)((n + MG_ROWS - 1) / MG_ROWS);
   const unsigned nb_phys = (nb_log + NXCD - 1) / NXCD * NXCD;
   dim3 grid(nb_phys, (ninj + MG_COLS - 1) / MG_COLS);
-  hipLaunchKernelGGL((k_masked_tall_gemm<T>), grid, dim3(NT), 0, st, n, r, ninj, U, ldu, Tm, ldt,
-                     bits, OY, ldoy, N, ldn, nb_log);
+  const int na = std::min(ninj, MG_COLS);
+  const int nta = na <= 16 ? 1 : na <= 32 ? 2 : na <= 64 ? 4 : 8;
+#define MG_CASE(K)                                                                               \
+  case K:                                                                                        \
+    hipLaunchKernelGGL((k_masked_tall_gemm<T, K>), grid, dim3(NT), 0, st, n, r, ninj, U, ldu, Tm, \
+                       ldt, bits, OY, ldoy, N, ldn, nb_log);                                     \
+    break;
+  switch (nta) {
+    MG_CASE(1) MG_CASE(2) MG_CASE(4) MG_CASE(8)
+  }
+#undef MG_CASE
   CR_HIP(hipGetLastError());
   return CR_OK;
 }

@@ -51,6 +51,8 @@ CASES = {
     "tiny3d": lambda: synth.config2_tiny(),
     "mid3d": mid_box,
     "densemask": dense_mask_box,
+    # more than one 128-injection block of the masked products
+    "manyinj": lambda: mid_box(seed=6, n_inj=150),
 }
 
 
@@ -61,7 +63,9 @@ def case(request):
 
 
 # ------------------------------------------------------------------ op_apply
-@pytest.mark.parametrize("r", [0, 1, 7, 67])
+# 112 is the largest rank of the register-resident masked product, 120 takes
+# the LDS-chunked one
+@pytest.mark.parametrize("r", [0, 1, 7, 67, 112, 120])
 def test_op_apply_fp64(case, r):
     name, d, P = case
     r = min(r, P.n_x)
@@ -90,7 +94,7 @@ def test_op_apply_fp64(case, r):
         assert rel(A, oop.apply_A(P, Wd)) < 1e-12
 
 
-@pytest.mark.parametrize("r", [1, 67])
+@pytest.mark.parametrize("r", [1, 67, 120])
 def test_op_apply_fp32(case, r):
     name, d, P = case
     r = min(r, P.n_x)
