@@ -39,6 +39,19 @@ def op_apply_bytes(n_y, n_x, n_inj, r, s):
             + n_y * n_inj / 8 + 24 * (n_y + n_x))
 
 
+def op_traffic():
+    """HBM bytes of one op_apply call from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    from paper_1808_05510_amd import traffic
+    path = os.path.join(ROOT, "profiles", "op_apply_shells_r100_fp64_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    return t["traffic_bytes"] if t.get("sources_sha") == traffic.sources_hash() else None
+
+
 def time_solves(prob, steps, warmup, opts):
     res = None
     for _ in range(warmup):
@@ -147,6 +160,52 @@ def bench_batch(count=16, max_rank=40, tau=1e-4, prec="mixed"):
     return out
 
 
+def bench_learned(d2, lam, opts, steps, warmup, train_seeds=(100, 101), train_steps=300):
+    """Mixed precision with the learned u-system preconditioner on the same
+    workload: the network (spectral base step + 3-D conv refinement) is
+    trained on u-systems dumped from FP64 greedy runs of other seeds (same
+    grids and lambda); collection and training are timed separately.  The
+    same mixed solve with the spectral base step alone is timed beside it."""
+    from paper_1808_05510_amd import lpc_train
+    t0 = time.perf_counter()
+    parts = []
+    handles = []
+    for s in train_seeds:
+        dtr = synth.config2(lam=lam, seed=s)
+        ptr = connreg.Problem(dtr, "fp64", "cuda:0")
+        ptr.set_box(dtr["box_y"])
+        parts.append(lpc_train.collect_pairs(ptr, max_rank=20, every=2, perturb=0.3, seed=s))
+        handles.append(ptr)
+    data = lpc_train.concat(parts)
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    pc = connreg.Pc(tuple(int(v) for v in d2["box_y"]), channels=8, seed=0)
+    t0 = time.perf_counter()
+    hist = lpc_train.train(pc, handles[-1], data, steps=train_steps, batch=8, lr=3e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    out = dict(pairs=len(data), collect_s=t_collect, train_s=t_train, train_steps=train_steps,
+               loss_first=hist[0], loss_last=float(np.mean(hist[-20:])))
+    for kind in ("learned", "base"):
+        pm = connreg.Problem(d2, "mixed", "cuda:0")
+        pm.set_box(d2["box_y"])
+        if kind == "learned":
+            pm.set_pc(pc)
+        else:
+            pm.set_precond("base")
+        _, mtimes, mres = time_solves(pm, steps, warmup, opts)
+        out[kind] = dict(seconds=float(np.mean(mtimes)), rank=mres["rank"],
+                         relres=mres["stats"]["relres"], pcg_iters=mres["stats"]["pcg_iters"],
+                         reached_tau=bool(mres["stats"]["relres"] <= opts["tau_res"]),
+                         curve=[[h["rank"], h["relres"], h["seconds"]] for h in mres["history"]])
+        pm.set_pc(None)
+        pm.close()
+    for h in handles:
+        h.close()
+    pc.close()
+    return out
+
+
 def cpu_baseline(d, lam, ranks_needed, sample_ranks):
     """FP64 oracle (NumPy/SciPy, Jacobi-CG inner solves) on the first
     ``sample_ranks`` greedy steps of the same workload; seconds per rank times
@@ -183,6 +242,7 @@ def main():
     ap.add_argument("--op-only", action="store_true", help="only the op_apply bandwidth part")
     ap.add_argument("--batch-only", action="store_true", help="only the 16-problem batch")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the solver is a "
@@ -227,6 +287,14 @@ def main():
         log(f"[bench] mixed: {mixed['seconds']:.3f} s/solve, rank {mixed['rank']}")
         pm.close()
 
+    learned = None
+    if not a.no_learned:
+        log("[bench] mixed precision + learned u-system preconditioner")
+        learned = bench_learned(d2, a.lam, opts, a.steps, a.warmup)
+        log(f"[bench] mixed+learned: {learned['learned']['seconds']:.3f} s/solve "
+            f"(base step alone {learned['base']['seconds']:.3f} s; training "
+            f"{learned['train_s']:.1f} s on {learned['pairs']} pairs)")
+
     op = None
     roof = None
     if not a.no_op:
@@ -247,7 +315,7 @@ def main():
         op["gram"] = gram
         o = op["f64_r100"]
         roof = dict(bound="hbm", achieved=o["GBps"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=o["frac"], traffic=None, kernel="cr_op_apply (FP64, r=100, shells)")
+                    frac=o["frac"], traffic=op_traffic(), kernel="cr_op_apply (FP64, r=100, shells)")
         del d3
 
     batch = None
@@ -289,6 +357,7 @@ def main():
         "galerkin_iters": res["stats"]["galerkin_iters"],
         "relres_curve": [[h["rank"], h["relres"], h["seconds"]] for h in hist],
         "mixed": mixed,
+        "mixed_learned_pc": learned,
         "op_apply": op,
         "batch": batch,
         "roofline": roof,

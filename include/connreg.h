@@ -260,25 +260,49 @@ cr_status cr_pc_forward(cr_pc* pc, const float* in, float* y);
 cr_status cr_pc_vjp(cr_pc* pc, const float* in, const float* dy, float* grad_host);
 /* One Adam step on a batch of u-systems of handle p (whose target graph is
  * the pc's box): b, x, d [dev] batch x n_y (x = exact solutions),
- * coef [host] batch x 2, loss = mean over the batch of
- * ||N(b) - x||^2 / ||x||^2 with N(b) = y ||b|| / lambda.  loss_out [host]. */
+ * coef [host] batch x 2 ([2 v^T L_x v, ||L_x v||^2]).  The network refines
+ * the base step w of the flexible CG (the spectral solve when
+ * cr_problem_set_box was called, else Jacobi) into z = w_n + y with
+ * w_n = sqrt(N) w / ||w||; loss = mean over the batch of 1 - cos^2(z, x),
+ * the quantity that a scale-invariant preconditioner step can reduce.
+ * loss_out [host]. */
 cr_status cr_pc_train_step(cr_pc* pc, cr_problem* p, int32_t batch, const double* b,
                            const double* x, const double* d, const double* coef, float lr,
                            double* loss_out);
 
-/* Solve A_hat x = rhs (FP64): pc == NULL -> persistent Jacobi-PCG; otherwise
- * FCG with the network.  x_out [dev] n_y (not normalised); iters_out,
- * relres_out, fallbacks_out [host] may be NULL.  Synchronises. */
+/* Solve A_hat x = rhs (FP64) for the u-system of eq. ALS_linsys with data
+ * diagonal d [dev] n_y and coef [host] = [2 v^T L_x v, ||L_x v||^2]:
+ * precond 0 -> persistent Jacobi-PCG; 1 -> flexible CG with the base step
+ * (spectral on a box set by cr_problem_set_box, else Jacobi); 2 -> flexible
+ * CG with the base step refined by the network pc (pc required).  x_out
+ * [dev] n_y (not normalised); iters_out, relres_out, fallbacks_out [host]
+ * may be NULL.  Synchronises. */
 cr_status cr_u_solve(cr_problem* p, const double* d, const double* coef, const double* rhs,
-                     double* x_out, double rtol, int32_t maxit, cr_pc* pc, int32_t* iters_out,
-                     double* relres_out, int32_t* fallbacks_out);
+                     double* x_out, double rtol, int32_t maxit, int32_t precond, cr_pc* pc,
+                     int32_t* iters_out, double* relres_out, int32_t* fallbacks_out);
 
 /* Use pc (NULL: none) for the u-systems of cr_greedy_solve / cr_als_step on
  * this handle (full-box targets matching the pc's box; with a mixed handle
- * the flexible CG runs in FP64 on FP64 copies of the system).  The handle
- * does not own pc.  Jacobi-PCG takes over any u-solve that the
- * network-preconditioned FCG does not finish. */
+ * the flexible CG runs in FP64 on FP64 copies of the system); sets the
+ * u-system preconditioner to 2 (pc) or 0 (NULL).  The handle does not own
+ * pc.  Jacobi-PCG takes over any u-solve that the flexible CG does not
+ * finish. */
 cr_status cr_problem_set_pc(cr_problem* p, cr_pc* pc);
+
+/* u-system preconditioner of cr_greedy_solve / cr_als_step: 0 persistent
+ * Jacobi-PCG (default), 1 flexible CG with the base step, 2 flexible CG with
+ * the base step refined by the network of cr_problem_set_pc.  CR_EINVAL for
+ * other values or 2 without a network. */
+cr_status cr_problem_set_precond(cr_problem* p, int32_t kind);
+
+/* Declares the target grid a full dims[0] x dims[1] x dims[2] box numbered
+ * first axis fastest.  Checks the target Laplacian against the box's
+ * free-face 7-point Laplacian (CR_EINVAL if it differs) and builds the
+ * per-axis DCT-II eigenbases of the path-graph Laplacians, so that the base
+ * step of the flexible CG becomes the spectral solve
+ *   w = Q diag(1 / (lambda (mu^2 + 2 b mu + a) + mean(d))) Q^T r,
+ * exact for the u-system of eq. ALS_linsys when d is constant.  dims [host]. */
+cr_status cr_problem_set_box(cr_problem* p, const int32_t* dims);
 
 /* ---------------------------------------------------------------------------
  * Batched solves and autotuning.

@@ -29,7 +29,8 @@ EXPORTS = ["cr_problem_create", "cr_problem_destroy", "cr_rhs_norm", "cr_op_appl
            "cr_u_system", "cr_u_solve", "cr_problem_set_pc", "cr_pc_create", "cr_pc_destroy",
            "cr_pc_num_params", "cr_pc_get_params", "cr_pc_set_params", "cr_pc_forward",
            "cr_pc_vjp", "cr_pc_train_step", "cr_masked_gram", "cr_greedy_solve_batch",
-           "cr_autotune_pcg", "cr_problem_set_tuning"]
+           "cr_autotune_pcg", "cr_problem_set_tuning", "cr_problem_set_precond",
+           "cr_problem_set_box"]
 
 
 class CSR(ctypes.Structure):
@@ -102,9 +103,11 @@ def load(path: str = LIB_PATH):
                                   POINTER(SolveStats), RANK_CB, P]
     L.cr_u_system.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, P, P,
                               POINTER(c_double)]
-    L.cr_u_solve.argtypes = [P, P, POINTER(c_double), P, P, c_double, c_int32, P,
+    L.cr_u_solve.argtypes = [P, P, POINTER(c_double), P, P, c_double, c_int32, c_int32, P,
                              POINTER(c_int32), POINTER(c_double), POINTER(c_int32)]
     L.cr_problem_set_pc.argtypes = [P, P]
+    L.cr_problem_set_precond.argtypes = [P, c_int32]
+    L.cr_problem_set_box.argtypes = [P, POINTER(c_int32)]
     L.cr_pc_create.argtypes = [c_int32, c_int32, c_int32, c_int32, c_uint64, P, POINTER(P)]
     L.cr_pc_destroy.argtypes = [P]
     L.cr_pc_destroy.restype = None
@@ -312,18 +315,32 @@ class Problem:
                                   _ld(V), _ptr(v), _ptr(rhs), _ptr(d), coef))
         return rhs, d, (coef[0], coef[1])
 
-    def u_solve(self, d, coef, rhs, rtol=1e-8, maxit=5000, pc=None):
-        """Solve the u-system: Jacobi-PCG (pc None) or FCG with the network.
+    PRECOND = {"jacobi": 0, "base": 1, "learned": 2}
+
+    def u_solve(self, d, coef, rhs, rtol=1e-8, maxit=5000, pc=None, precond=None):
+        """Solve the u-system.  precond: "jacobi" (persistent Jacobi-PCG),
+        "base" (flexible CG with the base step: spectral on a declared box,
+        else Jacobi) or "learned" (base step refined by the network pc);
+        default "learned" when pc is given, else "jacobi".
         Returns (x, iters, relres, fallbacks, status)."""
+        kind = self.PRECOND[precond or ("learned" if pc is not None else "jacobi")]
         d = self._col(d).reshape(-1).contiguous()
         rhs = self._col(rhs).reshape(-1).contiguous()
         x = torch.empty(self.n_y, device=self.device, dtype=torch.float64)
         cf = (c_double * 2)(*coef)
         it, rr, fb = c_int32(), c_double(), c_int32()
-        s = _check(load().cr_u_solve(self.h, _ptr(d), cf, _ptr(rhs), _ptr(x), rtol, maxit,
+        s = _check(load().cr_u_solve(self.h, _ptr(d), cf, _ptr(rhs), _ptr(x), rtol, maxit, kind,
                                      pc.h if pc is not None else None, ctypes.byref(it),
                                      ctypes.byref(rr), ctypes.byref(fb)))
         return x, it.value, rr.value, fb.value, STATUS_NAMES[s]
+
+    def set_box(self, dims):
+        """Declare the target grid a full box (first axis fastest)."""
+        _check(load().cr_problem_set_box(self.h, (c_int32 * 3)(*[int(v) for v in dims])))
+
+    def set_precond(self, kind):
+        """u-system preconditioner of the greedy solve: "jacobi", "base" or "learned"."""
+        _check(load().cr_problem_set_precond(self.h, self.PRECOND[kind]))
 
     def set_pc(self, pc):
         _check(load().cr_problem_set_pc(self.h, pc.h if pc is not None else None))

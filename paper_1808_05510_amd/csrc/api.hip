@@ -55,6 +55,8 @@ struct cr_problem {
   double* hscal = nullptr;  // pinned host scratch
   unsigned* bar = nullptr;  // grid-barrier words: [0] generation, [64] timeout, [128] arrivals
   cr_pc* pc = nullptr;      // learned preconditioner for the u-systems (not owned)
+  int fcg_mode = 0;         // u-systems: 0 Jacobi-PCG, 1 FCG + base step, 2 FCG + base step + network
+  BoxBasis boxy;            // spectral basis of the target grid when it is a full box
   int64_t pc_fallbacks = 0;
   int cu_share = 0;         // > 0: persistent grids limited to this many CUs' worth of slots
   int coop = 1;             // persistent kernels launched cooperatively
@@ -247,6 +249,77 @@ __global__ void k_jacobi(int64_t n, const double* __restrict__ minv, const doubl
 }
 
 // ===================================================================== solver context
+// ----------------------------------------------------------- device-scalar FCG
+// Scalars of the flexible CG live in device memory, so an iteration is a
+// fixed launch sequence with no host synchronisation:
+//   S[0] b.b   S[1] r.r   S[2] p.q of the previous step   S[5] alpha   S[6] beta
+//   S[7] state (0 running, 1 converged, 2 breakdown)   S[8] iterations
+//   S[10] 1 when the base step replaces the network output   S[11] fallbacks
+//   S[12] w.w   S[13] mean of d   S[16..19] [r.z, qq.z, r.w, qq.w]   S[20..21] [q.p, r.p]
+enum { FS_BB = 0, FS_RR = 1, FS_PQP = 2, FS_ALPHA = 5, FS_BETA = 6, FS_STATE = 7, FS_IT = 8,
+       FS_USEW = 10, FS_FB = 11, FS_WW = 12, FS_DBAR = 13, FS_DZ = 16, FS_DP = 20, FS_N = 24 };
+
+__global__ void k_fcg_beta(double* S, int first, int net) {
+  if (S[FS_STATE] != 0.0) return;
+  double zr = S[FS_DZ + 0], zq = S[FS_DZ + 1];
+  const bool ok = net == 0 || (zr > 0.0 && isfinite(zr) && (first || isfinite(zq)));
+  if (!ok) {  // the network output is not a descent direction: use the base step
+    zr = S[FS_DZ + 2];
+    zq = S[FS_DZ + 3];
+    S[FS_FB] += 1.0;
+  }
+  S[FS_USEW] = (net == 0 || !ok) ? 1.0 : 0.0;
+  S[FS_BETA] = first ? 0.0 : -zq / S[FS_PQP];
+}
+
+__global__ void k_fcg_dir(int64_t n, const double* __restrict__ z, const double* __restrict__ w,
+                          const double* __restrict__ S, const double* __restrict__ pp,
+                          double* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || S[FS_STATE] != 0.0) return;
+  const double beta = S[FS_BETA];
+  const double zi = S[FS_USEW] != 0.0 ? w[i] : z[i];
+  p[i] = beta != 0.0 ? zi + beta * pp[i] : zi;
+}
+
+__global__ void k_fcg_alpha(double* S) {
+  if (S[FS_STATE] != 0.0) {
+    S[FS_ALPHA] = 0.0;
+    return;
+  }
+  const double pq = S[FS_DP + 0], pr = S[FS_DP + 1];
+  if (!(pq > 0.0) || !isfinite(pr)) {
+    S[FS_STATE] = 2.0;
+    S[FS_ALPHA] = 0.0;
+    return;
+  }
+  S[FS_ALPHA] = pr / pq;
+  S[FS_PQP] = pq;
+}
+
+__global__ void k_fcg_update(int64_t n, const double* __restrict__ S, const double* __restrict__ p,
+                             const double* __restrict__ q, double* __restrict__ x,
+                             double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double a = S[FS_ALPHA];
+  if (i >= n || a == 0.0) return;
+  x[i] += a * p[i];
+  r[i] -= a * q[i];
+}
+
+__global__ void k_fcg_check(double* S, double tol2) {
+  if (S[FS_STATE] != 0.0) return;
+  S[FS_IT] += 1.0;
+  if (S[FS_RR] <= tol2 * S[FS_BB]) S[FS_STATE] = 1.0;
+}
+
+__global__ void k_scale1(double* x, double s) { x[0] *= s; }
+
+__global__ void k_fill(int64_t n, double v, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
 template <typename T>
 struct Ctx {
   cr_problem* P;
@@ -516,7 +589,7 @@ struct Ctx {
   // (x accumulated in FP64, r = b - A x evaluated in FP64 arithmetic).
   cr_status solve_sys(bool usys, const T* b, T* xout, double rtol, int maxit, double* dsc,
                       SolveOut* out, bool& deferred) {
-    if (usys && P->pc) {
+    if (usys && P->fcg_mode > 0) {
       deferred = false;
       double* xs = WS(double, "fcg_x", ny);
       int fb = 0;
@@ -533,10 +606,10 @@ struct Ctx {
         d64 = cd;
         m64 = cm;
       }
-      CR_TRY(fcg_u(b64, xs, rtol, maxit, out, &fb, d64, m64));
+      CR_TRY(fcg_u(b64, xs, rtol, maxit, out, &fb, d64, m64, P->fcg_mode == 2));
       P->pc_fallbacks += fb;
       if (out->status != 0) {
-        // the network-preconditioned solve failed: Jacobi-PCG decides
+        // the flexible CG failed: Jacobi-PCG decides
         ++P->pc_fallbacks;
         CR_TRY(pcg(true, b, xout, rtol, maxit, dsc));
         double h[4];
@@ -610,48 +683,76 @@ struct Ctx {
   // network as preconditioner; z = M r falls back to the Jacobi step when
   // <r, z> <= 0 or is not finite.  FP64 vectors, host-side scalars.
   // Writes the solution into xsol (not normalised).
+  // Flexible CG (one previous direction kept, Notay's FCG(1)) on the u-system
+  // of eq. ALS_linsys.  The preconditioner is a base step w = M^-1 r, the
+  // spectral solve of the box when the target grid is a full box, else
+  // Jacobi, optionally refined by the learned network (z = network(w));
+  // whenever the network's z is not a descent direction (r.z <= 0 or not
+  // finite) the iteration uses w instead and counts a fallback.  All scalars
+  // stay on the device; the host checks convergence every 8 iterations.
   cr_status fcg_u(const double* b, double* xsol, double rtol, int maxit, SolveOut* out,
-                  int* fallbacks, const double* dv, const double* mi) {
+                  int* fallbacks, const double* dv, const double* mi, bool use_net) {
     cr_pc* pc = P->pc;
+    const bool net = use_net && pc;
     const int64_t n = ny;
-    double* W = WS(double, "fcg_work", 8 * n);
+    double* W = WS(double, "fcg_work", 9 * n);
     double *r = W, *z = W + n, *p = W + 2 * n, *q = W + 3 * n, *pp = W + 4 * n, *qq = W + 5 * n,
-           *t = W + 6 * n, *zj = W + 7 * n;
-    double h[4];
+           *t = W + 6 * n, *w = W + 7 * n, *t2 = W + 8 * n;
+    double* S = WS(double, "fcg_S", FS_N);
+    CR_HIP(hipMemsetAsync(S, 0, sizeof(double) * FS_N, st));
     CR_HIP(hipMemsetAsync(xsol, 0, sizeof(double) * n, st));
+    CR_HIP(hipMemsetAsync(pp, 0, sizeof(double) * n, st));
+    CR_HIP(hipMemsetAsync(qq, 0, sizeof(double) * n, st));
     CR_HIP(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    CR_TRY(dot64(n, b, b, tmp + 12));
-    CR_TRY(read_scalars(tmp + 12, 1, h));
+    CR_TRY(dot64(n, b, b, S + FS_BB));
+    const bool spectral = P->boxy.valid;
+    if (spectral) {
+      double* ones = WS(double, "fcg_ones", n);
+      hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, ones);
+      CR_HIP(hipGetLastError());
+      CR_TRY(dot64(n, dv, ones, S + FS_DBAR));
+      hipLaunchKernelGGL(k_scale1, dim3(1), dim3(1), 0, st, S + FS_DBAR, 1.0 / (double)n);
+      CR_HIP(hipGetLastError());
+    }
+    double h[FS_N];
+    CR_TRY(read_scalars(S, 1, h));
     const double bb = h[0];
     *out = SolveOut{};
     if (!(bb > 0.0)) {
       out->status = 2;
       return CR_OK;
     }
-    double pq_prev = 0.0, rr = bb;
+    const double tol2 = rtol * rtol;
     int it = 0;
     for (; it < maxit; ++it) {
-      // z = M r: the network refines the Jacobi step zj = D^-1 r
-      hipLaunchKernelGGL(k_jacobi, dim3(nblk(n)), dim3(256), 0, st, n, mi, r, zj);
-      CR_HIP(hipGetLastError());
-      CR_TRY(dot64(n, zj, zj, tmp + 12));
-      CR_TRY(lpc_input(pc->net, zj, tmp + 12, mi, dv, P->gy.deg, cu, lam, pc->acts.in, st));
-      CR_TRY(lpc_forward(pc->net, pc->acts.in, pc->acts, st));
-      CR_TRY(lpc_output(pc->net, pc->acts.in, pc->acts.y, z, st));
-      Blocks<double> A;
+      // base step w, then z (network refinement or w itself)
+      if (spectral) {
+        CR_TRY(box_spectral_solve(P->boxy, cu, lam, S + FS_DBAR, r, w, t2, st));
+      } else {
+        hipLaunchKernelGGL(k_jacobi, dim3(nblk(n)), dim3(256), 0, st, n, mi, r, w);
+        CR_HIP(hipGetLastError());
+      }
+      const double* zz = w;
+      if (net) {
+        CR_TRY(dot64(n, w, w, S + FS_WW));
+        CR_TRY(lpc_input(pc->net, w, S + FS_WW, mi, dv, P->gy.deg, cu, lam, pc->acts.in, st));
+        CR_TRY(lpc_forward(pc->net, pc->acts.in, pc->acts, st));
+        CR_TRY(lpc_output(pc->net, pc->acts.in, pc->acts.y, z, st));
+        zz = z;
+      }
+      // [r.z, qq.z, r.w, qq.w]
+      Blocks<double> A, B;
       A.clear();
       A.add(r, n, 1);
-      if (it > 0) A.add(qq, n, 1);
-      CR_TRY(gemv_t<double>(n, A, z, tmp + 13, part, st));
-      CR_TRY(read_scalars(tmp + 13, it > 0 ? 2 : 1, h));
-      if (!(h[0] > 0.0) || !std::isfinite(h[0]) || (it > 0 && !std::isfinite(h[1]))) {
-        CR_HIP(hipMemcpyAsync(z, zj, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-        CR_TRY(gemv_t<double>(n, A, z, tmp + 13, part, st));
-        CR_TRY(read_scalars(tmp + 13, it > 0 ? 2 : 1, h));
-        ++*fallbacks;
-      }
-      const double beta = it > 0 ? -h[1] / pq_prev : 0.0;
-      hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, st, n, z, beta, pp, p);
+      A.add(qq, n, 1);
+      B.clear();
+      B.add(zz, n, 1);
+      B.add(w, n, 1);
+      CR_TRY(gemm_tn<double>(n, A, B, nullptr, nullptr, 0, S + FS_DZ, 2, gpart, gemm_part_cap(P),
+                             st));
+      hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(1), 0, st, S, it == 0 ? 1 : 0, net ? 1 : 0);
+      hipLaunchKernelGGL(k_fcg_dir, dim3(nblk(n)), dim3(256), 0, st, n, zz, w, S, pp, p);
+      CR_HIP(hipGetLastError());
       CR_TRY(stencil<double>(P->gy, 1, p, n, t, n, st));
       hipLaunchKernelGGL(k_uapply, dim3(nblk(n)), dim3(256), 0, st, n, P->gy.K, P->gy.nbr, lam,
                          cu, dv, p, t, q);
@@ -659,32 +760,27 @@ struct Ctx {
       A.clear();
       A.add(q, n, 1);
       A.add(r, n, 1);
-      CR_TRY(gemv_t<double>(n, A, p, tmp + 13, part, st));
-      CR_TRY(read_scalars(tmp + 13, 2, h));
-      const double pq = h[0], pr = h[1];
-      if (!(pq > 0.0)) {
-        out->status = 2;
-        break;
-      }
-      const double alpha = pr / pq;
-      hipLaunchKernelGGL(k_xr_update, dim3(nblk(n)), dim3(256), 0, st, n, alpha, p, q, xsol, r);
+      CR_TRY(gemv_t<double>(n, A, p, S + FS_DP, part, st));
+      hipLaunchKernelGGL(k_fcg_alpha, dim3(1), dim3(1), 0, st, S);
+      hipLaunchKernelGGL(k_fcg_update, dim3(nblk(n)), dim3(256), 0, st, n, S, p, q, xsol, r);
       CR_HIP(hipGetLastError());
-      CR_TRY(dot64(n, r, r, tmp + 12));
-      CR_TRY(read_scalars(tmp + 12, 1, h));
-      rr = h[0];
+      CR_TRY(dot64(n, r, r, S + FS_RR));
+      hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(1), 0, st, S, tol2);
+      CR_HIP(hipGetLastError());
       std::swap(p, pp);
       std::swap(q, qq);
-      pq_prev = pq;
-      if (rr <= rtol * rtol * bb) {
-        ++it;
-        break;
+      if ((it & 7) == 7 || it + 1 == maxit) {
+        CR_TRY(read_scalars(S, FS_N, h));
+        if (h[FS_STATE] != 0.0) break;
       }
     }
-    out->iters = it;
-    out->relres = std::sqrt(rr / bb);
-    if (out->status == 0 && !(rr <= rtol * rtol * bb)) out->status = 1;
-    CR_TRY(dot64(n, xsol, xsol, tmp + 12));
-    CR_TRY(read_scalars(tmp + 12, 1, h));
+    CR_TRY(read_scalars(S, FS_N, h));
+    out->iters = (int)h[FS_IT];
+    out->relres = std::sqrt(std::max(h[FS_RR], 0.0) / bb);
+    out->status = h[FS_STATE] == 2.0 ? 2 : h[FS_STATE] == 1.0 ? 0 : 1;
+    *fallbacks = (int)h[FS_FB];
+    CR_TRY(dot64(n, xsol, xsol, S + FS_WW));
+    CR_TRY(read_scalars(S + FS_WW, 1, h));
     out->norm = std::sqrt(h[0]);
     return CR_OK;
   }
@@ -1593,7 +1689,79 @@ extern "C" cr_status cr_problem_set_pc(cr_problem* P, cr_pc* pc) {
     }
   }
   P->pc = pc;
+  P->fcg_mode = pc ? 2 : 0;
   P->pc_fallbacks = 0;
+  return CR_OK;
+}
+
+extern "C" cr_status cr_problem_set_precond(cr_problem* P, int32_t kind) {
+  if (!P || kind < 0 || kind > 2 || (kind == 2 && !P->pc)) {
+    set_error("precond must be 0 (Jacobi-PCG), 1 (flexible CG with the base step) or 2 "
+              "(flexible CG with the learned network, after cr_problem_set_pc)");
+    return CR_EINVAL;
+  }
+  P->fcg_mode = kind;
+  return CR_OK;
+}
+
+// Target grid as a full d0 x d1 x d2 box (first axis fastest): checks that the
+// Laplacian is the box's free-face 7-point Laplacian, then builds the per-axis
+// DCT-II bases used by the spectral base step.
+extern "C" cr_status cr_problem_set_box(cr_problem* P, const int32_t* dims) {
+  if (!P || !dims || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0 ||
+      (int64_t)dims[0] * dims[1] * dims[2] != P->ny) {
+    set_error("box dimensions must be positive and multiply to the number of target voxels");
+    return CR_EINVAL;
+  }
+  const int64_t n = P->ny;
+  const int K = P->gy.K;
+  std::vector<int32_t> nbr((size_t)K * n);
+  CR_HIP(hipMemcpy(nbr.data(), P->gy.nbr, sizeof(int32_t) * nbr.size(), hipMemcpyDeviceToHost));
+  const int d0 = dims[0], d1 = dims[1], d2 = dims[2];
+  for (int64_t i = 0; i < n; ++i) {
+    const int i0 = (int)(i % d0), i1 = (int)((i / d0) % d1), i2 = (int)(i / ((int64_t)d0 * d1));
+    int64_t want[6];
+    int nw = 0;
+    if (i0 > 0) want[nw++] = i - 1;
+    if (i0 + 1 < d0) want[nw++] = i + 1;
+    if (i1 > 0) want[nw++] = i - d0;
+    if (i1 + 1 < d1) want[nw++] = i + d0;
+    if (i2 > 0) want[nw++] = i - (int64_t)d0 * d1;
+    if (i2 + 1 < d2) want[nw++] = i + (int64_t)d0 * d1;
+    int have = 0;
+    for (int k = 0; k < K; ++k) {
+      const int64_t j = nbr[(size_t)k * n + i];
+      if (j == i) continue;
+      bool found = false;
+      for (int m = 0; m < nw; ++m) found = found || want[m] == j;
+      if (!found) {
+        set_error("the target Laplacian is not the box's 7-point Laplacian");
+        return CR_EINVAL;
+      }
+      ++have;
+    }
+    if (have != nw) {
+      set_error("the target Laplacian is not the box's 7-point Laplacian");
+      return CR_EINVAL;
+    }
+  }
+  BoxBasis bx;
+  bx.valid = true;
+  for (int a = 0; a < 3; ++a) {
+    const int m = dims[a];
+    bx.dims[a] = m;
+    std::vector<double> Q((size_t)m * m), mu(m);
+    for (int k = 0; k < m; ++k) {
+      const double c = k == 0 ? std::sqrt(1.0 / m) : std::sqrt(2.0 / m);
+      for (int j = 0; j < m; ++j) Q[(size_t)j * m + k] = c * std::cos(M_PI * k * (j + 0.5) / m);
+      mu[k] = 2.0 - 2.0 * std::cos(M_PI * k / m);
+    }
+    CR_TRY(dev_alloc(P, &bx.Q[a], (int64_t)m * m));
+    CR_TRY(dev_alloc(P, &bx.mu[a], m));
+    CR_HIP(hipMemcpy(bx.Q[a], Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
+    CR_HIP(hipMemcpy(bx.mu[a], mu.data(), sizeof(double) * m, hipMemcpyHostToDevice));
+  }
+  P->boxy = bx;
   return CR_OK;
 }
 
@@ -1627,9 +1795,10 @@ extern "C" cr_status cr_u_system(cr_problem* P, int64_t r, const double* U, int6
 
 extern "C" cr_status cr_u_solve(cr_problem* P, const double* d, const double* coef,
                                 const double* rhs, double* x_out, double rtol, int32_t maxit,
-                                cr_pc* pc, int32_t* iters_out, double* relres_out,
-                                int32_t* fallbacks_out) {
-  if (!P || !d || !coef || !rhs || !x_out || !(rtol > 0) || maxit <= 0) {
+                                int32_t precond, cr_pc* pc, int32_t* iters_out,
+                                double* relres_out, int32_t* fallbacks_out) {
+  if (!P || !d || !coef || !rhs || !x_out || !(rtol > 0) || maxit <= 0 || precond < 0 ||
+      precond > 2 || (precond == 2 && !pc)) {
     set_error("invalid arguments to cr_u_solve");
     return CR_EINVAL;
   }
@@ -1649,10 +1818,10 @@ extern "C" cr_status cr_u_solve(cr_problem* P, const double* d, const double* co
   CR_TRY(pcg_diag<double>(P->gy, c.lam, c.cu, c.dvec, nullptr, 0, 0, nullptr, c.minv_u, c.st));
   Ctx<double>::SolveOut so;
   int fb = 0;
-  if (pc) {
+  if (precond > 0) {
     cr_pc* saved = P->pc;
     P->pc = pc;
-    cr_status s = c.fcg_u(rhs, x_out, rtol, maxit, &so, &fb, c.dvec, c.minv_u);
+    cr_status s = c.fcg_u(rhs, x_out, rtol, maxit, &so, &fb, c.dvec, c.minv_u, precond == 2);
     P->pc = saved;
     CR_TRY(s);
   } else {
@@ -1687,7 +1856,7 @@ extern "C" cr_status cr_pc_train_step(cr_pc* pc, cr_problem* P, int32_t batch, c
   }
   hipStream_t st = pc->st;
   const int64_t lsz = lpc_loss_scratch(pc->net);
-  const int64_t need = 8 + lsz + gemv_t_part_size(n, 1) + 4 * n;
+  const int64_t need = 8 + lsz + gemv_t_part_size(n, 1) + 6 * n;
   if (pc->dwork_n < need) {
     if (pc->dwork) (void)hipFree(pc->dwork);
     pc->dwork = nullptr;
@@ -1703,6 +1872,10 @@ extern "C" cr_status cr_pc_train_step(cr_pc* pc, cr_problem* P, int32_t batch, c
   double* gpart = lscr + lsz;       // gemv partials
   double* minv = gpart + gemv_t_part_size(n, 1);
   double* w = minv + n;
+  double* wt = w + n;      // spectral scratch
+  double* ones = wt + n;
+  hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, ones);
+  CR_HIP(hipGetLastError());
   double total = 0.0;
   for (int s = 0; s < batch; ++s) {
     const double* bs = b + (int64_t)s * n;
@@ -1710,7 +1883,17 @@ extern "C" cr_status cr_pc_train_step(cr_pc* pc, cr_problem* P, int32_t batch, c
     const double* ds = d + (int64_t)s * n;
     CR_HIP(hipMemcpyAsync(sc + 2, coef + 2 * s, 2 * sizeof(double), hipMemcpyHostToDevice, st));
     CR_TRY(pcg_diag<double>(P->gy, P->lam, sc + 2, ds, nullptr, 0, 0, nullptr, minv, st));
-    hipLaunchKernelGGL(k_jacobi, dim3(nblk(n)), dim3(256), 0, st, n, minv, bs, w);
+    if (P->boxy.valid) {
+      // the base step of the flexible CG: spectral solve with the mean of d
+      Blocks<double> Dm;
+      Dm.clear();
+      Dm.add(ds, n, 1);
+      CR_TRY(gemv_t<double>(n, Dm, ones, sc + 4, gpart, st));
+      hipLaunchKernelGGL(k_scale1, dim3(1), dim3(1), 0, st, sc + 4, 1.0 / (double)n);
+      CR_TRY(box_spectral_solve(P->boxy, sc + 2, P->lam, sc + 4, bs, w, wt, st));
+    } else {
+      hipLaunchKernelGGL(k_jacobi, dim3(nblk(n)), dim3(256), 0, st, n, minv, bs, w);
+    }
     CR_HIP(hipGetLastError());
     Blocks<double> A;
     A.clear();

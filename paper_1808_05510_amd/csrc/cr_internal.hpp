@@ -206,6 +206,18 @@ int galerkin_max_wg(int r);
 // ---------------------------------------------------------------- learned preconditioner
 constexpr int LPC_MAXC = 8;
 constexpr int LPC_LAYERS = 5;
+// Per-axis DCT-II bases of a full box (first axis fastest): Q[a] row-major
+// d_a x d_a (row = position, column = mode), mu[a] the path-graph eigenvalues.
+struct BoxBasis {
+  bool valid = false;
+  int dims[3] = {0, 0, 0};
+  double* Q[3] = {nullptr, nullptr, nullptr};
+  double* mu[3] = {nullptr, nullptr, nullptr};
+};
+// out = Q diag(1 / (lam (mu^2 + c[0] mu + c[1]) + dbar[0])) Q^T r; tmp: n doubles
+cr_status box_spectral_solve(const BoxBasis& bx, const double* c, double lam, const double* dbar,
+                             const double* r, double* out, double* tmp, hipStream_t st);
+
 struct LpcNet {
   int nx = 0, ny = 0, nz = 0, C = 0;
   int ci[LPC_LAYERS], co[LPC_LAYERS];

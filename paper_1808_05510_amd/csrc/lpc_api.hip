@@ -95,14 +95,14 @@ extern "C" cr_status cr_pc_create(int32_t nx, int32_t ny, int32_t nz, int32_t ch
     n.vB[l] = base[3] + off;
     off += co[l];
   }
-  // He-uniform weights from SplitMix64(seed), zero biases; the last layer is
-  // scaled down so an untrained network starts close to a small multiple of
-  // a smoothing filter
+  // He-uniform weights from SplitMix64(seed), zero biases; the last layer
+  // starts at zero, so an untrained network returns its input's base step
+  // unchanged (z = w) and training moves it only as far as the loss asks
   std::vector<float> h(np, 0.f);
   int64_t k = 0;
   for (int l = 0; l < LPC_LAYERS; ++l) {
     const int64_t nw = (int64_t)co[l] * ci[l] * 27;
-    const double lim = std::sqrt(6.0 / (ci[l] * 27.0)) * (l == LPC_LAYERS - 1 ? 0.1 : 1.0);
+    const double lim = l == LPC_LAYERS - 1 ? 0.0 : std::sqrt(6.0 / (ci[l] * 27.0));
     for (int64_t e = 0; e < nw; ++e, ++k) {
       const double u = (double)(sm64(seed, (uint64_t)k + 1) >> 11) * 0x1.0p-52 - 1.0;
       h[k] = (float)(lim * u);

@@ -138,3 +138,109 @@ def test_greedy_with_network_keeps_the_answer():
     assert err < 1e-6
     g.set_pc(None)
     pc.close()
+
+
+# ------------------------------------------------------------------ spectral base step
+def _dense_u_matrix(P, d, coef):
+    """lam (L^2 + 2 b L + a I) + diag(d), coef = [2 b, a], from the oracle's Laplacian."""
+    L = P.Ly.toarray()
+    n = L.shape[0]
+    return P.lam * (L @ L + coef[0] * L + coef[1] * np.eye(n)) + np.diag(d)
+
+
+def test_spectral_step_is_exact_for_constant_d():
+    d = box(seed=3)
+    P = oop.problem_from_arrays(d)
+    g = connreg.Problem(d, "fp64", DEV)
+    g.set_box(d["box_y"])
+    rng = np.random.default_rng(21)
+    n = P.n_y
+    dd = np.full(n, 0.37)
+    coef = (2 * 1.3, 1.3 ** 2 + 0.8)  # a >= b^2
+    rhs = rng.standard_normal(n)
+    x, it, rr, fb, st = g.u_solve(torch.tensor(dd, device=DEV), coef, torch.tensor(rhs, device=DEV),
+                                  rtol=1e-12, maxit=50, precond="base")
+    xref = np.linalg.solve(_dense_u_matrix(P, dd, coef), rhs)
+    assert st == "ok" and it <= 2 and rel(x.cpu().numpy(), xref) < 1e-11
+
+
+def test_set_box_checks_the_geometry():
+    d = box(seed=3)
+    g = connreg.Problem(d, "fp64", DEV)
+    by = d["box_y"]
+    with pytest.raises(connreg.ConnRegError):
+        g.set_box((by[1], by[0], by[2]))  # same count, other numbering
+    with pytest.raises(connreg.ConnRegError):
+        g.set_box((by[0], by[1], by[2] + 1))
+    s = mid_shell()
+    gs = connreg.Problem(s, "fp64", DEV)
+    with pytest.raises(connreg.ConnRegError):
+        gs.set_box((gs.n_y, 1, 1))
+
+
+def mid_shell():
+    """A target that is not a full box: the box minus one voxel row."""
+    d = box(seed=4)
+    keep = np.ones(len(d["coords_y"]), bool)
+    keep[: d["box_y"][0]] = False
+    cy = d["coords_y"][keep]
+    rp, ci, va = synth.graph_laplacian_csr(cy)
+    d = dict(d)
+    d.update(Ly_rowptr=rp, Ly_colidx=ci, Ly_val=va, coords_y=cy, Y=d["Y"][keep],
+             Omega=d["Omega"][keep])
+    return d
+
+
+@pytest.mark.parametrize("kind", ["base", "learned"])
+def test_greedy_with_flexible_cg_keeps_the_answer(kind):
+    d = box(seed=2)
+    P = oop.problem_from_arrays(d)
+    ores = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(max_rank=6, als_fixed_sweeps=2,
+                                                         u_method="dense", v_method="dense",
+                                                         galerkin="dense", seed=4))
+    g = connreg.Problem(d, "fp64", DEV)
+    g.set_box(d["box_y"])
+    pc = connreg.Pc(d["box_y"], channels=8, seed=9)
+    if kind == "learned":
+        g.set_pc(pc)
+    else:
+        g.set_precond("base")
+    res = g.greedy_solve(max_rank=6, als_fixed_sweeps=2, pcg_rtol=1e-13, pcg_maxit=20000,
+                         galerkin_rtol=1e-13, galerkin_maxit=20000, seed=4)
+    U, V, Z = (res[k].cpu().numpy() for k in ("U", "V", "Z"))
+    err = omet.diff_norm(U, Z, V, ores.U, ores.Z, ores.V) / omet.low_rank_norm(ores.U, ores.Z, ores.V)
+    assert err < 1e-6
+    g.set_pc(None)
+    pc.close()
+
+
+def test_trained_network_gain_over_jacobi(capsys):
+    """The network is trained on u-systems of random low-rank iterates and
+    evaluated on unseen ones: the flexible CG with the trained network needs
+    far fewer iterations than Jacobi-PCG for the same answer.  Iterations of
+    the base step alone are printed beside them (no claim on that ratio)."""
+    d = box(seed=7, by=(12, 10, 8), bx=(8, 6, 6), n_inj=6, lam=1e3)
+    P = oop.problem_from_arrays(d)
+    g = connreg.Problem(d, "fp64", DEV)
+    g.set_box(d["box_y"])
+    rng = np.random.default_rng(31)
+    b, x, dd, cf = _pairs(g, P, rng, 24)
+    pc = connreg.Pc(d["box_y"], channels=8, seed=1)
+    for s in range(150):
+        idx = rng.choice(24, size=8, replace=False)
+        it = torch.tensor(idx, device=DEV)
+        pc.train_step(g, b[it], x[it], dd[it], cf[idx], lr=3e-3 * 0.1 ** (s / 150))
+    eb, ex, ed, ec = _pairs(g, P, np.random.default_rng(77), 6)
+    its = {"jacobi": [], "base": [], "learned": []}
+    for i in range(6):
+        for kind in its:
+            xs, n_it, rr, fb, st = g.u_solve(ed[i], tuple(ec[i]), eb[i], rtol=1e-9, maxit=20000,
+                                             pc=pc if kind == "learned" else None, precond=kind)
+            assert st in ("ok", "pc_fallback") and rr <= 1e-9
+            assert rel(xs.cpu().numpy(), ex[i].cpu().numpy()) < 1e-6
+            its[kind].append(n_it)
+    m = {k: float(np.mean(v)) for k, v in its.items()}
+    with capsys.disabled():
+        print(f"\n[lpc] mean iterations on unseen u-systems: {m}")
+    assert m["learned"] < 0.5 * m["jacobi"]
+    pc.close()
