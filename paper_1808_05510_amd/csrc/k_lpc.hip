@@ -1,7 +1,8 @@
 // Learned preconditioner for the ALS u-system (eq. ALS_linsys) on a box
 // grid: a small two-level 3-D convolutional network trained on the GPU by
 // the kernels below (forward, data gradient, weight gradient, pooling,
-// loss, Adam), applied inside flexible CG with Jacobi as fallback.
+// loss, Adam), applied inside flexible CG with the base step as fallback and
+// Jacobi-PCG as the final judge.
 //
 // Grid: nx * ny * nz voxels, index v = x + nx (y + ny z), the numbering of
 // the box generator.  Activations are channel-major [C][N] float.
@@ -13,14 +14,15 @@
 //   a3 = relu(conv(a2, C -> C))         half
 //   s  = upsample2(a3) + a1             full (nearest, skip connection)
 //   y  = conv(s, C -> 1)                full
-// The network refines the Jacobi step.  With D the Jacobi diagonal of the
-// u-system and w = D^-1 r, the inputs are
+// The network refines the base step w = M^-1 r of the flexible CG (the
+// spectral solve of the box when the target is declared a full box, else the
+// Jacobi step D^-1 r, D the Jacobi diagonal of the u-system).  Its inputs are
 //   [ sqrt(N) w / ||w||,  d / D,  lambda c0 / D,  lambda c1 deg / D ]
 // (the last three are the data, mass and first-order fractions of the
 // diagonal, all in [0, 1]) and the preconditioned residual is
 //   z = sqrt(N) w / ||w|| + y,
-// so an untrained network with a small last layer is the Jacobi step.  FCG
-// is invariant to the scale of z; training minimises 1 - cos^2(z, x*) with x*
+// so an untrained network (zero last layer) returns the base step.  FCG is
+// invariant to the scale of z; training minimises 1 - cos^2(z, x*) with x*
 // the exact solution for right-hand side r.
 #include <hip/hip_runtime.h>
 
