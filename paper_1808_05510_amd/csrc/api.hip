@@ -61,6 +61,11 @@ struct cr_problem {
   int cu_share = 0;         // > 0: persistent grids limited to this many CUs' worth of slots
   int coop = 1;             // persistent kernels launched cooperatively
   int tuned_vpt_u = 0, tuned_vpt_v = 0;  // autotuned PCG voxels per thread (0 = heuristic)
+  // threads per PCG workgroup: 1024 (a quarter of the workgroups, so a quarter
+  // of the arrivals at every grid barrier; measured 5% faster FP64 and 16%
+  // faster mixed solves on the 40^3 / 30^3 problem than 256); CONNREG_PCG_BS=256
+  // restores 256.  Batched solves use 256 (their CU shares are sized for it).
+  int pcg_bs = 1024;
   int bar_mode = 1;
   std::map<std::string, DevBuf> ws;
   std::vector<void*> owned;
@@ -348,7 +353,7 @@ struct Ctx {
   double *y0 = nullptr, *coef = nullptr, *cu = nullptr, *cv = nullptr, *gw = nullptr;
   double *sc = nullptr, *part = nullptr, *pcgpart = nullptr, *sbuf = nullptr, *gpart = nullptr;
   double* tmp = nullptr;
-  int pcg_vpt_u = 1, pcg_vpt_v = 1, pcg_nwg_u = 1, pcg_nwg_v = 1;
+  int pcg_vpt_u = 1, pcg_vpt_v = 1, pcg_nwg_u = 1, pcg_nwg_v = 1, pcg_bs = NT;
   // stats of the last ALS
   int it_u = 0, it_v = 0, notconv = 0;
 
@@ -388,10 +393,11 @@ struct Ctx {
     part = WS(double, "part", pt);
     // PCG grid sizes: the fewest voxels per thread (1, 2, 4, 8) whose grid
     // fits co-resident on the device and stays at or below 512 workgroups.
-    // Measured on the 40^3 / 30^3 problem: one voxel per thread (250 / 106
-    // workgroups) beats fewer, fatter workgroups, whose per-phase latency
-    // grows faster than the grid barrier (3 us at 64, 8 us at 256 groups)
-    // shrinks.
+    // Measured on the 40^3 / 30^3 problem: one voxel per thread beats more
+    // voxels per thread, whose per-phase latency grows faster than the grid
+    // barrier (3 us at 64, 8 us at 256 groups) shrinks; wider workgroups
+    // (pcg_bs) cut the group count without adding work per thread.
+    pcg_bs = P->cu_share > 0 ? NT : P->pcg_bs;
     auto pick = [&](const Geom& g, const T* Xm, int& vpt, int& nwg) -> bool {
       const int tuned = Xm ? P->tuned_vpt_v : P->tuned_vpt_u;
       const int want = vpt_opt > 0 ? vpt_opt : tuned;
@@ -401,9 +407,11 @@ struct Ctx {
         probe.g = g;
         probe.Xm = Xm;
         probe.vpt = v;
+        probe.bs = pcg_bs;
         int maxwg = pcg_max_wg<T>(probe);
         if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
-        const int64_t w = std::max<int64_t>(1, (g.n + (int64_t)NT * v - 1) / ((int64_t)NT * v));
+        const int64_t w =
+            std::max<int64_t>(1, (g.n + (int64_t)pcg_bs * v - 1) / ((int64_t)pcg_bs * v));
         if (maxwg > 0 && w <= maxwg && (w <= 512 || want > 0 || v == 8)) {
           vpt = v;
           nwg = (int)w;
@@ -565,6 +573,7 @@ struct Ctx {
     a.rtol = rtol;
     a.maxit = maxit;
     a.vpt = usys ? pcg_vpt_u : pcg_vpt_v;
+    a.bs = pcg_bs;
     a.bar.bar = P->bar;
     a.bar.mode = P->bar_mode;
     a.bar.coop = P->coop;
@@ -1123,6 +1132,7 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   CR_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
   CR_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
   if (const char* e = std::getenv("CONNREG_OP_FORK")) P->op_fork = std::atoi(e) != 0;
+  if (const char* e = std::getenv("CONNREG_PCG_BS")) P->pcg_bs = std::atoi(e) == NT ? NT : 1024;
   P->ny = d->Ly.n;
   P->nx = d->Lx.n;
   P->ninj = (int)d->n_inj;

@@ -156,6 +156,7 @@ struct PcgArgs {
   double rtol;
   int maxit;
   int vpt;              // voxels per thread
+  int bs = NT;          // threads per workgroup (NT or 1024)
   BarrierArg bar;
 };
 template <typename T>

@@ -22,7 +22,8 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-// Sum of v over the workgroup; result returned to every thread.
+// Sum of v over a workgroup of BS threads; result returned to every thread.
+template <int BS = NT>
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wsum(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -31,16 +32,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < NT / WAVE; ++k) s += red[k];
+  for (int k = 0; k < BS / WAVE; ++k) s += red[k];
   return s;
 }
 
 // Grid total of slot `slot` of the partial array (part[slot*nwg + b]),
 // summed in the same order by every workgroup.
+template <int BS = NT>
 __device__ __forceinline__ double grid_total(const double* part, int slot, int nwg, double* red) {
   double s = 0.0;
-  for (int b = threadIdx.x; b < nwg; b += NT) s += part[(int64_t)slot * nwg + b];
-  return block_sum(s, red);
+  for (int b = threadIdx.x; b < nwg; b += BS) s += part[(int64_t)slot * nwg + b];
+  return block_sum<BS>(s, red);
 }
 
 // ------------------------------------------------------------ grid barrier
@@ -108,12 +110,12 @@ __device__ __forceinline__ double lap(const T* __restrict__ w, const int32_t* __
 }
 
 // partial X^T z over this workgroup's voxels, z staged in LDS
-template <typename T>
+template <typename T, int BS>
 __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, int64_t n, int nwg,
                            double* lrpart) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int per = a.vpt * (NT / WAVE);  // rows per lane
-  for (int al = wv; al < a.ninj; al += NT / WAVE) {
+  const int per = a.vpt * (BS / WAVE);  // rows per lane
+  for (int al = wv; al < a.ninj; al += BS / WAVE) {
     const T* xc = a.Xm + (int64_t)al * a.ldx;
     double acc = 0.0;
     for (int k = 0; k < per; ++k) {
@@ -134,15 +136,15 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // iteration: phase B (q = A p, needs t at neighbours), phase C (x, r, z
 // updates), phase D (p = z + beta p, t = L z + beta t, needs z at
 // neighbours), each ended by a grid barrier.
-template <typename T, int K, bool LR, int VPT>
-__global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
+template <typename T, int K, bool LR, int VPT, int BS>
+__global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   cgrp::grid_group grid = cgrp::this_grid();
-  __shared__ double red[NT / WAVE];
-  __shared__ double zs[NT * VPT];
+  __shared__ double red[BS / WAVE];
+  __shared__ double zs[BS * VPT];
   __shared__ double slr[LR ? PCG_MAX_NINJ : 1];
   const int64_t n = a.g.n;
   const int nwg = gridDim.x;
-  const int64_t lo = (int64_t)blockIdx.x * NT * VPT;
+  const int64_t lo = (int64_t)blockIdx.x * BS * VPT;
   double* part = a.part;
   double* lrpart = a.part + PCG_SLOTS * nwg;
   const double lam = a.lam;
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
   double rz = 0.0, bb = 0.0;
 #pragma unroll
   for (int m = 0; m < VPT; ++m) {
-    const int64_t i = lo + threadIdx.x + NT * m;
+    const int64_t i = lo + threadIdx.x + BS * m;
     ok[m] = i < n;
     double bi = 0.0;
     mi[m] = 0.0;
@@ -179,21 +181,21 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
     p[m] = 0.0;
     t[m] = 0.0;
     if (ok[m]) zg[i] = (T)z[m];
-    zs[threadIdx.x + NT * m] = z[m];
+    zs[threadIdx.x + BS * m] = z[m];
     rz += r[m] * z[m];
     bb += r[m] * r[m];
   }
   __syncthreads();
-  if (LR) lr_partial(a, zs, lo, n, nwg, lrpart);
-  rz = block_sum(rz, red);
-  bb = block_sum(bb, red);
+  if (LR) lr_partial<T, BS>(a, zs, lo, n, nwg, lrpart);
+  rz = block_sum<BS>(rz, red);
+  bb = block_sum<BS>(bb, red);
   if (threadIdx.x == 0) {
     part[1 * nwg + blockIdx.x] = rz;
     part[3 * nwg + blockIdx.x] = bb;
   }
   grid_barrier(a.bar, grid);
-  double rz_cur = grid_total(part, 1, nwg, red);
-  const double bnorm2 = grid_total(part, 3, nwg, red);
+  double rz_cur = grid_total<BS>(part, 1, nwg, red);
+  const double bnorm2 = grid_total<BS>(part, 3, nwg, red);
   int status = 0, it = 0;
   double rr = bnorm2;
   const double tol2 = a.rtol * a.rtol * bnorm2;
@@ -209,14 +211,14 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
         for (int k = 0; k < K; ++k) s -= (double)zg[nb[m][k]];
         p[m] = z[m];
         t[m] = (double)(T)s;
-        tg[lo + threadIdx.x + NT * m] = (T)t[m];
+        tg[lo + threadIdx.x + BS * m] = (T)t[m];
       }
     }
     if (LR) {
       for (int al = blockIdx.x; al < ninj; al += nwg) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nwg; b += NT) s += lrpart[(int64_t)al * nwg + b];
-        s = block_sum(s, red);
+        for (int b = threadIdx.x; b < nwg; b += BS) s += lrpart[(int64_t)al * nwg + b];
+        s = block_sum<BS>(s, red);
         if (threadIdx.x == 0) a.sbuf[al] = s;
       }
     }
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
     for (it = 0; it < a.maxit; ++it) {
       // ---- phase B: q = A p, partial p.q
       if (LR) {
-        for (int al = threadIdx.x; al < ninj; al += NT) slr[al] = a.gw[al] * a.sbuf[al];
+        for (int al = threadIdx.x; al < ninj; al += BS) slr[al] = a.gw[al] * a.sbuf[al];
         __syncthreads();
       }
       double q[VPT];
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
       for (int m = 0; m < VPT; ++m) {
         q[m] = 0.0;
         if (ok[m]) {
-          const int64_t i = lo + threadIdx.x + NT * m;
+          const int64_t i = lo + threadIdx.x + BS * m;
           double lt = (double)K * t[m];
 #pragma unroll
           for (int k = 0; k < K; ++k) lt -= (double)tg[nb[m][k]];
@@ -248,12 +250,12 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
           pq += p[m] * q[m];
         }
       }
-      pq = block_sum(pq, red);
+      pq = block_sum<BS>(pq, red);
       if (threadIdx.x == 0) part[0 * nwg + blockIdx.x] = pq;
       grid_barrier(a.bar, grid);
 
       // ---- phase C: x += alpha p, r -= alpha q, z = M^-1 r
-      const double pq_tot = grid_total(part, 0, nwg, red);
+      const double pq_tot = grid_total<BS>(part, 0, nwg, red);
       if (!(pq_tot > 0.0)) {
         status = 2;
         break;
@@ -266,16 +268,16 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
           x[m] = (double)(T)(x[m] + alpha * p[m]);
           r[m] = (double)(T)(r[m] - alpha * q[m]);
           z[m] = (double)(T)(mi[m] * r[m]);
-          zg[lo + threadIdx.x + NT * m] = (T)z[m];
+          zg[lo + threadIdx.x + BS * m] = (T)z[m];
           rzn += r[m] * z[m];
           rrn += r[m] * r[m];
         }
-        zs[threadIdx.x + NT * m] = z[m];
+        zs[threadIdx.x + BS * m] = z[m];
       }
       __syncthreads();
-      if (LR) lr_partial(a, zs, lo, n, nwg, lrpart);
-      rzn = block_sum(rzn, red);
-      rrn = block_sum(rrn, red);
+      if (LR) lr_partial<T, BS>(a, zs, lo, n, nwg, lrpart);
+      rzn = block_sum<BS>(rzn, red);
+      rrn = block_sum<BS>(rrn, red);
       if (threadIdx.x == 0) {
         part[1 * nwg + blockIdx.x] = rzn;
         part[2 * nwg + blockIdx.x] = rrn;
@@ -283,8 +285,8 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
       grid_barrier(a.bar, grid);
 
       // ---- phase D: beta, convergence, p = z + beta p, t = L z + beta t
-      const double rz_new = grid_total(part, 1, nwg, red);
-      rr = grid_total(part, 2, nwg, red);
+      const double rz_new = grid_total<BS>(part, 1, nwg, red);
+      rr = grid_total<BS>(part, 2, nwg, red);
       if (rr <= tol2) {
         ++it;
         break;
@@ -299,14 +301,14 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
           for (int k = 0; k < K; ++k) lz -= (double)zg[nb[m][k]];
           p[m] = (double)(T)(z[m] + beta * p[m]);
           t[m] = (double)(T)(lz + beta * t[m]);
-          tg[lo + threadIdx.x + NT * m] = (T)t[m];
+          tg[lo + threadIdx.x + BS * m] = (T)t[m];
         }
       }
       if (LR) {
         for (int al = blockIdx.x; al < ninj; al += nwg) {
           double s = 0.0;
-          for (int b = threadIdx.x; b < nwg; b += NT) s += lrpart[(int64_t)al * nwg + b];
-          s = block_sum(s, red);
+          for (int b = threadIdx.x; b < nwg; b += BS) s += lrpart[(int64_t)al * nwg + b];
+          s = block_sum<BS>(s, red);
           if (threadIdx.x == 0) a.sbuf[al] = s + beta * a.sbuf[al];
         }
       }
@@ -319,15 +321,15 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
   double xx = 0.0;
 #pragma unroll
   for (int m = 0; m < VPT; ++m) xx += x[m] * x[m];
-  xx = block_sum(xx, red);
+  xx = block_sum<BS>(xx, red);
   if (threadIdx.x == 0) part[4 * nwg + blockIdx.x] = xx;
   grid_barrier(a.bar, grid);
-  const double xnorm2 = grid_total(part, 4, nwg, red);
+  const double xnorm2 = grid_total<BS>(part, 4, nwg, red);
   const double xn = sqrt(xnorm2);
   const double inv = xn > 0.0 ? 1.0 / xn : 0.0;
 #pragma unroll
   for (int m = 0; m < VPT; ++m) {
-    const int64_t i = lo + threadIdx.x + NT * m;
+    const int64_t i = lo + threadIdx.x + BS * m;
     if (ok[m]) {
       a.x[i] = (T)x[m];
       a.xout[i] = (T)(x[m] * inv);
@@ -341,23 +343,29 @@ __global__ __launch_bounds__(NT) void k_pcg(PcgArgs<T> a) {
   }
 }
 
-template <typename T, int K, bool LR>
-static void* pcg_fn_v(int vpt) {
+template <typename T, int K, bool LR, int BS>
+static void* pcg_fn_vb(int vpt) {
   switch (vpt) {
-    case 1: return (void*)&k_pcg<T, K, LR, 1>;
-    case 2: return (void*)&k_pcg<T, K, LR, 2>;
-    case 4: return (void*)&k_pcg<T, K, LR, 4>;
-    case 8: return (void*)&k_pcg<T, K, LR, 8>;
+    case 1: return (void*)&k_pcg<T, K, LR, 1, BS>;
+    case 2: return (void*)&k_pcg<T, K, LR, 2, BS>;
+    case 4: return (void*)&k_pcg<T, K, LR, 4, BS>;
+    case 8: return (void*)&k_pcg<T, K, LR, 8, BS>;
     default: return nullptr;
   }
 }
 
+template <typename T, int K, bool LR>
+static void* pcg_fn_v(int vpt, int bs) {
+  return bs == 1024 ? pcg_fn_vb<T, K, LR, 1024>(vpt)
+                    : bs == NT ? pcg_fn_vb<T, K, LR, NT>(vpt) : nullptr;
+}
+
 template <typename T>
-static void* pcg_select(int K, bool lr, int vpt) {
+static void* pcg_select(int K, bool lr, int vpt, int bs) {
   switch (K) {
 #define CASE(KK) \
   case KK:       \
-    return lr ? pcg_fn_v<T, KK, true>(vpt) : pcg_fn_v<T, KK, false>(vpt);
+    return lr ? pcg_fn_v<T, KK, true>(vpt, bs) : pcg_fn_v<T, KK, false>(vpt, bs);
     CASE(2) CASE(4) CASE(6) CASE(8)
 #undef CASE
     default:
@@ -367,13 +375,13 @@ static void* pcg_select(int K, bool lr, int vpt) {
 
 template <typename T>
 int pcg_max_wg(const PcgArgs<T>& a) {
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs);
   if (!fn) return 0;
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, NT, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, a.bs, 0) != hipSuccess) return 0;
   return per * ncu;
 }
 
@@ -387,11 +395,11 @@ cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
     set_error("pcg: n_inj above the low-rank limit");
     return CR_EINVAL;
   }
-  if ((int64_t)nwg * NT * a.vpt < a.g.n) {
+  if ((int64_t)nwg * a.bs * a.vpt < a.g.n) {
     set_error("pcg: grid does not cover the voxels");
     return CR_EINVAL;
   }
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs);
   if (!fn) {
     set_error("pcg: unsupported stencil width or voxels per thread");
     return CR_EINVAL;
@@ -400,9 +408,9 @@ cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
   if (arg.bar.mode == 1) CR_HIP(hipMemsetAsync(arg.bar.bar, 0, BAR_WORDS * sizeof(unsigned), st));
   void* params[] = {&arg};
   if (arg.bar.coop || arg.bar.mode == 0)
-    CR_HIP(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(NT), params, 0, st));
+    CR_HIP(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(arg.bs), params, 0, st));
   else
-    CR_HIP(hipLaunchKernel(fn, dim3(nwg), dim3(NT), params, 0, st));
+    CR_HIP(hipLaunchKernel(fn, dim3(nwg), dim3(arg.bs), params, 0, st));
   return CR_OK;
 }
 
