@@ -165,7 +165,9 @@ def bench_learned(d2, lam, opts, steps, warmup, train_seeds=(100, 101), train_st
     workload: the network (spectral base step + 3-D conv refinement) is
     trained on u-systems dumped from FP64 greedy runs of other seeds (same
     grids and lambda); collection and training are timed separately.  The
-    same mixed solve with the spectral base step alone is timed beside it."""
+    same mixed solve with the spectral base step alone is timed beside it.
+    Both declare the source box too, so the v-systems take the SMW direct
+    solve."""
     from paper_1808_05510_amd import lpc_train
     t0 = time.perf_counter()
     parts = []
@@ -186,9 +188,24 @@ def bench_learned(d2, lam, opts, steps, warmup, train_seeds=(100, 101), train_st
     t_train = time.perf_counter() - t0
     out = dict(pairs=len(data), collect_s=t_collect, train_s=t_train, train_steps=train_steps,
                loss_first=hist[0], loss_last=float(np.mean(hist[-20:])))
+    # inner u-solves of the timed workload (a seed unseen in training) to
+    # relres 1e-4, checked in FP64 by the solver's own residual
+    pe = connreg.Problem(d2, "fp64", "cuda:0")
+    pe.set_box(d2["box_y"])
+    ev = lpc_train.collect_pairs(pe, max_rank=20, every=4, perturb=0.3, seed=0)
+    inner = {}
+    for kind in ("jacobi", "base", "learned"):
+        rows = lpc_train.evaluate(pe, ev, pc if kind == "learned" else None, rtol=1e-4,
+                                  precond=kind)
+        inner[kind] = dict(systems=len(rows), mean_iters=float(np.mean([r["iters"] for r in rows])),
+                           mean_ms=1e3 * float(np.mean([r["seconds"] for r in rows])),
+                           max_relres=float(max(r["relres"] for r in rows)))
+    out["inner_u_solves"] = inner
+    pe.close()
     for kind in ("learned", "base"):
         pm = connreg.Problem(d2, "mixed", "cuda:0")
         pm.set_box(d2["box_y"])
+        pm.set_box(d2["box_x"], which="source")
         if kind == "learned":
             pm.set_pc(pc)
         else:
@@ -203,6 +220,27 @@ def bench_learned(d2, lam, opts, steps, warmup, train_seeds=(100, 101), train_st
     for h in handles:
         h.close()
     pc.close()
+    return out
+
+
+def bench_shells(steps=1):
+    """Greedy solve on the cortex-shell workload (plain FP64 and mixed), to
+    relres 1e-4 or the rank cap of 100: one timed solve each after a short
+    warm-up that allocates the workspace."""
+    d3 = synth.config3(seed=0)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        p = connreg.Problem(d3, prec, "cuda:0")
+        p.greedy_solve(max_rank=2, tau_res=1e-4, seed=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = p.greedy_solve(max_rank=int(d3["max_rank"]), tau_res=1e-4, seed=0)
+        torch.cuda.synchronize()
+        out[prec] = dict(seconds=time.perf_counter() - t0, rank=res["rank"],
+                         relres=res["stats"]["relres"], pcg_iters=res["stats"]["pcg_iters"],
+                         reached_tau=bool(res["stats"]["relres"] <= 1e-4),
+                         curve=[[h["rank"], h["relres"], h["seconds"]] for h in res["history"]])
+        p.close()
     return out
 
 
@@ -243,6 +281,7 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="only the 16-problem batch")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-shells", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the solver is a "
@@ -294,6 +333,13 @@ def main():
         log(f"[bench] mixed+learned: {learned['learned']['seconds']:.3f} s/solve "
             f"(base step alone {learned['base']['seconds']:.3f} s; training "
             f"{learned['train_s']:.1f} s on {learned['pairs']} pairs)")
+
+    shells = None
+    if not a.no_shells:
+        log("[bench] greedy solve on the cortex-shell workload (n_y 262,136, n_x 131,068)")
+        shells = bench_shells()
+        log(f"[bench] shells: fp64 {shells['fp64']['seconds']:.2f} s (rank {shells['fp64']['rank']}, "
+            f"relres {shells['fp64']['relres']:.2e}); mixed {shells['mixed']['seconds']:.2f} s")
 
     op = None
     roof = None
@@ -358,6 +404,7 @@ def main():
         "relres_curve": [[h["rank"], h["relres"], h["seconds"]] for h in hist],
         "mixed": mixed,
         "mixed_learned_pc": learned,
+        "shells": shells,
         "op_apply": op,
         "batch": batch,
         "roofline": roof,

@@ -295,14 +295,19 @@ cr_status cr_problem_set_pc(cr_problem* p, cr_pc* pc);
  * other values or 2 without a network. */
 cr_status cr_problem_set_precond(cr_problem* p, int32_t kind);
 
-/* Declares the target grid a full dims[0] x dims[1] x dims[2] box numbered
- * first axis fastest.  Checks the target Laplacian against the box's
- * free-face 7-point Laplacian (CR_EINVAL if it differs) and builds the
- * per-axis DCT-II eigenbases of the path-graph Laplacians, so that the base
- * step of the flexible CG becomes the spectral solve
- *   w = Q diag(1 / (lambda (mu^2 + 2 b mu + a) + mean(d))) Q^T r,
- * exact for the u-system of eq. ALS_linsys when d is constant.  dims [host]. */
-cr_status cr_problem_set_box(cr_problem* p, const int32_t* dims);
+/* Declares the target (which 0) or source (which 1) grid a full
+ * dims[0] x dims[1] x dims[2] box numbered first axis fastest.  Checks the
+ * Laplacian against the box's free-face 7-point Laplacian (CR_EINVAL if it
+ * differs) and builds the per-axis DCT-II eigenbases of the path-graph
+ * Laplacians.  Target: the base step of the flexible CG becomes the spectral
+ * solve w = Q diag(1 / (lambda (mu^2 + 2 b mu + a) + mean(d))) Q^T r, exact
+ * for the u-system of eq. ALS_linsys when d is constant.  Source (with
+ * precond 1 or 2 and n_inj <= 128): the v-systems of eq. ALS_linsys_v are
+ * solved directly by the Sherman-Morrison-Woodbury identity around the
+ * spectral solve of lambda (L_x^2 + 2 c L_x + e I), with FP64 residual
+ * refinement; a solve that misses its tolerance falls back to Jacobi-PCG.
+ * dims [host]. */
+cr_status cr_problem_set_box(cr_problem* p, int32_t which, const int32_t* dims);
 
 /* ---------------------------------------------------------------------------
  * Batched solves and autotuning.

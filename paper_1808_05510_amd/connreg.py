@@ -107,7 +107,7 @@ def load(path: str = LIB_PATH):
                              POINTER(c_int32), POINTER(c_double), POINTER(c_int32)]
     L.cr_problem_set_pc.argtypes = [P, P]
     L.cr_problem_set_precond.argtypes = [P, c_int32]
-    L.cr_problem_set_box.argtypes = [P, POINTER(c_int32)]
+    L.cr_problem_set_box.argtypes = [P, c_int32, POINTER(c_int32)]
     L.cr_pc_create.argtypes = [c_int32, c_int32, c_int32, c_int32, c_uint64, P, POINTER(P)]
     L.cr_pc_destroy.argtypes = [P]
     L.cr_pc_destroy.restype = None
@@ -334,9 +334,10 @@ class Problem:
                                      ctypes.byref(rr), ctypes.byref(fb)))
         return x, it.value, rr.value, fb.value, STATUS_NAMES[s]
 
-    def set_box(self, dims):
-        """Declare the target grid a full box (first axis fastest)."""
-        _check(load().cr_problem_set_box(self.h, (c_int32 * 3)(*[int(v) for v in dims])))
+    def set_box(self, dims, which="target"):
+        """Declare the target or source grid a full box (first axis fastest)."""
+        w = {"target": 0, "source": 1}[which]
+        _check(load().cr_problem_set_box(self.h, w, (c_int32 * 3)(*[int(v) for v in dims])))
 
     def set_precond(self, kind):
         """u-system preconditioner of the greedy solve: "jacobi", "base" or "learned"."""

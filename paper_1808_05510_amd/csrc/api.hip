@@ -57,6 +57,7 @@ struct cr_problem {
   cr_pc* pc = nullptr;      // learned preconditioner for the u-systems (not owned)
   int fcg_mode = 0;         // u-systems: 0 Jacobi-PCG, 1 FCG + base step, 2 FCG + base step + network
   BoxBasis boxy;            // spectral basis of the target grid when it is a full box
+  BoxBasis boxx;            // spectral basis of the source grid when it is a full box
   int64_t pc_fallbacks = 0;
   int cu_share = 0;         // > 0: persistent grids limited to this many CUs' worth of slots
   int coop = 1;             // persistent kernels launched cooperatively
@@ -236,6 +237,11 @@ __global__ void k_axpby(int64_t n, const double* __restrict__ z, double beta,
                         const double* __restrict__ pp, double* __restrict__ p) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = z[i] + beta * pp[i];
+}
+// x += t
+__global__ void k_add_to(int64_t n, const double* __restrict__ t, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += t[i];
 }
 // x += alpha p ; r -= alpha q
 __global__ void k_xr_update(int64_t n, double alpha, const double* __restrict__ p,
@@ -592,6 +598,69 @@ struct Ctx {
     return gemv_t<double>(n, A, b, out, part, st);
   }
 
+  // Direct solve of the v-system (eq. ALS_linsys_v) on a full source box by
+  // the Sherman-Morrison-Woodbury identity with spectral solves (k_spec.hip),
+  // in FP64, followed by up to two refinement steps with the same factors
+  // until the FP64 residual meets rtol.  done = false (nothing written) when
+  // it does not, and the caller falls back to PCG.
+  cr_status smw_v(const T* b, T* xout, double rtol, SolveOut* out, bool& done) {
+    done = false;
+    const int64_t n = nx;
+    double* Y = WS(double, "smw_Y", n * ninj);
+    double* YT = WS(double, "smw_YT", n * ninj);
+    double* Km = WS(double, "smw_K", (int64_t)ninj * ninj);
+    double* h = WS(double, "smw_h", ninj);
+    double* kv = WS(double, "smw_k", ninj);
+    double* b64 = WS(double, "smw_b", n);
+    double* x64 = WS(double, "smw_x", n);
+    double* t64 = WS(double, "smw_t", n);
+    double* r64 = WS(double, "smw_r", n);
+    double* w64 = WS(double, "smw_w", n);
+    const double* X64 = P->X64;
+    CR_TRY((convert2d<double, T>(n, 1, b, n, b64, n, st)));
+    // Y = S^-1 X, K = chol(I + G^1/2 X^T Y G^1/2)
+    CR_TRY(box_spectral_solve_cols(P->boxx, cv, lam, nullptr, ninj, X64, n, Y, n, YT, n, st));
+    Blocks<double> A, B;
+    A.clear();
+    A.add(X64, n, ninj);
+    B.clear();
+    B.add(Y, n, ninj);
+    CR_TRY(gemm_tn<double>(n, A, B, nullptr, nullptr, 0, Km, ninj, gpart, gemm_part_cap(P), st));
+    CR_TRY(smw_factor(ninj, gw, Km, st));
+    // x = 0, r = b; then x += SMW(r), r = b - A x, up to three times
+    CR_HIP(hipMemsetAsync(x64, 0, sizeof(double) * n, st));
+    CR_HIP(hipMemcpyAsync(r64, b64, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    CR_TRY(dot64(n, b64, b64, tmp + 9));
+    double q[2] = {0.0, 0.0};
+    for (int pass = 0; pass < 3; ++pass) {
+      CR_TRY(box_spectral_solve(P->boxx, cv, lam, nullptr, r64, t64, w64, st));
+      CR_TRY((gemv_tx<double, double>(n, A, t64, h, part, st)));
+      CR_TRY(smw_apply(ninj, gw, Km, h, kv, st));
+      CR_TRY(gemv_n<double>(n, B, kv, 1.0, t64, st));  // t - Y G^1/2 K^-1 G^1/2 X^T t
+      hipLaunchKernelGGL(k_add_to, dim3(nblk(n)), dim3(256), 0, st, n, t64, x64);
+      CR_HIP(hipGetLastError());
+      // r = b - A x in FP64 with FP64 operator data
+      CR_TRY((gemv_tx<double, double>(n, A, x64, y0, part, st)));
+      CR_TRY(als_residual<double>(P->gx, lam, cv, nullptr, X64, n, ninj, gw, y0, b64, x64, w64,
+                                  r64, st));
+      CR_TRY(dot64(n, r64, r64, tmp + 10));
+      CR_TRY(read_scalars(tmp + 9, 2, q));
+      if (!std::isfinite(q[1])) return CR_OK;
+      if (q[1] <= rtol * rtol * q[0]) break;
+    }
+    if (!(q[1] <= rtol * rtol * q[0])) return CR_OK;
+    done = true;
+    *out = SolveOut{};
+    out->iters = 1;
+    out->relres = q[0] > 0.0 ? std::sqrt(q[1] / q[0]) : 0.0;
+    CR_TRY(dot64(n, x64, x64, tmp + 11));
+    CR_TRY(normalize_out<T>(n, x64, tmp + 11, xout, st));
+    double hn[1];
+    CR_TRY(read_scalars(tmp + 11, 1, hn));
+    out->norm = std::sqrt(std::max(hn[0], 0.0));
+    return CR_OK;
+  }
+
   // Solve the u-system (usys) or the v-system for b; xout = unit solution.
   // FP64: one PCG launch; its scalars stay in dsc[0..3] for a later read.
   // Mixed: FP32 PCG corrections inside an FP64 residual-and-refinement loop
@@ -629,6 +698,14 @@ struct Ctx {
       CR_TRY(dot64(ny, xs, xs, tmp + 11));
       CR_TRY(normalize_out<T>(ny, xs, tmp + 11, xout, st));
       return CR_OK;
+    }
+    if (!usys && P->fcg_mode > 0 && P->boxx.valid && ninj <= SMW_MAX) {
+      bool done = false;
+      CR_TRY(smw_v(b, xout, rtol, out, done));
+      if (done) {
+        deferred = false;
+        return CR_OK;
+      }
     }
     if (std::is_same<T, double>::value) {
       deferred = true;
@@ -698,7 +775,8 @@ struct Ctx {
   // Jacobi, optionally refined by the learned network (z = network(w));
   // whenever the network's z is not a descent direction (r.z <= 0 or not
   // finite) the iteration uses w instead and counts a fallback.  All scalars
-  // stay on the device; the host checks convergence every 8 iterations.
+  // stay on the device; the host checks convergence after 1, 2, 4, 8, 16
+  // iterations and every 16 after that.
   cr_status fcg_u(const double* b, double* xsol, double rtol, int maxit, SolveOut* out,
                   int* fallbacks, const double* dv, const double* mi, bool use_net) {
     cr_pc* pc = P->pc;
@@ -778,7 +856,10 @@ struct Ctx {
       CR_HIP(hipGetLastError());
       std::swap(p, pp);
       std::swap(q, qq);
-      if ((it & 7) == 7 || it + 1 == maxit) {
+      // host checks after 1, 2, 4, 8, 16 iterations, then every 16: a solve
+      // that converges in a few steps runs at most as many again
+      const int done_its = it + 1;
+      if ((done_its & (done_its - 1)) == 0 || (done_its & 15) == 0 || done_its == maxit) {
         CR_TRY(read_scalars(S, FS_N, h));
         if (h[FS_STATE] != 0.0) break;
       }
@@ -1714,19 +1795,25 @@ extern "C" cr_status cr_problem_set_precond(cr_problem* P, int32_t kind) {
   return CR_OK;
 }
 
-// Target grid as a full d0 x d1 x d2 box (first axis fastest): checks that the
-// Laplacian is the box's free-face 7-point Laplacian, then builds the per-axis
-// DCT-II bases used by the spectral base step.
-extern "C" cr_status cr_problem_set_box(cr_problem* P, const int32_t* dims) {
-  if (!P || !dims || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0 ||
-      (int64_t)dims[0] * dims[1] * dims[2] != P->ny) {
-    set_error("box dimensions must be positive and multiply to the number of target voxels");
+// Target (which 0) or source (which 1) grid as a full d0 x d1 x d2 box
+// (first axis fastest): checks that the Laplacian is the box's free-face
+// 7-point Laplacian, then builds the per-axis DCT-II bases used by the
+// spectral base step (target) and the SMW v-solve (source).
+extern "C" cr_status cr_problem_set_box(cr_problem* P, int32_t which, const int32_t* dims) {
+  if (!P || (which != 0 && which != 1)) {
+    set_error("which must be 0 (target) or 1 (source)");
     return CR_EINVAL;
   }
-  const int64_t n = P->ny;
-  const int K = P->gy.K;
+  const Geom& geo = which == 0 ? P->gy : P->gx;
+  if (!dims || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0 ||
+      (int64_t)dims[0] * dims[1] * dims[2] != geo.n) {
+    set_error("box dimensions must be positive and multiply to the number of voxels");
+    return CR_EINVAL;
+  }
+  const int64_t n = geo.n;
+  const int K = geo.K;
   std::vector<int32_t> nbr((size_t)K * n);
-  CR_HIP(hipMemcpy(nbr.data(), P->gy.nbr, sizeof(int32_t) * nbr.size(), hipMemcpyDeviceToHost));
+  CR_HIP(hipMemcpy(nbr.data(), geo.nbr, sizeof(int32_t) * nbr.size(), hipMemcpyDeviceToHost));
   const int d0 = dims[0], d1 = dims[1], d2 = dims[2];
   for (int64_t i = 0; i < n; ++i) {
     const int i0 = (int)(i % d0), i1 = (int)((i / d0) % d1), i2 = (int)(i / ((int64_t)d0 * d1));
@@ -1745,13 +1832,13 @@ extern "C" cr_status cr_problem_set_box(cr_problem* P, const int32_t* dims) {
       bool found = false;
       for (int m = 0; m < nw; ++m) found = found || want[m] == j;
       if (!found) {
-        set_error("the target Laplacian is not the box's 7-point Laplacian");
+        set_error("the Laplacian is not the box's 7-point Laplacian");
         return CR_EINVAL;
       }
       ++have;
     }
     if (have != nw) {
-      set_error("the target Laplacian is not the box's 7-point Laplacian");
+      set_error("the Laplacian is not the box's 7-point Laplacian");
       return CR_EINVAL;
     }
   }
@@ -1771,7 +1858,7 @@ extern "C" cr_status cr_problem_set_box(cr_problem* P, const int32_t* dims) {
     CR_HIP(hipMemcpy(bx.Q[a], Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
     CR_HIP(hipMemcpy(bx.mu[a], mu.data(), sizeof(double) * m, hipMemcpyHostToDevice));
   }
-  P->boxy = bx;
+  (which == 0 ? P->boxy : P->boxx) = bx;
   return CR_OK;
 }
 

@@ -215,9 +215,19 @@ struct BoxBasis {
   double* Q[3] = {nullptr, nullptr, nullptr};
   double* mu[3] = {nullptr, nullptr, nullptr};
 };
-// out = Q diag(1 / (lam (mu^2 + c[0] mu + c[1]) + dbar[0])) Q^T r; tmp: n doubles
+// out = Q diag(1 / (lam (mu^2 + c[0] mu + c[1]) + dbar[0])) Q^T r; tmp: n doubles;
+// dbar may be null (0).  The _cols form solves ncols columns at once.
 cr_status box_spectral_solve(const BoxBasis& bx, const double* c, double lam, const double* dbar,
                              const double* r, double* out, double* tmp, hipStream_t st);
+cr_status box_spectral_solve_cols(const BoxBasis& bx, const double* c, double lam,
+                                  const double* dbar, int ncols, const double* R, int64_t ldr,
+                                  double* OUT, int64_t ldo, double* TMP, int64_t ldt,
+                                  hipStream_t st);
+// SMW solve of the v-system on a full source box (n_inj <= SMW_MAX)
+constexpr int SMW_MAX = 128;
+cr_status smw_factor(int n, const double* g, double* K, hipStream_t st);
+cr_status smw_apply(int n, const double* g, const double* L, const double* h, double* kvec,
+                    hipStream_t st);
 
 struct LpcNet {
   int nx = 0, ny = 0, nz = 0, C = 0;

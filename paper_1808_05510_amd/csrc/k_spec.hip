@@ -11,6 +11,8 @@
 //     M^-1 r = Q diag(1 / (lam (mu^2 + 2 b mu + a) + dbar)) Q^T r
 // is an SPD approximate inverse, exact where d is constant; it serves as the
 // base step of the flexible CG (alone, or refined by the learned network).
+// On the source box the same transforms solve the v-system exactly through
+// the Sherman-Morrison-Woodbury identity (below).
 #include <hip/hip_runtime.h>
 
 #include "cr_internal.hpp"
@@ -21,13 +23,17 @@ namespace cr {
 //   forward (Q^T):  out[.., k, ..] = sum_j Q[j m + k] in[.., j, ..]
 //   inverse (Q):    out[.., j, ..] = sum_k Q[j m + k] in[.., k, ..]
 // Q is row-major m x m (row = position j, column = mode k).
+// blockIdx.y selects the column of an n x ncols block (leading dimensions
+// ldi, ldo).
 __global__ __launch_bounds__(NT) void k_box_axis(int d0, int d1, int d2, int axis,
                                                  const double* __restrict__ Q, int inverse,
-                                                 const double* __restrict__ in,
-                                                 double* __restrict__ out) {
+                                                 const double* __restrict__ in, int64_t ldi,
+                                                 double* __restrict__ out, int64_t ldo) {
   const int64_t n = (int64_t)d0 * d1 * d2;
   const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (o >= n) return;
+  in += (int64_t)blockIdx.y * ldi;
+  out += (int64_t)blockIdx.y * ldo;
   const int i0 = (int)(o % d0);
   const int64_t rest = o / d0;
   const int i1 = (int)(rest % d1);
@@ -46,41 +52,138 @@ __global__ __launch_bounds__(NT) void k_box_axis(int d0, int d1, int d2, int axi
   out[o] = acc;
 }
 
-// xhat /= lam (mu^2 + c[0] mu + c[1]) + dbar   (c = [2 b, a])
+// xhat /= lam (mu^2 + c[0] mu + c[1]) + dbar   (c = [2 b, a]; dbar may be null: 0)
 __global__ __launch_bounds__(NT) void k_box_scale(int d0, int d1, int d2,
                                                   const double* __restrict__ mu0,
                                                   const double* __restrict__ mu1,
                                                   const double* __restrict__ mu2,
                                                   const double* __restrict__ c, double lam,
                                                   const double* __restrict__ dbar,
-                                                  double* __restrict__ xh) {
+                                                  double* __restrict__ xh, int64_t ld) {
   const int64_t n = (int64_t)d0 * d1 * d2;
   const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (o >= n) return;
+  xh += (int64_t)blockIdx.y * ld;
   const int i0 = (int)(o % d0);
   const int64_t rest = o / d0;
   const int i1 = (int)(rest % d1);
   const int i2 = (int)(rest / d1);
   const double mu = mu0[i0] + mu1[i1] + mu2[i2];
-  const double den = lam * (mu * mu + c[0] * mu + c[1]) + dbar[0];
+  const double den = lam * (mu * mu + c[0] * mu + c[1]) + (dbar ? dbar[0] : 0.0);
   xh[o] = xh[o] / den;
 }
 
 cr_status box_spectral_solve(const BoxBasis& bx, const double* c, double lam, const double* dbar,
                              const double* r, double* out, double* tmp, hipStream_t st) {
   const int64_t n = (int64_t)bx.dims[0] * bx.dims[1] * bx.dims[2];
-  const unsigned g = (unsigned)((n + NT - 1) / NT);
+  return box_spectral_solve_cols(bx, c, lam, dbar, 1, r, n, out, n, tmp, n, st);
+}
+
+cr_status box_spectral_solve_cols(const BoxBasis& bx, const double* c, double lam,
+                                  const double* dbar, int ncols, const double* R, int64_t ldr,
+                                  double* OUT, int64_t ldo, double* TMP, int64_t ldt,
+                                  hipStream_t st) {
+  if (ncols <= 0) return CR_OK;
+  const int64_t n = (int64_t)bx.dims[0] * bx.dims[1] * bx.dims[2];
+  const dim3 g((unsigned)((n + NT - 1) / NT), (unsigned)ncols);
   const int d0 = bx.dims[0], d1 = bx.dims[1], d2 = bx.dims[2];
-  // forward: r -> tmp -> out -> tmp
-  hipLaunchKernelGGL(k_box_axis, dim3(g), dim3(NT), 0, st, d0, d1, d2, 0, bx.Q[0], 0, r, tmp);
-  hipLaunchKernelGGL(k_box_axis, dim3(g), dim3(NT), 0, st, d0, d1, d2, 1, bx.Q[1], 0, tmp, out);
-  hipLaunchKernelGGL(k_box_axis, dim3(g), dim3(NT), 0, st, d0, d1, d2, 2, bx.Q[2], 0, out, tmp);
-  hipLaunchKernelGGL(k_box_scale, dim3(g), dim3(NT), 0, st, d0, d1, d2, bx.mu[0], bx.mu[1],
-                     bx.mu[2], c, lam, dbar, tmp);
-  // inverse: tmp -> out -> tmp -> out
-  hipLaunchKernelGGL(k_box_axis, dim3(g), dim3(NT), 0, st, d0, d1, d2, 2, bx.Q[2], 1, tmp, out);
-  hipLaunchKernelGGL(k_box_axis, dim3(g), dim3(NT), 0, st, d0, d1, d2, 1, bx.Q[1], 1, out, tmp);
-  hipLaunchKernelGGL(k_box_axis, dim3(g), dim3(NT), 0, st, d0, d1, d2, 0, bx.Q[0], 1, tmp, out);
+  // forward: R -> TMP -> OUT -> TMP
+  hipLaunchKernelGGL(k_box_axis, g, dim3(NT), 0, st, d0, d1, d2, 0, bx.Q[0], 0, R, ldr, TMP, ldt);
+  hipLaunchKernelGGL(k_box_axis, g, dim3(NT), 0, st, d0, d1, d2, 1, bx.Q[1], 0, TMP, ldt, OUT, ldo);
+  hipLaunchKernelGGL(k_box_axis, g, dim3(NT), 0, st, d0, d1, d2, 2, bx.Q[2], 0, OUT, ldo, TMP, ldt);
+  hipLaunchKernelGGL(k_box_scale, g, dim3(NT), 0, st, d0, d1, d2, bx.mu[0], bx.mu[1], bx.mu[2], c,
+                     lam, dbar, TMP, ldt);
+  // inverse: TMP -> OUT -> TMP -> OUT
+  hipLaunchKernelGGL(k_box_axis, g, dim3(NT), 0, st, d0, d1, d2, 2, bx.Q[2], 1, TMP, ldt, OUT, ldo);
+  hipLaunchKernelGGL(k_box_axis, g, dim3(NT), 0, st, d0, d1, d2, 1, bx.Q[1], 1, OUT, ldo, TMP, ldt);
+  hipLaunchKernelGGL(k_box_axis, g, dim3(NT), 0, st, d0, d1, d2, 0, bx.Q[0], 1, TMP, ldt, OUT, ldo);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ---------------------------------------------------------------- v-system by SMW
+// The v-system of eq. ALS_linsys_v is S + X G X^T with S = lam (L_x^2 + 2 c L_x
+// + e I), diagonal in the source box's basis, and G = diag(g), g >= 0.  With
+// W = X G^1/2, the Sherman-Morrison-Woodbury identity gives
+//   (S + W W^T)^-1 b = t - Y G^1/2 K^-1 G^1/2 X^T t,
+//   t = S^-1 b,  Y = S^-1 X,  K = I + G^1/2 X^T Y G^1/2  (SPD, n_inj x n_inj),
+// the paper's SMW route for this system with the spectral solve in place of
+// a sparse factorisation.  K is factored (Cholesky) by one workgroup in LDS.
+
+// K (n x n, column-major, holds X^T Y on entry) <- lower Cholesky factor of
+// I + G^1/2 sym(X^T Y) G^1/2; a non-positive pivot leaves NaN in the factor
+// (the caller's residual check then rejects the solve).
+__global__ __launch_bounds__(NT) void k_smw_factor(int n, const double* __restrict__ g,
+                                                   double* __restrict__ K) {
+  __shared__ double A[SMW_MAX][SMW_MAX + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += NT) {
+    const int i = e % n, j = e / n;
+    const double v = 0.5 * (K[(int64_t)j * n + i] + K[(int64_t)i * n + j]);
+    A[i][j] = sqrt(g[i] * g[j]) * v + (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double d = A[k][k];
+      A[k][k] = d > 0.0 ? sqrt(d) : __builtin_nan("");
+    }
+    __syncthreads();
+    const double dk = A[k][k];
+    for (int i = k + 1 + tid; i < n; i += NT) A[i][k] /= dk;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int e = tid; e < m * m; e += NT) {
+      const int i = k + 1 + e % m, j = k + 1 + e / m;
+      if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += NT) {
+    const int i = e % n, j = e / n;
+    K[(int64_t)j * n + i] = j <= i ? A[i][j] : 0.0;
+  }
+}
+
+// kvec = -G^1/2 K^-1 G^1/2 h with K = L L^T (L from k_smw_factor)
+__global__ __launch_bounds__(NT) void k_smw_apply(int n, const double* __restrict__ g,
+                                                  const double* __restrict__ L,
+                                                  const double* __restrict__ h,
+                                                  double* __restrict__ kvec) {
+  __shared__ double z[SMW_MAX];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += NT) z[i] = sqrt(g[i]) * h[i];
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {  // L y = z
+    if (tid == 0) z[j] /= L[(int64_t)j * n + j];
+    __syncthreads();
+    const double zj = z[j];
+    for (int i = j + 1 + tid; i < n; i += NT) z[i] -= L[(int64_t)j * n + i] * zj;
+    __syncthreads();
+  }
+  for (int j = n - 1; j >= 0; --j) {  // L^T w = y
+    if (tid == 0) z[j] /= L[(int64_t)j * n + j];
+    __syncthreads();
+    const double zj = z[j];
+    for (int i = tid; i < j; i += NT) z[i] -= L[(int64_t)i * n + j] * zj;
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += NT) kvec[i] = -sqrt(g[i]) * z[i];
+}
+
+cr_status smw_factor(int n, const double* g, double* K, hipStream_t st) {
+  if (n < 1 || n > SMW_MAX) {
+    set_error("SMW factor: n_inj out of range");
+    return CR_EINVAL;
+  }
+  hipLaunchKernelGGL(k_smw_factor, dim3(1), dim3(NT), 0, st, n, g, K);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+cr_status smw_apply(int n, const double* g, const double* L, const double* h, double* kvec,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_smw_apply, dim3(1), dim3(NT), 0, st, n, g, L, h, kvec);
   CR_HIP(hipGetLastError());
   return CR_OK;
 }

@@ -79,14 +79,16 @@ def train(pc: connreg.Pc, prob: connreg.Problem, data: Pairs, steps: int, batch:
     return hist
 
 
-def evaluate(prob: connreg.Problem, data: Pairs, pc: connreg.Pc | None, rtol: float = 1e-8):
-    """Iterations, seconds and final relative residual per system."""
+def evaluate(prob: connreg.Problem, data: Pairs, pc: connreg.Pc | None, rtol: float = 1e-8,
+             precond: str | None = None):
+    """Iterations, seconds and final relative residual per system (precond as
+    in Problem.u_solve)."""
     out = []
     for i in range(len(data)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, it, rr, fb, st = prob.u_solve(data.d[i], tuple(data.coef[i]), data.b[i], rtol=rtol,
-                                         maxit=50000, pc=pc)
+                                         maxit=50000, pc=pc, precond=precond)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         err = float((x - data.x[i]).norm() / data.x[i].norm())

@@ -172,6 +172,12 @@ def test_set_box_checks_the_geometry():
         g.set_box((by[1], by[0], by[2]))  # same count, other numbering
     with pytest.raises(connreg.ConnRegError):
         g.set_box((by[0], by[1], by[2] + 1))
+    bx = d["box_x"]
+    g.set_box(bx, which="source")
+    with pytest.raises(connreg.ConnRegError):
+        g.set_box((bx[2], bx[1], bx[0]) if bx[0] != bx[2] else (bx[1], bx[0], bx[2]), which="source")
+    with pytest.raises(connreg.ConnRegError):
+        g.set_box(by, which="source")
     s = mid_shell()
     gs = connreg.Problem(s, "fp64", DEV)
     with pytest.raises(connreg.ConnRegError):
@@ -191,8 +197,10 @@ def mid_shell():
     return d
 
 
+@pytest.mark.parametrize("source_box", [False, True])
 @pytest.mark.parametrize("kind", ["base", "learned"])
-def test_greedy_with_flexible_cg_keeps_the_answer(kind):
+def test_greedy_with_flexible_cg_keeps_the_answer(kind, source_box):
+    """With the source declared a box, the v-systems take the SMW direct solve."""
     d = box(seed=2)
     P = oop.problem_from_arrays(d)
     ores = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(max_rank=6, als_fixed_sweeps=2,
@@ -200,6 +208,8 @@ def test_greedy_with_flexible_cg_keeps_the_answer(kind):
                                                          galerkin="dense", seed=4))
     g = connreg.Problem(d, "fp64", DEV)
     g.set_box(d["box_y"])
+    if source_box:
+        g.set_box(d["box_x"], which="source")
     pc = connreg.Pc(d["box_y"], channels=8, seed=9)
     if kind == "learned":
         g.set_pc(pc)
