@@ -58,6 +58,7 @@ struct cr_problem {
   int fcg_mode = 0;         // u-systems: 0 Jacobi-PCG, 1 FCG + base step, 2 FCG + base step + network
   BoxBasis boxy;            // spectral basis of the target grid when it is a full box
   BoxBasis boxx;            // spectral basis of the source grid when it is a full box
+  bool kr_omega_ready = false;  // workspace "kraux" holds the BF16 copy of Omega
   int64_t pc_fallbacks = 0;
   int cu_share = 0;         // > 0: persistent grids limited to this many CUs' worth of slots
   int coop = 1;             // persistent kernels launched cooperatively
@@ -2022,7 +2023,17 @@ extern "C" cr_status cr_masked_gram(cr_problem* P, int64_t r, const double* U, i
   if (mode == 1) {
     float* part = P->buf<float>("krpart", kr_gram_part_size(P->ny, (int)r, P->ninj));
     if (!part) return CR_ENOMEM;
-    return kr_gram_bf16<double>(P->ny, (int)r, P->ninj, U, ldu, P->bits, G, ldg, part, P->st);
+    // the BF16 copy of Omega survives between calls (the block list behind it
+    // is rewritten every call); a reallocation (larger r) rebuilds it
+    const int64_t aux_bytes = kr_gram_aux_size(P->ny, (int)r, P->ninj);
+    const bool ready = P->ws.count("kraux") && P->ws["kraux"].bytes >= (size_t)aux_bytes &&
+                       P->kr_omega_ready;
+    char* aux = P->buf<char>("kraux", aux_bytes);
+    if (!aux) return CR_ENOMEM;
+    const cr_status s = kr_gram_bf16<double>(P->ny, (int)r, P->ninj, U, ldu, P->bits, G, ldg,
+                                             part, aux, ready, P->st);
+    P->kr_omega_ready = s == CR_OK;
+    return s;
   }
   Ctx<double> c(P);
   CR_TRY(c.alloc_rank((int)r));

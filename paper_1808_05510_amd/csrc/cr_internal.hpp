@@ -258,10 +258,15 @@ cr_status lpc_loss(const LpcNet& net, const float* in0, const float* y, const do
 cr_status lpc_adam(LpcNet& net, float lr, float scale, hipStream_t st);
 
 // ---------------------------------------------------------------- BF16 Khatri-Rao Grams
+// part: kr_gram_part_size floats; aux: kr_gram_aux_size bytes holding the BF16
+// copy of Omega (built when omega_ready is false, reusable afterwards) and the
+// block list
 int64_t kr_gram_part_size(int64_t n, int r, int ninj);
+int64_t kr_gram_aux_size(int64_t n, int r, int ninj);
 template <typename TU>
 cr_status kr_gram_bf16(int64_t n, int r, int ninj, const TU* U, int64_t ldu, const uint32_t* bits,
-                       double* G, int64_t ldr, float* part, hipStream_t st);
+                       double* G, int64_t ldr, float* part, void* aux, bool omega_ready,
+                       hipStream_t st);
 
 // ---------------------------------------------------------------- small ops
 // out[i] = sum_k M[i + k*ldm] * v[k] * alpha  (i < m, k < kk), single block
