@@ -32,6 +32,14 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+static bool poison_workspace() {
+  static const bool v = [] {
+    const char* e = std::getenv("CONNREG_POISON");
+    return e && std::atoi(e) != 0;
+  }();
+  return v;
+}
+
 struct cr_problem {
   hipStream_t st = nullptr;
   hipStream_t aux = nullptr;  // library-owned second stream (default priority) for fork/join
@@ -68,6 +76,7 @@ struct cr_problem {
   // faster mixed solves on the 40^3 / 30^3 problem than 256); CONNREG_PCG_BS=256
   // restores 256.  Batched solves use 256 (their CU shares are sized for it).
   int pcg_bs = 1024;
+  bool no_xreg = false;     // CONNREG_PCG_XREG=0: v-system PCG streams X (no register-resident rows)
   int bar_mode = 1;
   std::map<std::string, DevBuf> ws;
   std::vector<void*> owned;
@@ -90,6 +99,9 @@ struct cr_problem {
       return nullptr;
     }
     b.bytes = need;
+    // CONNREG_POISON=1: fill new workspace with NaN bytes, so that a read of
+    // workspace the library never wrote shows up in results (checking aid)
+    if (poison_workspace()) (void)hipMemsetAsync(b.p, 0xFF, need, st);
     return (T*)b.p;
   }
   template <typename T>
@@ -361,6 +373,7 @@ struct Ctx {
   double *sc = nullptr, *part = nullptr, *pcgpart = nullptr, *sbuf = nullptr, *gpart = nullptr;
   double* tmp = nullptr;
   int pcg_vpt_u = 1, pcg_vpt_v = 1, pcg_nwg_u = 1, pcg_nwg_v = 1, pcg_bs = NT;
+  int pcg_bs_v = NT, pcg_nxr_v = 0;  // v-system: X rows in registers when n_inj <= PCG_NXR
   // stats of the last ALS
   int it_u = 0, it_v = 0, notconv = 0;
 
@@ -414,11 +427,11 @@ struct Ctx {
         probe.g = g;
         probe.Xm = Xm;
         probe.vpt = v;
-        probe.bs = pcg_bs;
+        const int bs = Xm ? pcg_bs_v : pcg_bs;
+        probe.bs = bs;
         int maxwg = pcg_max_wg<T>(probe);
         if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
-        const int64_t w =
-            std::max<int64_t>(1, (g.n + (int64_t)pcg_bs * v - 1) / ((int64_t)pcg_bs * v));
+        const int64_t w = std::max<int64_t>(1, (g.n + (int64_t)bs * v - 1) / ((int64_t)bs * v));
         if (maxwg > 0 && w <= maxwg && (w <= 512 || want > 0 || v == 8)) {
           vpt = v;
           nwg = (int)w;
@@ -431,7 +444,35 @@ struct Ctx {
       set_error("pcg_vpt must be 0 (auto), 1, 2, 4 or 8");
       return CR_EINVAL;
     }
-    if (!pick(P->gy, nullptr, pcg_vpt_u, pcg_nwg_u) || !pick(P->gx, X(), pcg_vpt_v, pcg_nwg_v)) {
+    // v-system: X rows in registers (256-thread groups, one voxel per thread)
+    // when n_inj fits and the grid fits, else the general kernel with the
+    // default group size (measured on the shells: 256-thread groups there cost
+    // more in barrier arrivals than the 1024-thread kernel's register spills)
+    pcg_bs_v = pcg_bs;
+    pcg_nxr_v = 0;
+    {
+      const int tuned = P->tuned_vpt_v;
+      const int want = vpt_opt > 0 ? vpt_opt : tuned;
+      if (ninj <= PCG_NXR && want <= 1 && !P->no_xreg) {
+        PcgArgs<T> probe{};
+        probe.g = P->gx;
+        probe.Xm = X();
+        probe.vpt = 1;
+        probe.bs = NT;
+        probe.nxr = PCG_NXR;
+        int maxwg = pcg_max_wg<T>(probe);
+        if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
+        const int64_t w = std::max<int64_t>(1, (nx + NT - 1) / NT);
+        if (maxwg > 0 && w <= maxwg) {
+          pcg_vpt_v = 1;
+          pcg_nwg_v = (int)w;
+          pcg_bs_v = NT;
+          pcg_nxr_v = PCG_NXR;
+        }
+      }
+    }
+    if (!pick(P->gy, nullptr, pcg_vpt_u, pcg_nwg_u) ||
+        (pcg_nxr_v == 0 && !pick(P->gx, X(), pcg_vpt_v, pcg_nwg_v))) {
       set_error("problem too large for one cooperative PCG grid");
       return CR_EINVAL;
     }
@@ -580,7 +621,8 @@ struct Ctx {
     a.rtol = rtol;
     a.maxit = maxit;
     a.vpt = usys ? pcg_vpt_u : pcg_vpt_v;
-    a.bs = pcg_bs;
+    a.bs = usys ? pcg_bs : pcg_bs_v;
+    a.nxr = usys ? 0 : pcg_nxr_v;
     a.bar.bar = P->bar;
     a.bar.mode = P->bar_mode;
     a.bar.coop = P->coop;
@@ -766,10 +808,6 @@ struct Ctx {
     return CR_OK;
   }
 
-  // Flexible CG (Notay, one stored direction) on the u-system with the
-  // network as preconditioner; z = M r falls back to the Jacobi step when
-  // <r, z> <= 0 or is not finite.  FP64 vectors, host-side scalars.
-  // Writes the solution into xsol (not normalised).
   // Flexible CG (one previous direction kept, Notay's FCG(1)) on the u-system
   // of eq. ALS_linsys.  The preconditioner is a base step w = M^-1 r, the
   // spectral solve of the box when the target grid is a full box, else
@@ -1215,6 +1253,7 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   CR_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
   if (const char* e = std::getenv("CONNREG_OP_FORK")) P->op_fork = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_PCG_BS")) P->pcg_bs = std::atoi(e) == NT ? NT : 1024;
+  if (const char* e = std::getenv("CONNREG_PCG_XREG")) P->no_xreg = std::atoi(e) == 0;
   P->ny = d->Ly.n;
   P->nx = d->Lx.n;
   P->ninj = (int)d->n_inj;

@@ -157,8 +157,10 @@ struct PcgArgs {
   int maxit;
   int vpt;              // voxels per thread
   int bs = NT;          // threads per workgroup (NT or 1024)
+  int nxr = 0;          // PCG_NXR: X rows in registers (low-rank term, vpt 1, bs NT)
   BarrierArg bar;
 };
+constexpr int PCG_NXR = 64;  // injections held in registers by the X-resident PCG
 template <typename T>
 cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st);
 template <typename T>

@@ -652,10 +652,17 @@ __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
       }
     }
   };
-  loadB(tile, b);
   const uint32_t* wbits = bits + (int64_t)(a0 >> 5) * n;
+  // mask word of a tile's voxel (clamped: always in bounds)
+  auto loadW = [&](int64_t tl) {
+    const int64_t v = tl * 16 + fr;
+    return wbits[v < n ? v : n - 1];
+  };
+  loadB(tile, b);
+  uint32_t wd = loadW(tile), wdn = 0u;
   for (; tile < ntile; tile += stride) {
     const bool more = tile + stride < ntile;
+    if (more) wdn = loadW(tile + stride);
     if (PF && more) loadB(tile + stride, bn);
     acc_t acc0 = acc_t{0, 0, 0, 0}, acc1 = acc_t{0, 0, 0, 0};
 #pragma unroll
@@ -663,9 +670,11 @@ __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
       acc0 = Mfma16<T>::mma(a[0][ks], b[ks], acc0);
       acc1 = Mfma16<T>::mma(a[1][ks], b[ks], acc1);
     }
+    // without a second buffer, the next tile's fragments are requested as
+    // soon as the MFMAs have been issued, so they load during the stores
+    if (!PF && more) loadB(tile + stride, b);
     const int64_t v = tile * 16 + fr;
     if (v < n) {
-      const uint32_t wd = wbits[v];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
 #pragma unroll
@@ -681,11 +690,10 @@ __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
       }
     }
     if (more) {
+      wd = wdn;
       if (PF) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
-      } else {
-        loadB(tile + stride, b);
       }
     }
   }

@@ -136,12 +136,17 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // iteration: phase B (q = A p, needs t at neighbours), phase C (x, r, z
 // updates), phase D (p = z + beta p, t = L z + beta t, needs z at
 // neighbours), each ended by a grid barrier.
-template <typename T, int K, bool LR, int VPT, int BS>
+// NXR > 0 (low-rank term, one voxel per thread, n_inj <= NXR): each thread
+// keeps its voxel's row of X in registers, so the X^T z partials and the
+// X (g o s) products read no memory.
+template <typename T, int K, bool LR, int VPT, int BS, int NXR>
 __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
+  static_assert(NXR == 0 || (LR && VPT == 1), "register-resident X needs LR and VPT 1");
   cgrp::grid_group grid = cgrp::this_grid();
   __shared__ double red[BS / WAVE];
   __shared__ double zs[BS * VPT];
   __shared__ double slr[LR ? PCG_MAX_NINJ : 1];
+  __shared__ double lred[NXR > 0 ? BS / WAVE : 1][NXR > 0 ? NXR : 1];
   const int64_t n = a.g.n;
   const int nwg = gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * BS * VPT;
@@ -154,6 +159,35 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   const T* __restrict__ Xm = a.Xm;
   const int64_t ldx = a.ldx;
   const int ninj = a.ninj;
+
+  double xr[NXR > 0 ? NXR : 1];
+  if (NXR > 0) {
+    const int64_t i0 = lo + threadIdx.x;
+#pragma unroll
+    for (int al = 0; al < NXR; ++al)
+      xr[al] = (i0 < n && al < ninj) ? (double)Xm[(int64_t)al * ldx + i0] : 0.0;
+    for (int al = threadIdx.x; al < NXR; al += BS) slr[al] = 0.0;
+  }
+  // per-workgroup partials of X^T z into lrpart (z of this thread's voxels)
+  auto lr_part = [&](const double* zv) {
+    if (NXR > 0) {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+      for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) {
+        const double v = wsum(xr[al] * zv[0]);
+        if (lane == 0) lred[wv][al] = v;
+      }
+      __syncthreads();
+      for (int al = threadIdx.x; al < ninj; al += BS) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < BS / WAVE; ++w) t += lred[w][al];
+        lrpart[(int64_t)al * nwg + blockIdx.x] = t;
+      }
+    } else {
+      lr_partial<T, BS>(a, zs, lo, n, nwg, lrpart);
+    }
+  };
 
   int32_t nb[VPT][K];
   double x[VPT], r[VPT], z[VPT], p[VPT], t[VPT], mi[VPT], dd[VPT];
@@ -186,7 +220,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
     bb += r[m] * r[m];
   }
   __syncthreads();
-  if (LR) lr_partial<T, BS>(a, zs, lo, n, nwg, lrpart);
+  if (LR) lr_part(z);
   rz = block_sum<BS>(rz, red);
   bb = block_sum<BS>(bb, red);
   if (threadIdx.x == 0) {
@@ -243,7 +277,12 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
           double qi = lam * (lt + c1 * t[m] + c0 * p[m]) + dd[m] * p[m];
           if (LR) {
             double s = 0.0;
-            for (int al = 0; al < ninj; ++al) s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
+            if (NXR > 0) {
+#pragma unroll
+              for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) s += xr[al] * slr[al];
+            } else {
+              for (int al = 0; al < ninj; ++al) s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
+            }
             qi += s;
           }
           q[m] = (double)(T)qi;
@@ -275,7 +314,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         zs[threadIdx.x + BS * m] = z[m];
       }
       __syncthreads();
-      if (LR) lr_partial<T, BS>(a, zs, lo, n, nwg, lrpart);
+      if (LR) lr_part(z);
       rzn = block_sum<BS>(rzn, red);
       rrn = block_sum<BS>(rrn, red);
       if (threadIdx.x == 0) {
@@ -346,26 +385,29 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
 template <typename T, int K, bool LR, int BS>
 static void* pcg_fn_vb(int vpt) {
   switch (vpt) {
-    case 1: return (void*)&k_pcg<T, K, LR, 1, BS>;
-    case 2: return (void*)&k_pcg<T, K, LR, 2, BS>;
-    case 4: return (void*)&k_pcg<T, K, LR, 4, BS>;
-    case 8: return (void*)&k_pcg<T, K, LR, 8, BS>;
+    case 1: return (void*)&k_pcg<T, K, LR, 1, BS, 0>;
+    case 2: return (void*)&k_pcg<T, K, LR, 2, BS, 0>;
+    case 4: return (void*)&k_pcg<T, K, LR, 4, BS, 0>;
+    case 8: return (void*)&k_pcg<T, K, LR, 8, BS, 0>;
     default: return nullptr;
   }
 }
 
 template <typename T, int K, bool LR>
-static void* pcg_fn_v(int vpt, int bs) {
+static void* pcg_fn_v(int vpt, int bs, int nxr) {
+  if (nxr > 0)  // register-resident X: one voxel per thread, 256-thread groups
+    return (LR && vpt == 1 && bs == NT && nxr == PCG_NXR) ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR>
+                                                         : nullptr;
   return bs == 1024 ? pcg_fn_vb<T, K, LR, 1024>(vpt)
                     : bs == NT ? pcg_fn_vb<T, K, LR, NT>(vpt) : nullptr;
 }
 
 template <typename T>
-static void* pcg_select(int K, bool lr, int vpt, int bs) {
+static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr) {
   switch (K) {
 #define CASE(KK) \
   case KK:       \
-    return lr ? pcg_fn_v<T, KK, true>(vpt, bs) : pcg_fn_v<T, KK, false>(vpt, bs);
+    return lr ? pcg_fn_v<T, KK, true>(vpt, bs, nxr) : pcg_fn_v<T, KK, false>(vpt, bs, nxr);
     CASE(2) CASE(4) CASE(6) CASE(8)
 #undef CASE
     default:
@@ -375,7 +417,7 @@ static void* pcg_select(int K, bool lr, int vpt, int bs) {
 
 template <typename T>
 int pcg_max_wg(const PcgArgs<T>& a) {
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr);
   if (!fn) return 0;
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -399,7 +441,7 @@ cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
     set_error("pcg: grid does not cover the voxels");
     return CR_EINVAL;
   }
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr);
   if (!fn) {
     set_error("pcg: unsupported stencil width or voxels per thread");
     return CR_EINVAL;
