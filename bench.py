@@ -247,21 +247,35 @@ def bench_shells(steps=1):
 def cpu_baseline(d, lam, ranks_needed, sample_ranks):
     """FP64 oracle (NumPy/SciPy, Jacobi-CG inner solves) on the first
     ``sample_ranks`` greedy steps of the same workload; seconds per rank times
-    the ranks the GPU needed."""
+    the ranks the GPU needed.  Also: the same sample's first rank on one host
+    thread, and the full 1-D toy solve (rank 20, dense inner solves)."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import greedy as ogreedy
     from oracle import operator as oop
     P = oop.problem_from_arrays(d, lam=lam)
+    opts = dict(u_method="cg", v_method="cg", inner_rtol=1e-8, galerkin="dense", tau_res=1e-4)
     t0 = time.perf_counter()
-    res = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(
-        max_rank=sample_ranks, u_method="cg", v_method="cg", inner_rtol=1e-8, galerkin="dense",
-        tau_res=1e-4))
+    res = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(max_rank=sample_ranks, **opts))
     dt = time.perf_counter() - t0
     per_rank = dt / max(1, len(res.history))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ogreedy.greedy_solve(P, ogreedy.GreedyOptions(max_rank=1, **opts))
+        one_thread_rank = time.perf_counter() - t0
+    d1 = synth.config1()
+    P1 = oop.problem_from_arrays(d1)
+    t0 = time.perf_counter()
+    r1 = ogreedy.greedy_solve(P1, ogreedy.GreedyOptions(
+        max_rank=int(d1["max_rank"]), tau_res=float(d1["tau_res"]), u_method="dense",
+        v_method="dense", galerkin="dense"))
+    toy_s = time.perf_counter() - t0
     return dict(value=per_rank * ranks_needed, unit="s", cores=os.cpu_count(), kind="oracle",
                 sample=f"first {len(res.history)} greedy ranks of the same workload on the host "
                        f"({dt:.1f} s, {per_rank:.2f} s/rank), scaled by the {ranks_needed} ranks "
                        f"the GPU solve needed (extrapolated; later ranks cost more on the CPU)",
-                seconds_per_rank=per_rank)
+                seconds_per_rank=per_rank, one_thread_first_rank_s=one_thread_rank,
+                toy_1d_full_solve_s=toy_s, toy_1d_rank=len(r1.history))
 
 
 def main():
