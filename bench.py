@@ -123,9 +123,10 @@ def bench_gram(d, r, reps, warm):
                 frac=flops / med / 1e12 / BF16_PEAK_TFLOPS)
 
 
-def bench_batch(count=16, max_rank=40, tau=1e-4, prec="mixed"):
+def bench_batch(count=16, max_rank=40, tau=1e-4, prec="mixed", precond="jacobi"):
     """The uneven 16-problem batch: each problem solved on its own (full
-    device), then all at once through cr_greedy_solve_batch."""
+    device), then all at once through cr_greedy_solve_batch.  precond "base"
+    declares both grids boxes (spectral u-steps, SMW v-solves)."""
     specs = synth.config4_specs(0, count)
     t0 = time.perf_counter()
     datas = [synth.box_problem(box_y=s.box_y, box_x=s.box_x,
@@ -135,6 +136,11 @@ def bench_batch(count=16, max_rank=40, tau=1e-4, prec="mixed"):
     gen = time.perf_counter() - t0
     streams = [torch.cuda.Stream() for _ in datas]
     probs = [connreg.Problem(d, prec, "cuda:0", stream=st) for d, st in zip(datas, streams)]
+    if precond != "jacobi":
+        for d, p in zip(datas, probs):
+            p.set_box(d["box_y"])
+            p.set_box(d["box_x"], which="source")
+            p.set_precond(precond)
     opts = dict(max_rank=max_rank, tau_res=tau, seed=0)
     # warm-up (workspace allocation) then sequential timing
     connreg.greedy_solve_batch(probs[:1], [dict(opts, max_rank=2)])
@@ -149,8 +155,8 @@ def bench_batch(count=16, max_rank=40, tau=1e-4, prec="mixed"):
     bat = connreg.greedy_solve_batch(probs, [opts] * len(probs))
     torch.cuda.synchronize()
     t_bat = time.perf_counter() - t0
-    out = dict(problems=count, precision=prec, generation_s=gen, sequential_s=t_seq,
-               batched_s=t_bat, speedup=t_seq / t_bat,
+    out = dict(problems=count, precision=prec, precond=precond, generation_s=gen,
+               sequential_s=t_seq, batched_s=t_bat, speedup=t_seq / t_bat,
                sizes=[[p.n_y, p.n_x, p.n_inj] for p in probs],
                ranks_seq=[r["rank"] for r in seq], ranks_batch=[r["rank"] for r in bat],
                relres_seq=[r["stats"]["relres"] for r in seq],
@@ -305,8 +311,9 @@ def main():
     connreg.load()
 
     if a.batch_only:
-        b = bench_batch()
-        log(json.dumps(b))
+        for pre in ("jacobi", "base"):
+            b = bench_batch(precond=pre)
+            log(json.dumps(b))
         return
     if a.op_only:
         d3 = synth.config3(seed=0)
@@ -384,6 +391,10 @@ def main():
         batch = bench_batch()
         log(f"[bench] batch: sequential {batch['sequential_s']:.2f} s, batched "
             f"{batch['batched_s']:.2f} s, speedup {batch['speedup']:.2f}")
+        bb = bench_batch(precond="base")
+        batch["with_base_step"] = bb
+        log(f"[bench] batch with spectral/SMW solves: sequential {bb['sequential_s']:.2f} s, "
+            f"batched {bb['batched_s']:.2f} s, speedup {bb['speedup']:.2f}")
 
     cpu = None
     if not a.no_cpu:
