@@ -295,7 +295,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-op", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--op-reps", type=int, default=30)
+    ap.add_argument("--op-reps", type=int, default=100)
+    ap.add_argument("--op-warm", type=int, default=20)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--op-only", action="store_true", help="only the op_apply bandwidth part")
     ap.add_argument("--batch-only", action="store_true", help="only the 16-problem batch")
@@ -318,7 +319,7 @@ def main():
     if a.op_only:
         d3 = synth.config3(seed=0)
         for fp32 in (False, True):
-            o = bench_op_apply(d3, 100, a.op_reps, 5, fp32)
+            o = bench_op_apply(d3, 100, a.op_reps, a.op_warm, fp32)
             log(f"[bench] op_apply {o['dtype']} r=100: {o['seconds']*1e6:.1f} us, {o['GBps']:.0f} GB/s")
         for r in (60, 100):
             o = bench_gram(d3, r, 10, 3)
@@ -370,7 +371,7 @@ def main():
         op = {}
         for fp32 in (False, True):
             for r in (20, 60, 100):
-                o = bench_op_apply(d3, r, a.op_reps, 5, fp32)
+                o = bench_op_apply(d3, r, a.op_reps, a.op_warm, fp32)
                 op[f"{o['dtype']}_r{r}"] = o
                 log(f"[bench] op_apply {o['dtype']} r={r}: {o['seconds']*1e6:.1f} us, "
                     f"{o['GBps']:.0f} GB/s ({100*o['frac']:.1f}% of HBM peak)")
