@@ -1465,9 +1465,17 @@ static cr_status op_apply_impl(cr_problem* P, int64_t r, const T* U, int64_t ldu
       B.clear();
       A.add(P->X<T>(), nx, ninj);
       B.add(V, ldv, rr);
-      CR_TRY(gemm_tn<T>(nx, A, B, nullptr, nullptr, 0, Ht, ninj, gpart, gemm_part_cap(P), as));
-      CR_TRY((convert2d<double, T>(r, r, Z, ldz, Zd, r, as)));
-      CR_TRY(small_gemm(rr, ninj, rr, Zd, r, false, Ht, ninj, true, 1.0, Tm, r, as));
+      if (rr <= ZH_RMAX) {
+        // H = V^T X (V as the left operand: each column of H contiguous in
+        // the partials), then T = Z H in one kernel
+        int ks = 0;
+        CR_TRY(gemm_tn<T>(nx, B, A, nullptr, nullptr, 0, Ht, rr, gpart, gemm_part_cap(P), as, &ks));
+        CR_TRY(zh_from_partials<T>(ninj, rr, ks, gpart, Z, ldz, Tm, r, as));
+      } else {
+        CR_TRY(gemm_tn<T>(nx, A, B, nullptr, nullptr, 0, Ht, ninj, gpart, gemm_part_cap(P), as));
+        CR_TRY((convert2d<double, T>(r, r, Z, ldz, Zd, r, as)));
+        CR_TRY(small_gemm(rr, ninj, rr, Zd, r, false, Ht, ninj, true, 1.0, Tm, r, as));
+      }
     }
     return masked_tall_gemm<T>(ny, rr, ninj, U, ldu, Tm, std::max<int64_t>(r, 1), P->bits,
                                (const T*)nullptr, 0, F + 2 * r * ldf, ldf, as);

@@ -93,10 +93,21 @@ cr_status gemv_n(int64_t n, const Blocks<T>& A, const double* coef, double beta,
 // C (p x q, ldc, double) = A^T B for block lists A, B over n rows.  When
 // mask_bits is non-null B is implicit: B[i,a] = omega_{i,a} * w[i] with
 // omega bit a of word bits[(a/32)*n + i].  part: >= ksplit*p*q doubles.
+// With ks_out non-null the split-K partials are left unreduced in part
+// (part[z p q + i + j p], z < *ks_out) and C is not written.
 template <typename T>
 cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint32_t* mask_bits,
                   const T* w, int q_mask, double* C, int64_t ldc, double* part,
-                  int64_t part_cap, hipStream_t st);
+                  int64_t part_cap, hipStream_t st, int* ks_out = nullptr);
+
+// T (r x p, double, ldt) = Z H with H = V^T X (r x p) given as the ks split-K
+// partials of gemm_tn(V, X) (ks_out form: part[z r p + j + a r]); Z: r x r
+// (ldz).  One workgroup per column of T; the partials are summed in a fixed
+// order.  r <= ZH_RMAX.
+constexpr int ZH_RMAX = 2048;
+template <typename T>
+cr_status zh_from_partials(int p, int r, int ks, const double* part, const T* Z, int64_t ldz,
+                           double* Tm, int64_t ldt, hipStream_t st);
 
 // N = OY - Omega o (U T)  (n x ninj), or, with OY == nullptr, N = Omega o (U T).
 // U: n x r (ldu), T: r x ninj (double, ldt).

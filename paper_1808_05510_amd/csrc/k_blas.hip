@@ -430,18 +430,25 @@ __global__ __launch_bounds__(NT) void k_reduce_split(int p, int q, int ks,
 template <typename T>
 cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint32_t* mask_bits,
                   const T* w, int q_mask, double* C, int64_t ldc, double* part,
-                  int64_t part_cap, hipStream_t st) {
+                  int64_t part_cap, hipStream_t st, int* ks_out) {
   const int p = A.ncols();
   const int q = mask_bits ? q_mask : B.ncols();
   if (p == 0 || q == 0) return CR_OK;
   if (n == 0) {
+    if (ks_out) {
+      CR_HIP(hipMemsetAsync(part, 0, (size_t)p * q * sizeof(double), st));
+      *ks_out = 1;
+      return CR_OK;
+    }
     CR_HIP(hipMemset2DAsync(C, ldc * sizeof(double), 0, p * sizeof(double), q, st));
     return CR_OK;
   }
   if (sizeof(T) == 4 && !mask_bits && p <= 128 && q <= 128) {
     // FP32 operands: one slab of at least 512 rows per workgroup, at most about
     // 512 slabs (measured faster than the 64 x 64 tiles below for FP32 data,
-    // slower for FP64 data, whose tiled form keeps more loads in flight)
+    // slower for FP64 data, whose tiled form keeps more loads in flight; in
+    // the forked operator application its few workgroups also leave the CUs
+    // to the concurrent stencil sweeps: 533 us against 581 us tiled)
     int64_t ks = std::max<int64_t>(1, std::min<int64_t>(512, n / 512));
     while (ks > 1 && ks * (int64_t)p * q > part_cap) --ks;
     if (ks * (int64_t)p * q > part_cap) {
@@ -454,6 +461,10 @@ cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint3
     hipLaunchKernelGGL((k_gemm_tn_wide<T>), dim3((unsigned)ks), dim3(GW_NT), 0, st, n, A, B, p, q,
                        kchunk, part);
     CR_HIP(hipGetLastError());
+    if (ks_out) {
+      *ks_out = (int)ks;
+      return CR_OK;
+    }
     const int64_t pq = (int64_t)p * q;
     hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((pq + WAVE - 1) / WAVE)), dim3(NT), 0, st,
                        p, q, (int)ks, part, C, ldc);
@@ -481,8 +492,96 @@ cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint3
                        q, kchunk, part);
   CR_HIP(hipGetLastError());
   const int64_t pq = (int64_t)p * q;
+  if (ks_out) {
+    *ks_out = (int)ks;
+    return CR_OK;
+  }
   hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((pq + WAVE - 1) / WAVE)), dim3(NT), 0, st,
                      p, q, (int)ks, part, C, ldc);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ============================================================== T = Z H from partials
+// H = V^T X arrives as split-K partials part[z r n_inj + j + a r] (V^T X
+// computed with V as the left operand, so a column of H is contiguous).
+// Workgroup a (1024 threads = 8 groups of 128): group g sums partials z = g,
+// g + 8, ... for 128 rows j at a time, coalesced, and the 8 group sums are
+// added in a fixed order in LDS; then T[:, a] = Z h, with group g taking
+// columns j = g, g + 8, ... of Z for 128 rows of T at a time (coalesced column
+// reads of Z, which stays in L2 across workgroups), again summed over the
+// groups in a fixed order.  Replaces a reduce, a copy of Z and a small GEMM:
+// three latency-bound launches in front of the masked product.
+constexpr int ZH_NT = 1024, ZH_G = ZH_NT / 128;
+
+template <typename T>
+__global__ __launch_bounds__(ZH_NT) void k_zh_part(int p, int r, int ks,
+                                                   const double* __restrict__ part,
+                                                   const T* __restrict__ Z, int64_t ldz,
+                                                   double* __restrict__ Tm, int64_t ldt) {
+  extern __shared__ double hs[];  // r doubles of h
+  __shared__ double red[ZH_G][128];
+  const int a = blockIdx.x;
+  const int t = threadIdx.x;
+  const int li = t & 127, g = t >> 7;
+  const int64_t pq = (int64_t)p * r;
+  for (int j0 = 0; j0 < r; j0 += 128) {
+    const int j = j0 + li;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (j < r) {
+      const double* pj = part + (int64_t)a * r + j;
+      int z = g;
+      for (; z + 3 * ZH_G < ks; z += 4 * ZH_G) {
+        s0 += pj[(int64_t)z * pq];
+        s1 += pj[(int64_t)(z + ZH_G) * pq];
+        s2 += pj[(int64_t)(z + 2 * ZH_G) * pq];
+        s3 += pj[(int64_t)(z + 3 * ZH_G) * pq];
+      }
+      for (; z < ks; z += ZH_G) s0 += pj[(int64_t)z * pq];
+    }
+    red[g][li] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (g == 0 && j < r) {
+      double h = 0.0;
+#pragma unroll
+      for (int q = 0; q < ZH_G; ++q) h += red[q][li];
+      hs[j] = h;
+    }
+    __syncthreads();
+  }
+  for (int k0 = 0; k0 < r; k0 += 128) {
+    const int k = k0 + li;
+    double s0 = 0.0, s1 = 0.0;
+    if (k < r) {
+      int j = g;
+      for (; j + ZH_G < r; j += 2 * ZH_G) {
+        s0 += (double)Z[k + (int64_t)j * ldz] * hs[j];
+        s1 += (double)Z[k + (int64_t)(j + ZH_G) * ldz] * hs[j + ZH_G];
+      }
+      for (; j < r; j += ZH_G) s0 += (double)Z[k + (int64_t)j * ldz] * hs[j];
+    }
+    red[g][li] = s0 + s1;
+    __syncthreads();
+    if (g == 0 && k < r) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < ZH_G; ++q) v += red[q][li];
+      Tm[k + (int64_t)a * ldt] = v;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+cr_status zh_from_partials(int p, int r, int ks, const double* part, const T* Z, int64_t ldz,
+                           double* Tm, int64_t ldt, hipStream_t st) {
+  if (p <= 0 || r <= 0) return CR_OK;
+  if (r > ZH_RMAX || ks < 1) {
+    set_error("zh_from_partials: rank out of range");
+    return CR_EINVAL;
+  }
+  hipLaunchKernelGGL((k_zh_part<T>), dim3((unsigned)p), dim3(ZH_NT), r * sizeof(double), st, p, r,
+                     ks, part, Z, ldz, Tm, ldt);
   CR_HIP(hipGetLastError());
   return CR_OK;
 }
@@ -607,7 +706,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
 // is read once per workgroup instead of once per voxel tile, and the MFMA
 // chain of a tile is 2 KS back-to-back instructions.  KS = k steps of 4
 // (r <= 4 KS); the mask word of a wave's 32 injections is a single bits word.
-template <typename T, int KS>
+template <typename T, int KS, bool HAS_OY>
 __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
     int64_t n, int r, int ninj, const T* __restrict__ U, int64_t ldu, const double* __restrict__ Tm,
     int64_t ldt, const uint32_t* __restrict__ bits, const T* __restrict__ OY, int64_t ldoy,
@@ -631,6 +730,7 @@ __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
   const int64_t stride = gridDim.x;
   int64_t tile = blockIdx.x;
   if (tile >= ntile) return;
+  const bool full = a0 + 32 <= ninj;
   // FP64 at large KS: no second fragment buffer (register budget of two waves
   // per SIMD); the other wave on the SIMD covers the load latency instead
   constexpr bool PF = sizeof(T) == 4 || KS <= 16;
@@ -638,14 +738,22 @@ __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
   // the k part of an address is uniform (scalar); the lane part is one 32-bit
   // offset fk ldu + voxel (the host checks that it fits).  Columns k >= r are
   // clamped to r - 1: their T^T fragments are zero, so any finite value works.
+  // Full k steps address as a uniform column base (scalar registers) plus one
+  // 32-bit lane byte offset (the host checks that it fits), so the loads use
+  // the scalar-base form and no per-step 64-bit lane addresses are kept.
   auto loadB = [&](int64_t tl, T* x) {
     const int64_t v = tl * 16 + fr;
     const int32_t vc = (int32_t)(v < n ? v : n - 1);
     const int32_t off = fk * (int32_t)ldu + vc;
+    const uint32_t offb = (uint32_t)off * (uint32_t)sizeof(T);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      if (4 * ks + 3 < r) {
-        x[ks] = U[(int64_t)(4 * ks) * ldu + off];
+      // KS > 16 is launched only with KS = ceil(r / 4): every step but the
+      // last is then full, known at compile time (no clamped alternative
+      // address is formed for them)
+      if ((KS > 16 && ks < KS - 1) || 4 * ks + 3 < r) {
+        const char* base = reinterpret_cast<const char*>(U + (int64_t)(4 * ks) * ldu);
+        x[ks] = *reinterpret_cast<const T*>(base + offb);
       } else {
         const int k = min(4 * ks + fk, r - 1);
         x[ks] = U[(int64_t)k * ldu + vc];
@@ -675,16 +783,34 @@ __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
     if (!PF && more) loadB(tile + stride, b);
     const int64_t v = tile * 16 + fr;
     if (v < n) {
+      if (full) {
+        // all 32 injections of the wave exist: unconditional stores
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < 2; ++t) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int al_loc = 16 * t + Mfma16<T>::row(fk, e);  // < 32
-          const int64_t al = a0 + al_loc;
-          if (al < ninj) {
+          for (int e = 0; e < 4; ++e) {
+            const int al_loc = 16 * t + Mfma16<T>::row(fk, e);
+            const int64_t al = a0 + al_loc;
             const T om = (T)((wd >> al_loc) & 1u);
             const T val = om * (t ? acc1[e] : acc0[e]);
-            N[al * ldn + v] = OY ? OY[al * ldoy + v] - val : val;
+            if (HAS_OY)
+              N[al * ldn + v] = OY[al * ldoy + v] - val;
+            else
+              N[al * ldn + v] = val;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int al_loc = 16 * t + Mfma16<T>::row(fk, e);  // < 32
+            const int64_t al = a0 + al_loc;
+            if (al < ninj) {
+              const T om = (T)((wd >> al_loc) & 1u);
+              const T val = om * (t ? acc1[e] : acc0[e]);
+              N[al * ldn + v] = HAS_OY ? OY[al * ldoy + v] - val : val;
+            }
           }
         }
       }
@@ -704,25 +830,42 @@ cr_status masked_tall_gemm(int64_t n, int r, int ninj, const T* U, int64_t ldu, 
                            int64_t ldt, const uint32_t* bits, const T* OY, int64_t ldoy, T* N,
                            int64_t ldn, hipStream_t st) {
   if (n == 0 || ninj == 0) return CR_OK;
-  if (r >= 1 && r <= 112 && 4 * ldu + n < INT32_MAX) {
-    // one wave per 32 injections of a 128-injection block; about 4 workgroups per CU
+  if (r >= 1 && r <= 112 && (4 * ldu + n) * (int64_t)sizeof(T) <= (int64_t)UINT32_MAX) {
+    // one wave per 32 injections of a 128-injection block; as many workgroups
+    // as fit on the device at once (two per CU for FP64 at r = 100)
     const int na = std::min(ninj, MG_COLS);
     const int waves = (na + 31) / 32;
     const int64_t ntile = (n + 15) / 16;
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess)
       (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t want = (int64_t)ncu * 16 / waves;
-    dim3 grid((unsigned)std::max<int64_t>(1, std::min(ntile, want)), (ninj + MG_COLS - 1) / MG_COLS);
+    // the grid-stride loop wants exactly one round of resident workgroups:
+    // a partial second round runs at a fraction of the occupancy
     const int ks = (r + 3) / 4;
 #define RT_CASE(K)                                                                             \
   if (ks <= K) {                                                                               \
-    hipLaunchKernelGGL((k_masked_gemm_rt<T, K>), grid, dim3(64 * waves), 0, st, n, r, ninj, U, \
-                       ldu, Tm, ldt, bits, OY, ldoy, N, ldn);                                  \
+    int per_cu = 0;                                                                            \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_masked_gemm_rt<T, K, false>,   \
+                                                     64 * waves, 0) != hipSuccess ||           \
+        per_cu < 1)                                                                            \
+      per_cu = 1;                                                                              \
+    const int gy = (ninj + MG_COLS - 1) / MG_COLS;                                             \
+    const int64_t want = (int64_t)ncu * per_cu / gy;                                           \
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min(ntile, want)), gy);                      \
+    if (OY)                                                                                    \
+      hipLaunchKernelGGL((k_masked_gemm_rt<T, K, true>), grid, dim3(64 * waves), 0, st, n, r,  \
+                         ninj, U, ldu, Tm, ldt, bits, OY, ldoy, N, ldn);                       \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_masked_gemm_rt<T, K, false>), grid, dim3(64 * waves), 0, st, n, r, \
+                         ninj, U, ldu, Tm, ldt, bits, OY, ldoy, N, ldn);                       \
     CR_HIP(hipGetLastError());                                                                 \
     return CR_OK;                                                                              \
   }
-    RT_CASE(4) RT_CASE(8) RT_CASE(12) RT_CASE(16) RT_CASE(20) RT_CASE(24) RT_CASE(28)
+    // k steps in fours up to 16, then exact: at r > 64 the FP64 MFMA work is
+    // the kernel's floor, and a padded step costs a full MFMA pair per tile
+    RT_CASE(4) RT_CASE(8) RT_CASE(12) RT_CASE(16) RT_CASE(17) RT_CASE(18) RT_CASE(19)
+    RT_CASE(20) RT_CASE(21) RT_CASE(22) RT_CASE(23) RT_CASE(24) RT_CASE(25) RT_CASE(26)
+    RT_CASE(27) RT_CASE(28)
 #undef RT_CASE
   }
   const unsigned nb_log = (unsigned)((n + MG_ROWS - 1) / MG_ROWS);
@@ -1016,7 +1159,9 @@ cr_status hole_gram_col(int ninj, const int32_t* hptr, const int32_t* hidx, int 
                                hipStream_t);                                                    \
   template cr_status gemm_tn<T>(int64_t, const Blocks<T>&, const Blocks<T>&, const uint32_t*,   \
                                 const T*, int, double*, int64_t, double*, int64_t,             \
-                                hipStream_t);                                                   \
+                                hipStream_t, int*);                                             \
+  template cr_status zh_from_partials<T>(int, int, int, const double*, const T*, int64_t,       \
+                                         double*, int64_t, hipStream_t);                        \
   template cr_status masked_tall_gemm<T>(int64_t, int, int, const T*, int64_t, const double*,   \
                                          int64_t, const uint32_t*, const T*, int64_t, T*,       \
                                          int64_t, hipStream_t);                                 \
