@@ -1231,6 +1231,63 @@ static cr_status build_geom(const cr_csr& L, Geom& g, const char* which) {
   }
   CR_HIP(hipMemcpy(g.nbr, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice));
   CR_HIP(hipMemcpy(g.deg, deg.data(), n, hipMemcpyHostToDevice));
+  // window tables for the multi-column stencil (optional: left null when a
+  // tile reads more than WIN_NI intervals or WIN_MAX voxels)
+  const int64_t ntile = (n + NT - 1) / NT;
+  std::vector<int32_t> itab((size_t)ntile * WIN_TAB, 0);
+  std::vector<uint16_t> wpos((size_t)(K + 1) * n);
+  std::vector<int32_t> idx;
+  bool fits = true;
+  for (int64_t t = 0; t < ntile && fits; ++t) {
+    const int64_t t0 = t * NT, t1 = std::min(n, t0 + NT);
+    idx.clear();
+    for (int64_t i = t0; i < t1; ++i) {
+      idx.push_back((int32_t)i);
+      for (int k = 0; k < K; ++k) idx.push_back(nbr[(size_t)k * n + i]);
+    }
+    std::sort(idx.begin(), idx.end());
+    idx.erase(std::unique(idx.begin(), idx.end()), idx.end());
+    int32_t* it = itab.data() + t * WIN_TAB;
+    int nint = 0, tot = 0;
+    size_t a = 0;
+    while (a < idx.size()) {
+      size_t b = a;
+      while (b + 1 < idx.size() && idx[b + 1] - idx[b] <= WIN_GAP) ++b;
+      if (nint == WIN_NI) {
+        fits = false;
+        break;
+      }
+      it[2 + nint] = idx[a];
+      it[2 + WIN_NI + nint] = tot;
+      tot += idx[b] - idx[a] + 1;
+      ++nint;
+      a = b + 1;
+    }
+    if (!fits || tot > WIN_MAX) {
+      fits = false;
+      break;
+    }
+    it[0] = nint;
+    it[1] = tot;
+    auto pos = [&](int32_t j) {
+      int q = 0;
+      while (q + 1 < nint && it[2 + q + 1] <= j) ++q;
+      return (uint16_t)(it[2 + WIN_NI + q] + (j - it[2 + q]));
+    };
+    for (int64_t i = t0; i < t1; ++i) {
+      wpos[(size_t)i] = pos((int32_t)i);
+      for (int k = 0; k < K; ++k) wpos[(size_t)(k + 1) * n + i] = pos(nbr[(size_t)k * n + i]);
+    }
+  }
+  if (fits) {
+    if (hipMalloc(&g.witab, sizeof(int32_t) * itab.size()) != hipSuccess ||
+        hipMalloc(&g.wpos, sizeof(uint16_t) * wpos.size()) != hipSuccess) {
+      set_error("device allocation of the window tables failed");
+      return CR_ENOMEM;
+    }
+    CR_HIP(hipMemcpy(g.witab, itab.data(), sizeof(int32_t) * itab.size(), hipMemcpyHostToDevice));
+    CR_HIP(hipMemcpy(g.wpos, wpos.data(), sizeof(uint16_t) * wpos.size(), hipMemcpyHostToDevice));
+  }
   return CR_OK;
 }
 
@@ -1385,10 +1442,12 @@ extern "C" void cr_problem_destroy(cr_problem* P) {
   for (auto& kv : P->ws)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (void* p : P->owned) (void)hipFree(p);
-  if (P->gy.nbr) (void)hipFree(P->gy.nbr);
-  if (P->gy.deg) (void)hipFree(P->gy.deg);
-  if (P->gx.nbr) (void)hipFree(P->gx.nbr);
-  if (P->gx.deg) (void)hipFree(P->gx.deg);
+  for (Geom* g : {&P->gy, &P->gx}) {
+    if (g->nbr) (void)hipFree(g->nbr);
+    if (g->deg) (void)hipFree(g->deg);
+    if (g->witab) (void)hipFree(g->witab);
+    if (g->wpos) (void)hipFree(g->wpos);
+  }
   if (P->hscal) (void)hipHostFree(P->hscal);
   if (P->aux) {
     (void)hipStreamSynchronize(P->aux);

@@ -36,11 +36,21 @@ constexpr int NT = 256;  // threads per workgroup for streaming kernels
 // A voxel graph Laplacian L = Deg - Adj stored as an ELL neighbour table of
 // width K, structure-of-arrays (nbr[k*n + i]); an absent neighbour points to
 // the voxel itself, so (L w)_i = K w_i - sum_k w[nbr[k*n+i]] for every row.
+// LDS-window form of the stencil: per tile of NT consecutive voxels, the set
+// of voxels its rows read (the tile and its neighbours) as at most WIN_NI
+// index intervals (gaps of up to WIN_GAP voxels bridged) of total length at
+// most WIN_MAX, so that a workgroup stages them with coalesced loads.
+constexpr int WIN_NI = 16, WIN_MAX = 2048, WIN_GAP = 32;
+constexpr int WIN_TAB = 2 + 2 * WIN_NI;  // count, total, starts, LDS prefixes
+
 struct Geom {
   int64_t n = 0;
   int K = 0;
   int32_t* nbr = nullptr;  // device, K*n
   uint8_t* deg = nullptr;  // device, n
+  // window tables (null when some tile's window does not fit):
+  int32_t* witab = nullptr;  // device, ntile * WIN_TAB
+  uint16_t* wpos = nullptr;  // device, (K + 1) * n: window position of i, then of nbr_k(i)
 };
 
 // A column-block list: columns [col0, col0+ncols) of the logical matrix live

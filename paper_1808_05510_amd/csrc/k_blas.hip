@@ -64,12 +64,114 @@ __global__ __launch_bounds__(NT) void k_stencil(int64_t n, const int32_t* __rest
   }
 }
 
+// Window form (many columns): workgroup = one tile of NT voxels x a chunk of
+// columns.  Per column, the tile's window (the voxels its rows read, as index
+// intervals) is staged into LDS with coalesced loads, double-buffered so the
+// next column's loads are in flight while the current one is computed from
+// LDS; each row then reads itself and its neighbours at precomputed window
+// positions.  Measured 10-20% faster than the gather form on the shell
+// geometry (FP32 data), whose neighbour planes are a few thousand voxels
+// apart.
+constexpr int WIN_EPT = WIN_MAX / NT;  // window elements staged per thread
+
+template <typename T, int K>
+__global__ __launch_bounds__(NT) void k_stencil_win(int64_t n, unsigned nt_log,
+                                                    const int32_t* __restrict__ itab,
+                                                    const uint16_t* __restrict__ wpos, int ncols,
+                                                    int cchunk, const T* __restrict__ w,
+                                                    int64_t ldw, T* __restrict__ out,
+                                                    int64_t ldo) {
+  __shared__ T buf[2][WIN_MAX];
+  const int64_t tile = xcd_block(blockIdx.x, nt_log);
+  if (tile >= nt_log) return;  // uniform per workgroup
+  const int cb = blockIdx.y * cchunk;
+  const int ce = min(ncols, cb + cchunk);
+  if (cb >= ce) return;  // uniform per workgroup
+  const int tid = threadIdx.x;
+  const int32_t* it = itab + tile * WIN_TAB;
+  const int nint = it[0], tot = it[1];
+  int src[WIN_EPT];
+#pragma unroll
+  for (int m = 0; m < WIN_EPT; ++m) {
+    const int e = tid + NT * m;
+    int sv = -1;
+    if (e < tot) {
+      int q = 0;
+      for (int k = 1; k < nint; ++k)
+        if (it[2 + WIN_NI + k] <= e) q = k;
+      sv = it[2 + q] + (e - it[2 + WIN_NI + q]);
+    }
+    src[m] = sv;
+  }
+  const int64_t i = tile * NT + tid;
+  const bool valid = i < n;
+  int q0 = 0, q1[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) q1[k] = 0;
+  if (valid) {
+    q0 = wpos[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) q1[k] = wpos[(int64_t)(k + 1) * n + i];
+  }
+  T rg[WIN_EPT];
+  auto load = [&](int c) {
+    const T* wc = w + (int64_t)c * ldw;
+#pragma unroll
+    for (int m = 0; m < WIN_EPT; ++m) rg[m] = src[m] >= 0 ? wc[src[m]] : (T)0;
+  };
+  auto stage = [&](int b) {
+#pragma unroll
+    for (int m = 0; m < WIN_EPT; ++m)
+      if (tid + NT * m < tot) buf[b][tid + NT * m] = rg[m];
+  };
+  load(cb);
+  stage(0);
+  __syncthreads();
+  for (int c = cb; c < ce; ++c) {
+    const int b = (c - cb) & 1;
+    if (c + 1 < ce) load(c + 1);
+    if (valid) {
+      const T* B = buf[b];
+      T v = (T)K * B[q0];
+#pragma unroll
+      for (int k = 0; k < K; ++k) v -= B[q1[k]];
+      out[(int64_t)c * ldo + i] = v;
+    }
+    if (c + 1 < ce) stage(b ^ 1);
+    __syncthreads();
+  }
+}
+
 template <typename T>
 cr_status stencil(const Geom& g, int ncols, const T* w, int64_t ldw, T* out, int64_t ldo,
                   hipStream_t st) {
   if (ncols <= 0 || g.n == 0) return CR_OK;
   const unsigned nb_log = (unsigned)((g.n + NT - 1) / NT);
   const unsigned nb_phys = (nb_log + NXCD - 1) / NXCD * NXCD;
+  // FP32 data only: for FP64 the window form is faster alone (153 against
+  // 163 us on the shell target side, r = 100) but slower inside the forked
+  // operator application (806 against 769 us), where its LDS and register
+  // needs compete with the concurrent masked product
+  if (sizeof(T) == 4 && g.witab && ncols >= SCOL) {
+    // column chunks so that the launch has about 2048 workgroups
+    const int nsplit = std::max(1, std::min({4, ncols / 2, (int)(2048 / nb_log)}));
+    const int cchunk = (ncols + nsplit - 1) / nsplit;
+    dim3 wg(nb_phys, (unsigned)((ncols + cchunk - 1) / cchunk));
+    switch (g.K) {
+#define WCASE(KK)                                                                          \
+  case KK:                                                                                 \
+    hipLaunchKernelGGL((k_stencil_win<T, KK>), wg, dim3(NT), 0, st, g.n, nb_log, g.witab, \
+                       g.wpos, ncols, cchunk, w, ldw, out, ldo);                           \
+    break;
+      WCASE(2) WCASE(4) WCASE(6) WCASE(8)
+#undef WCASE
+      default:
+        set_error("stencil width out of range");
+        return CR_EINVAL;
+    }
+    CR_HIP(hipGetLastError());
+    return CR_OK;
+  }
   dim3 grid(nb_phys, (unsigned)((ncols + SCOL - 1) / SCOL));
   switch (g.K) {
 #define CASE(KK)                                                                         \
