@@ -61,7 +61,7 @@ struct cr_problem {
   bool use_holes = false;
   double dnorm = 0.0;
   double* hscal = nullptr;  // pinned host scratch
-  unsigned* bar = nullptr;  // grid-barrier words: [0] generation, [64] timeout, [128] arrivals
+  unsigned* bar = nullptr;  // grid-barrier words (BAR_WORDS)
   cr_pc* pc = nullptr;      // learned preconditioner for the u-systems (not owned)
   int fcg_mode = 0;         // u-systems: 0 Jacobi-PCG, 1 FCG + base step, 2 FCG + base step + network
   BoxBasis boxy;            // spectral basis of the target grid when it is a full box
@@ -504,7 +504,7 @@ struct Ctx {
   cr_status read_scalars(const double* dev, int count, double* host) {
     unsigned* flag = (unsigned*)(P->hscal + 60);
     CR_HIP(hipMemcpyAsync(P->hscal, dev, sizeof(double) * count, hipMemcpyDeviceToHost, st));
-    CR_HIP(hipMemcpyAsync(flag, P->bar + 64, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    CR_HIP(hipMemcpyAsync(flag, P->bar + BAR_TIMEOUT, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     CR_HIP(hipStreamSynchronize(st));
     if (*flag) {
       set_error("grid barrier timed out in a persistent kernel");
@@ -1383,8 +1383,8 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   CR_HIP(hipMemcpy(P->hptr, hptr.data(), sizeof(int32_t) * hptr.size(), hipMemcpyHostToDevice));
   if (P->nholes)
     CR_HIP(hipMemcpy(P->hidx, hidx.data(), sizeof(int32_t) * hidx.size(), hipMemcpyHostToDevice));
-  CR_TRY(dev_alloc(P, &P->bar, 192));
-  CR_HIP(hipMemset(P->bar, 0, 192 * sizeof(unsigned)));
+  CR_TRY(dev_alloc(P, &P->bar, BAR_WORDS));
+  CR_HIP(hipMemset(P->bar, 0, BAR_WORDS * sizeof(unsigned)));
   if (const char* e = std::getenv("CONNREG_GRID_BARRIER"))
     P->bar_mode = (std::strcmp(e, "cg") == 0) ? 0 : 1;
   if (hipHostMalloc((void**)&P->hscal, 64 * sizeof(double)) != hipSuccess) {

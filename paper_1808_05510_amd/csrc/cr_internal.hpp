@@ -150,8 +150,11 @@ cr_status convert2d(int64_t rows, int64_t cols, const Ts* src, int64_t lds, Td* 
 // xout = x / ||x|| and scal[0] = ||x||, scal[1] = final ||r||/||b||,
 // scal[2] = iterations, scal[3] = status (0 ok, 1 not converged, 2 breakdown).
 // grid barrier selection for the persistent kernels (see k_cg.hip)
+// barrier words: [0] generation, [64] timeout flag, [128] arrivals (separate
+// 256-byte lines)
+constexpr int BAR_GEN = 0, BAR_TIMEOUT = 64, BAR_COUNT = 128, BAR_WORDS = 192;
 struct BarrierArg {
-  unsigned* bar = nullptr;  // 192 device words, zeroed before each launch
+  unsigned* bar = nullptr;  // BAR_WORDS device words, zeroed before each launch
   int mode = 1;             // 0: cooperative-groups grid sync, 1: atomic barrier
   int coop = 1;             // 1: cooperative launch; 0: ordinary launch (mode 1 only, for
                             // concurrent persistent kernels that together fit on the device)

@@ -808,7 +808,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
 // is read once per workgroup instead of once per voxel tile, and the MFMA
 // chain of a tile is 2 KS back-to-back instructions.  KS = k steps of 4
 // (r <= 4 KS); the mask word of a wave's 32 injections is a single bits word.
-template <typename T, int KS, bool HAS_OY>
+template <typename T, int KS, bool HAS_OY, bool SYNC>
 __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
     int64_t n, int r, int ninj, const T* __restrict__ U, int64_t ldu, const double* __restrict__ Tm,
     int64_t ldt, const uint32_t* __restrict__ bits, const T* __restrict__ OY, int64_t ldoy,
@@ -817,7 +817,16 @@ __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fr = lane & 15, fk = lane >> 4;
   const int a0 = blockIdx.y * MG_COLS + 32 * wv;  // first injection of this wave
-  if (a0 >= ninj) return;                         // whole wave idle (no barriers below)
+  const int64_t ntile = (n + 15) / 16;
+  const int64_t stride = gridDim.x;
+  int64_t tile = blockIdx.x;
+  if (tile >= ntile) return;  // uniform per workgroup
+  if (a0 >= ninj) {
+    // whole wave idle: with SYNC it still takes the per-tile barrier
+    if (SYNC)
+      for (; tile < ntile; tile += stride) __syncthreads();
+    return;
+  }
   T a[2][KS];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -828,10 +837,6 @@ __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
       a[t][ks] = (k < r && al < ninj) ? (T)Tm[(int64_t)al * ldt + k] : (T)0;
     }
   }
-  const int64_t ntile = (n + 15) / 16;
-  const int64_t stride = gridDim.x;
-  int64_t tile = blockIdx.x;
-  if (tile >= ntile) return;
   const bool full = a0 + 32 <= ninj;
   // FP64 at large KS: no second fragment buffer (register budget of two waves
   // per SIMD); the other wave on the SIMD covers the load latency instead
@@ -871,6 +876,10 @@ __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
   loadB(tile, b);
   uint32_t wd = loadW(tile), wdn = 0u;
   for (; tile < ntile; tile += stride) {
+    // SYNC: the workgroup's waves (one per SIMD) read the same U tile; a
+    // barrier per tile keeps them together, so the lines one wave brings
+    // into L2 are still there for the others
+    if (SYNC) __syncthreads();
     const bool more = tile + stride < ntile;
     if (more) wdn = loadW(tile + stride);
     if (PF && more) loadB(tile + stride, bn);
@@ -944,22 +953,36 @@ cr_status masked_tall_gemm(int64_t n, int r, int ninj, const T* U, int64_t ldu, 
     // the grid-stride loop wants exactly one round of resident workgroups:
     // a partial second round runs at a fraction of the occupancy
     const int ks = (r + 3) / 4;
+    // a barrier per tile keeps a workgroup's waves on the same U tile: for
+    // FP32 data 114 against 140 us alone and 499 against 524 us for the forked
+    // operator call; FP64 fetches less U with it (318 against 441 MB) but runs
+    // slower (218 against 211 us alone, 786 against 770 us forked)
+    constexpr bool mg_sync = sizeof(T) == 4;
 #define RT_CASE(K)                                                                             \
   if (ks <= K) {                                                                               \
     int per_cu = 0;                                                                            \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_masked_gemm_rt<T, K, false>,   \
-                                                     64 * waves, 0) != hipSuccess ||           \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                          \
+            &per_cu, k_masked_gemm_rt<T, K, false, false>, 64 * waves, 0) != hipSuccess ||     \
         per_cu < 1)                                                                            \
       per_cu = 1;                                                                              \
     const int gy = (ninj + MG_COLS - 1) / MG_COLS;                                             \
     const int64_t want = (int64_t)ncu * per_cu / gy;                                           \
     dim3 grid((unsigned)std::max<int64_t>(1, std::min(ntile, want)), gy);                      \
-    if (OY)                                                                                    \
-      hipLaunchKernelGGL((k_masked_gemm_rt<T, K, true>), grid, dim3(64 * waves), 0, st, n, r,  \
-                         ninj, U, ldu, Tm, ldt, bits, OY, ldoy, N, ldn);                       \
-    else                                                                                       \
-      hipLaunchKernelGGL((k_masked_gemm_rt<T, K, false>), grid, dim3(64 * waves), 0, st, n, r, \
-                         ninj, U, ldu, Tm, ldt, bits, OY, ldoy, N, ldn);                       \
+    if constexpr (mg_sync) {                                                                   \
+      if (OY)                                                                                  \
+        hipLaunchKernelGGL((k_masked_gemm_rt<T, K, true, true>), grid, dim3(64 * waves), 0,    \
+                           st, n, r, ninj, U, ldu, Tm, ldt, bits, OY, ldoy, N, ldn);           \
+      else                                                                                     \
+        hipLaunchKernelGGL((k_masked_gemm_rt<T, K, false, true>), grid, dim3(64 * waves), 0,   \
+                           st, n, r, ninj, U, ldu, Tm, ldt, bits, OY, ldoy, N, ldn);           \
+    } else {                                                                                   \
+      if (OY)                                                                                  \
+        hipLaunchKernelGGL((k_masked_gemm_rt<T, K, true, false>), grid, dim3(64 * waves), 0,   \
+                           st, n, r, ninj, U, ldu, Tm, ldt, bits, OY, ldoy, N, ldn);           \
+      else                                                                                     \
+        hipLaunchKernelGGL((k_masked_gemm_rt<T, K, false, false>), grid, dim3(64 * waves), 0,  \
+                           st, n, r, ninj, U, ldu, Tm, ldt, bits, OY, ldoy, N, ldn);           \
+    }                                                                                          \
     CR_HIP(hipGetLastError());                                                                 \
     return CR_OK;                                                                              \
   }

@@ -59,8 +59,6 @@ __device__ __forceinline__ double grid_total(const double* part, int slot, int n
 // far above any legitimate wait between phases) it sets the timeout flag;
 // once set, every later barrier is skipped, so a faulty launch ends quickly
 // instead of hanging the device, and the host reports the flag as an error.
-constexpr int BAR_GEN = 0, BAR_TIMEOUT = 64, BAR_COUNT = 128, BAR_WORDS = 192;
-
 __device__ __forceinline__ void grid_barrier(const BarrierArg& b, cgrp::grid_group& grid) {
   if (b.mode == 0) {
     grid.sync();
