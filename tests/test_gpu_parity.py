@@ -46,6 +46,29 @@ def dense_mask_box(seed=5):
     return d
 
 
+def scrambled_box(seed=7):
+    """mid_box with the target voxels renumbered at random: the Laplacian is
+    the same graph, but neighbours lie anywhere in the index range, so the
+    library has no LDS-window tables and every stencil takes the gather form."""
+    import scipy.sparse as sp
+    # 2,688 target voxels: a tile's scattered neighbours then span more than
+    # the 2,048-voxel window
+    d = synth.box_problem(box_y=(16, 14, 12), box_x=(8, 7, 9), offset=(1, 2, 0), n_inj=21,
+                          sigma=1.5, hole_r=1.5, wt_rank=4, wt_w=(2.0, 4.0), lam=30.0, seed=seed)
+    n = len(d["Ly_rowptr"]) - 1
+    perm = np.random.default_rng(seed).permutation(n)
+    L = sp.csr_matrix((d["Ly_val"], d["Ly_colidx"], d["Ly_rowptr"]), shape=(n, n))
+    Lp = L[perm][:, perm].tocsr()
+    Lp.sort_indices()
+    d["Ly_rowptr"] = Lp.indptr.astype(np.int32)
+    d["Ly_colidx"] = Lp.indices.astype(np.int32)
+    d["Ly_val"] = Lp.data.astype(np.float64)
+    for k in ("Y", "Omega", "coords_y", "Wt_g"):
+        d[k] = np.ascontiguousarray(d[k][perm])
+    d.pop("box_y", None)
+    return d
+
+
 CASES = {
     "toy1d": lambda: synth.config1(),
     "tiny3d": lambda: synth.config2_tiny(),
@@ -53,6 +76,7 @@ CASES = {
     "densemask": dense_mask_box,
     # more than one 128-injection block of the masked products
     "manyinj": lambda: mid_box(seed=6, n_inj=150),
+    "scrambled": scrambled_box,
 }
 
 
@@ -64,8 +88,10 @@ def case(request):
 
 # ------------------------------------------------------------------ op_apply
 # 112 is the largest rank of the register-resident masked product, 120 takes
-# the LDS-chunked one
-@pytest.mark.parametrize("r", [0, 1, 7, 67, 112, 120])
+# the LDS-chunked one; 64 is the last padded k-step count, 67 and 100 take
+# exact ones (67 with a partial last step); 150 makes T = Z H loop over two
+# 128-row chunks
+@pytest.mark.parametrize("r", [0, 1, 7, 64, 67, 100, 112, 120, 150])
 def test_op_apply_fp64(case, r):
     name, d, P = case
     r = min(r, P.n_x)
@@ -94,7 +120,9 @@ def test_op_apply_fp64(case, r):
         assert rel(A, oop.apply_A(P, Wd)) < 1e-12
 
 
-@pytest.mark.parametrize("r", [1, 67, 120])
+# FP32 sweeps of 8 or more columns take the LDS-window stencil where the
+# geometry has window tables (all cases but "scrambled")
+@pytest.mark.parametrize("r", [1, 8, 67, 100, 120])
 def test_op_apply_fp32(case, r):
     name, d, P = case
     r = min(r, P.n_x)
