@@ -339,13 +339,22 @@ template <typename T, bool MASK>
 __global__ __launch_bounds__(NT) void k_gemm_tn(int64_t n, Blocks<T> A, Blocks<T> B,
                                                 const uint32_t* __restrict__ bits,
                                                 const T* __restrict__ w, int p, int q,
-                                                int64_t kchunk, double* __restrict__ part) {
+                                                int64_t kchunk, double* __restrict__ part,
+                                                int ptiles, int ntiles, unsigned total) {
   __shared__ double As[KC][TM + 1];
   __shared__ double Bs[KC][TM + 1];
+  // one-dimensional grid, remapped so that the output tiles of one row slab
+  // are consecutive workgroups of one XCD (physical block b runs on XCD b % 8):
+  // they run together and read the slab's rows of A and B from that XCD's L2
+  const unsigned per = (total + NXCD - 1) / NXCD;
+  const unsigned lin = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+  if (lin >= total) return;  // uniform per workgroup
+  const int tile = (int)(lin % (unsigned)ntiles);
+  const unsigned zb = lin / (unsigned)ntiles;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int tp = blockIdx.x * TM, tq = blockIdx.y * TM;
-  const int64_t k0 = (int64_t)blockIdx.z * kchunk;
+  const int tp = (tile % ptiles) * TM, tq = (tile / ptiles) * TM;
+  const int64_t k0 = (int64_t)zb * kchunk;
   const int64_t k1 = std::min<int64_t>(n, k0 + kchunk);
   // wave wv computes the 32 x 32 sub-tile (rows 32*(wv%2), cols 32*(wv/2))
   const int wp = 32 * (wv & 1), wq = 32 * (wv >> 1);
@@ -414,7 +423,7 @@ __global__ __launch_bounds__(NT) void k_gemm_tn(int64_t n, Blocks<T> A, Blocks<T
     }
     __syncthreads();
   }
-  double* out = part + (int64_t)blockIdx.z * p * q;
+  double* out = part + (int64_t)zb * p * q;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -585,13 +594,16 @@ cr_status gemm_tn(int64_t n, const Blocks<T>& A, const Blocks<T>& B, const uint3
   int64_t kchunk = (n + ks - 1) / ks;
   kchunk = (kchunk + KC - 1) / KC * KC;
   ks = std::max<int64_t>(1, (n + kchunk - 1) / kchunk);
-  dim3 grid((p + TM - 1) / TM, (q + TM - 1) / TM, (unsigned)ks);
+  const int ptiles = (p + TM - 1) / TM;
+  const int ntiles = ptiles * ((q + TM - 1) / TM);
+  const unsigned total = (unsigned)(ntiles * ks);
+  dim3 grid((total + NXCD - 1) / NXCD * NXCD);
   if (mask_bits)
     hipLaunchKernelGGL((k_gemm_tn<T, true>), grid, dim3(NT), 0, st, n, A, B, mask_bits, w, p, q,
-                       kchunk, part);
+                       kchunk, part, ptiles, ntiles, total);
   else
     hipLaunchKernelGGL((k_gemm_tn<T, false>), grid, dim3(NT), 0, st, n, A, B, mask_bits, w, p,
-                       q, kchunk, part);
+                       q, kchunk, part, ptiles, ntiles, total);
   CR_HIP(hipGetLastError());
   const int64_t pq = (int64_t)p * q;
   if (ks_out) {
