@@ -793,7 +793,10 @@ struct Ctx {
       if (rr_prev >= 0.0 && rr > 0.25 * rr_prev) break;
       rr_prev = rr;
       CR_TRY((convert2d<T, double>(n, 1, r64, n, rb, n, st)));
-      CR_TRY(pcg(usys, rb, xout, in_rtol, maxit, dsc));
+      // the correction only has to take the residual from sqrt(rr) to
+      // rtol ||b|| (with a factor 2 of margin), not by a full in_rtol again
+      const double need = 0.5 * rtol * std::sqrt(bb / rr);
+      CR_TRY(pcg(usys, rb, xout, std::max(in_rtol, need), maxit, dsc));
       CR_TRY(read_scalars(dsc, 4, h));
       out->iters += (int)h[2];
       if (h[3] == 2.0) break;
