@@ -76,6 +76,8 @@ struct cr_problem {
   // faster mixed solves on the 40^3 / 30^3 problem than 256); CONNREG_PCG_BS=256
   // restores 256.  Batched solves use 256 (their CU shares are sized for it).
   int pcg_bs = 1024;
+  int pcg_xbs = 0;           // v-system group size with register-resident X (0: by precision;
+                             // CONNREG_PCG_XBS=256 or 512)
   bool no_xreg = false;     // CONNREG_PCG_XREG=0: v-system PCG streams X (no register-resident rows)
   int bar_mode = 1;
   std::map<std::string, DevBuf> ws;
@@ -454,20 +456,28 @@ struct Ctx {
       const int tuned = P->tuned_vpt_v;
       const int want = vpt_opt > 0 ? vpt_opt : tuned;
       if (ninj <= PCG_NXR && want <= 1 && !P->no_xreg) {
-        PcgArgs<T> probe{};
-        probe.g = P->gx;
-        probe.Xm = X();
-        probe.vpt = 1;
-        probe.bs = NT;
-        probe.nxr = PCG_NXR;
-        int maxwg = pcg_max_wg<T>(probe);
-        if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
-        const int64_t w = std::max<int64_t>(1, (nx + NT - 1) / NT);
-        if (maxwg > 0 && w <= maxwg) {
-          pcg_vpt_v = 1;
-          pcg_nwg_v = (int)w;
-          pcg_bs_v = NT;
-          pcg_nxr_v = PCG_NXR;
+        // FP32 data: 512-thread groups first (half the grid barrier's
+        // arrivals; mixed 40^3/30^3 solve 4.17 s against 4.34 s); FP64 data
+        // keeps 256 (3.80 s against 3.90 s: its halo traffic gains from the
+        // voxels spread over twice the CUs)
+        const int xbs = P->pcg_xbs > 0 ? P->pcg_xbs : (std::is_same<T, float>::value ? 512 : NT);
+        for (int bs : {xbs, NT}) {
+          PcgArgs<T> probe{};
+          probe.g = P->gx;
+          probe.Xm = X();
+          probe.vpt = 1;
+          probe.bs = bs;
+          probe.nxr = PCG_NXR;
+          int maxwg = pcg_max_wg<T>(probe);
+          if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
+          const int64_t w = std::max<int64_t>(1, (nx + bs - 1) / bs);
+          if (maxwg > 0 && w <= maxwg) {
+            pcg_vpt_v = 1;
+            pcg_nwg_v = (int)w;
+            pcg_bs_v = bs;
+            pcg_nxr_v = PCG_NXR;
+            break;
+          }
         }
       }
     }
@@ -1314,6 +1324,7 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   if (const char* e = std::getenv("CONNREG_OP_FORK")) P->op_fork = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_PCG_BS")) P->pcg_bs = std::atoi(e) == NT ? NT : 1024;
   if (const char* e = std::getenv("CONNREG_PCG_XREG")) P->no_xreg = std::atoi(e) == 0;
+  if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
   P->ny = d->Ly.n;
   P->nx = d->Lx.n;
   P->ninj = (int)d->n_inj;

@@ -393,9 +393,11 @@ static void* pcg_fn_vb(int vpt) {
 
 template <typename T, int K, bool LR>
 static void* pcg_fn_v(int vpt, int bs, int nxr) {
-  if (nxr > 0)  // register-resident X: one voxel per thread, 256-thread groups
-    return (LR && vpt == 1 && bs == NT && nxr == PCG_NXR) ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR>
-                                                         : nullptr;
+  if (nxr > 0) {  // register-resident X: one voxel per thread, 256- or 512-thread groups
+    if (!LR || vpt != 1 || nxr != PCG_NXR) return nullptr;
+    return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR>
+                     : bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR> : nullptr;
+  }
   return bs == 1024 ? pcg_fn_vb<T, K, LR, 1024>(vpt)
                     : bs == NT ? pcg_fn_vb<T, K, LR, NT>(vpt) : nullptr;
 }
