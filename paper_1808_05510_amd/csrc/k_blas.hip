@@ -816,10 +816,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
 // injection tiles 2w, 2w + 1 (32 injections) and keeps their T^T fragments for
 // every k in registers, loaded once; the workgroup then walks 16-voxel tiles
 // (grid-stride), each wave streaming the tile's U fragments (the next tile's
-// are in flight while the current tile's MFMAs run).  No LDS, no barriers: T
-// is read once per workgroup instead of once per voxel tile, and the MFMA
-// chain of a tile is 2 KS back-to-back instructions.  KS = k steps of 4
-// (r <= 4 KS); the mask word of a wave's 32 injections is a single bits word.
+// are in flight while the current tile's MFMAs run).  No LDS: T is read once
+// per workgroup instead of once per voxel tile, and the MFMA chain of a tile
+// is 2 KS back-to-back instructions.  KS = k steps of 4 (r <= 4 KS; exact
+// for KS > 16); the mask word of a wave's 32 injections is a single bits
+// word.  The register budget decides the overlap of MFMAs with memory: at
+// r = 100 the FP64 variant holds 224 VGPRs, two waves per SIMD.  SYNC adds a
+// workgroup barrier per tile (the four waves then read each U tile together).
+// HAS_OY selects N = OY - Omega o (U T) over N = Omega o (U T).
 template <typename T, int KS, bool HAS_OY, bool SYNC>
 __global__ __launch_bounds__(NT) void k_masked_gemm_rt(
     int64_t n, int r, int ninj, const T* __restrict__ U, int64_t ldu, const double* __restrict__ Tm,

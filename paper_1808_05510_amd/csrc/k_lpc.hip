@@ -2,7 +2,7 @@
 // grid: a small two-level 3-D convolutional network trained on the GPU by
 // the kernels below (forward, data gradient, weight gradient, pooling,
 // loss, Adam), applied inside flexible CG with the base step as fallback and
-// Jacobi-PCG as the final judge.
+// Jacobi-PCG as the last resort.
 //
 // Grid: nx * ny * nz voxels, index v = x + nx (y + ny z), the numbering of
 // the box generator.  Activations are channel-major [C][N] float.
