@@ -13,9 +13,9 @@ passes, one counter each:
 `summarize FETCH_CSV WRITE_CSV STEM` then sums the counters (KiB per
 dispatch) over the library kernels of the second call, scales each counter by
 copy bytes / counter reading of the copy, and writes STEM.md (table and the
-commands) and STEM.json (figures plus a hash of the file that holds the
-kernels, so that a reader can tell whether they changed since the counters
-were taken).
+commands) and STEM.json (figures plus a hash of the code, comments and layout excluded, of
+the file that holds the kernels, so that a reader can tell whether they
+changed since the counters were taken).
 """
 from __future__ import annotations
 
@@ -23,6 +23,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
@@ -34,12 +35,20 @@ RANK = 100
 KERNEL_SOURCES = ("k_blas.hip",)
 
 
+def _code_only(src: str) -> str:
+    """The source with comments removed and whitespace collapsed, so that an
+    edit of comments or layout leaves the hash unchanged."""
+    src = re.sub(r"//[^\n]*", "", src)
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return re.sub(r"\s+", " ", src).strip()
+
+
 def sources_hash() -> str:
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(CSRC, name), "rb") as f:
+        with open(os.path.join(CSRC, name)) as f:
             h.update(name.encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -128,7 +137,8 @@ def summarize(fetch_csv, write_csv, stem, n_y=262136, n_x=131068, n_inj=128):
     lines += ["", f"Scaled: fetch {fetch/1e6:.1f} MB, write {write/1e6:.1f} MB, total "
               f"{(fetch+write)/1e6:.1f} MB against {alg/1e6:.1f} MB algorithmic "
               f"({(fetch+write)/alg:.2f}x).", "",
-              f"Kernel sources hash: `{res['sources_sha']}`."]
+              f"Kernel sources hash (code only, comments and whitespace excluded): "
+              f"`{res['sources_sha']}`."]
     with open(stem + ".md", "w") as f:
         f.write("\n".join(lines) + "\n")
     print(json.dumps(res))
