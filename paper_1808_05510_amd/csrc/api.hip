@@ -66,7 +66,8 @@ struct cr_problem {
   int fcg_mode = 0;         // u-systems: 0 Jacobi-PCG, 1 FCG + base step, 2 FCG + base step + network
   BoxBasis boxy;            // spectral basis of the target grid when it is a full box
   BoxBasis boxx;            // spectral basis of the source grid when it is a full box
-  bool kr_omega_ready = false;  // workspace "kraux" holds the BF16 copy of Omega
+  bool kr_omega_ready = false;
+  bool smw_xh_ready = false;    // workspace "smw_Xh" holds Q^T X of the source box  // workspace "kraux" holds the BF16 copy of Omega
   int64_t pc_fallbacks = 0;
   int cu_share = 0;         // > 0: persistent grids limited to this many CUs' worth of slots
   int coop = 1;             // persistent kernels launched cooperatively
@@ -659,8 +660,8 @@ struct Ctx {
   cr_status smw_v(const T* b, T* xout, double rtol, SolveOut* out, bool& done) {
     done = false;
     const int64_t n = nx;
-    double* Y = WS(double, "smw_Y", n * ninj);
-    double* YT = WS(double, "smw_YT", n * ninj);
+    double* Xh = WS(double, "smw_Xh", n * ninj);  // Q^T X of the source box, per handle
+    double* Yh = WS(double, "smw_Yh", n * ninj);  // Xh scaled by 1/s, per solve
     double* Km = WS(double, "smw_K", (int64_t)ninj * ninj);
     double* h = WS(double, "smw_h", ninj);
     double* kv = WS(double, "smw_k", ninj);
@@ -671,14 +672,21 @@ struct Ctx {
     double* w64 = WS(double, "smw_w", n);
     const double* X64 = P->X64;
     CR_TRY((convert2d<double, T>(n, 1, b, n, b64, n, st)));
-    // Y = S^-1 X, K = chol(I + G^1/2 X^T Y G^1/2)
-    CR_TRY(box_spectral_solve_cols(P->boxx, cv, lam, nullptr, ninj, X64, n, Y, n, YT, n, st));
-    Blocks<double> A, B;
+    if (!P->smw_xh_ready) {
+      CR_TRY(box_transform_cols(P->boxx, false, ninj, X64, n, Xh, n, Yh, n, st));
+      P->smw_xh_ready = true;
+    }
+    // K = chol(I + G^1/2 Xh^T diag(1/s) Xh G^1/2)
+    CR_HIP(hipMemcpyAsync(Yh, Xh, sizeof(double) * n * ninj, hipMemcpyDeviceToDevice, st));
+    CR_TRY(box_scale_cols(P->boxx, cv, lam, nullptr, ninj, Yh, n, st));
+    Blocks<double> A, B, H;
     A.clear();
     A.add(X64, n, ninj);
+    H.clear();
+    H.add(Xh, n, ninj);
     B.clear();
-    B.add(Y, n, ninj);
-    CR_TRY(gemm_tn<double>(n, A, B, nullptr, nullptr, 0, Km, ninj, gpart, gemm_part_cap(P), st));
+    B.add(Yh, n, ninj);
+    CR_TRY(gemm_tn<double>(n, H, B, nullptr, nullptr, 0, Km, ninj, gpart, gemm_part_cap(P), st));
     CR_TRY(smw_factor(ninj, gw, Km, st));
     // x = 0, r = b; then x += SMW(r), r = b - A x, up to three times
     CR_HIP(hipMemsetAsync(x64, 0, sizeof(double) * n, st));
@@ -686,10 +694,16 @@ struct Ctx {
     CR_TRY(dot64(n, b64, b64, tmp + 9));
     double q[2] = {0.0, 0.0};
     for (int pass = 0; pass < 3; ++pass) {
-      CR_TRY(box_spectral_solve(P->boxx, cv, lam, nullptr, r64, t64, w64, st));
-      CR_TRY((gemv_tx<double, double>(n, A, t64, h, part, st)));
+      // rh = Q^T r (in w64); th = rh / s (in t64); h = Xh^T th
+      CR_TRY(box_transform_cols(P->boxx, false, 1, r64, n, w64, n, t64, n, st));
+      CR_HIP(hipMemcpyAsync(t64, w64, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      CR_TRY(box_scale_cols(P->boxx, cv, lam, nullptr, 1, t64, n, st));
+      CR_TRY((gemv_tx<double, double>(n, H, t64, h, part, st)));
       CR_TRY(smw_apply(ninj, gw, Km, h, kv, st));
-      CR_TRY(gemv_n<double>(n, B, kv, 1.0, t64, st));  // t - Y G^1/2 K^-1 G^1/2 X^T t
+      // xh = (rh + Xh k) / s, increment = Q xh
+      CR_TRY(gemv_n<double>(n, H, kv, 1.0, w64, st));
+      CR_TRY(box_scale_cols(P->boxx, cv, lam, nullptr, 1, w64, n, st));
+      CR_TRY(box_transform_cols(P->boxx, true, 1, w64, n, t64, n, r64, n, st));
       hipLaunchKernelGGL(k_add_to, dim3(nblk(n)), dim3(256), 0, st, n, t64, x64);
       CR_HIP(hipGetLastError());
       // r = b - A x in FP64 with FP64 operator data
@@ -1980,6 +1994,7 @@ extern "C" cr_status cr_problem_set_box(cr_problem* P, int32_t which, const int3
     CR_HIP(hipMemcpy(bx.mu[a], mu.data(), sizeof(double) * m, hipMemcpyHostToDevice));
   }
   (which == 0 ? P->boxy : P->boxx) = bx;
+  if (which != 0) P->smw_xh_ready = false;
   return CR_OK;
 }
 

@@ -249,6 +249,15 @@ cr_status box_spectral_solve_cols(const BoxBasis& bx, const double* c, double la
                                   const double* dbar, int ncols, const double* R, int64_t ldr,
                                   double* OUT, int64_t ldo, double* TMP, int64_t ldt,
                                   hipStream_t st);
+// The three passes of Q^T (forward) or Q (inverse) alone, on ncols columns;
+// OUT receives the result, TMP is scratch of the same shape (ldt).
+cr_status box_transform_cols(const BoxBasis& bx, bool inverse, int ncols, const double* R,
+                             int64_t ldr, double* OUT, int64_t ldo, double* TMP, int64_t ldt,
+                             hipStream_t st);
+// XH[:, j] /= lam (mu^2 + c[0] mu + c[1]) + dbar[0] in the spectral domain
+// (dbar may be null: 0), ncols columns of leading dimension ld
+cr_status box_scale_cols(const BoxBasis& bx, const double* c, double lam, const double* dbar,
+                         int ncols, double* XH, int64_t ld, hipStream_t st);
 // SMW solve of the v-system on a full source box (n_inj <= SMW_MAX)
 constexpr int SMW_MAX = 128;
 cr_status smw_factor(int n, const double* g, double* K, hipStream_t st);

@@ -24,32 +24,47 @@ namespace cr {
 //   inverse (Q):    out[.., j, ..] = sum_k Q[j m + k] in[.., k, ..]
 // Q is row-major m x m (row = position j, column = mode k).
 // blockIdx.y selects the column of an n x ncols block (leading dimensions
-// ldi, ldo).
+// ldi, ldo).  Index arithmetic is 32-bit (the box has fewer than 2^31
+// voxels, checked when the basis is built) and the m-term sum runs four
+// independent partial sums, so the loads of several terms are in flight at
+// once: the transform is latency-bound at these sizes.
 __global__ __launch_bounds__(NT) void k_box_axis(int d0, int d1, int d2, int axis,
                                                  const double* __restrict__ Q, int inverse,
                                                  const double* __restrict__ in, int64_t ldi,
                                                  double* __restrict__ out, int64_t ldo) {
-  const int64_t n = (int64_t)d0 * d1 * d2;
-  const int64_t o = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int n = d0 * d1 * d2;
+  const int o = blockIdx.x * NT + threadIdx.x;
   if (o >= n) return;
   in += (int64_t)blockIdx.y * ldi;
   out += (int64_t)blockIdx.y * ldo;
-  const int i0 = (int)(o % d0);
-  const int64_t rest = o / d0;
-  const int i1 = (int)(rest % d1);
-  const int i2 = (int)(rest / d1);
-  const int m = axis == 0 ? d0 : axis == 1 ? d1 : d2;
-  const int t = axis == 0 ? i0 : axis == 1 ? i1 : i2;
-  const int64_t s = axis == 0 ? 1 : axis == 1 ? (int64_t)d0 : (int64_t)d0 * d1;
-  const int64_t base = o - (int64_t)t * s;
-  double acc = 0.0;
-  if (inverse) {
-    const double* qrow = Q + (int64_t)t * m;
-    for (int k = 0; k < m; ++k) acc += qrow[k] * in[base + k * s];
+  int t, s, m;
+  if (axis == 0) {
+    t = o % d0;
+    s = 1;
+    m = d0;
+  } else if (axis == 1) {
+    t = (o / d0) % d1;
+    s = d0;
+    m = d1;
   } else {
-    for (int j = 0; j < m; ++j) acc += Q[(int64_t)j * m + t] * in[base + j * s];
+    s = d0 * d1;
+    t = o / s;
+    m = d2;
   }
-  out[o] = acc;
+  const double* ib = in + (o - t * s);
+  // inverse: coefficients Q[t m + k] (stride 1); forward: Q[k m + t] (stride m)
+  const double* q = inverse ? Q + t * m : Q + t;
+  const int qs = inverse ? 1 : m;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= m; k += 4) {
+    a0 += q[k * qs] * ib[k * s];
+    a1 += q[(k + 1) * qs] * ib[(k + 1) * s];
+    a2 += q[(k + 2) * qs] * ib[(k + 2) * s];
+    a3 += q[(k + 3) * qs] * ib[(k + 3) * s];
+  }
+  for (; k < m; ++k) a0 += q[k * qs] * ib[k * s];
+  out[o] = (a0 + a1) + (a2 + a3);
 }
 
 // xhat /= lam (mu^2 + c[0] mu + c[1]) + dbar   (c = [2 b, a]; dbar may be null: 0)
@@ -101,14 +116,45 @@ cr_status box_spectral_solve_cols(const BoxBasis& bx, const double* c, double la
   return CR_OK;
 }
 
+cr_status box_transform_cols(const BoxBasis& bx, bool inverse, int ncols, const double* R,
+                             int64_t ldr, double* OUT, int64_t ldo, double* TMP, int64_t ldt,
+                             hipStream_t st) {
+  if (ncols <= 0) return CR_OK;
+  const int64_t n = (int64_t)bx.dims[0] * bx.dims[1] * bx.dims[2];
+  const dim3 g((unsigned)((n + NT - 1) / NT), (unsigned)ncols);
+  const int d0 = bx.dims[0], d1 = bx.dims[1], d2 = bx.dims[2];
+  const int inv = inverse ? 1 : 0;
+  // forward: axes 0, 1, 2; inverse: axes 2, 1, 0 (R -> OUT -> TMP -> OUT)
+  const int a0 = inverse ? 2 : 0, a2 = inverse ? 0 : 2;
+  hipLaunchKernelGGL(k_box_axis, g, dim3(NT), 0, st, d0, d1, d2, a0, bx.Q[a0], inv, R, ldr, OUT, ldo);
+  hipLaunchKernelGGL(k_box_axis, g, dim3(NT), 0, st, d0, d1, d2, 1, bx.Q[1], inv, OUT, ldo, TMP, ldt);
+  hipLaunchKernelGGL(k_box_axis, g, dim3(NT), 0, st, d0, d1, d2, a2, bx.Q[a2], inv, TMP, ldt, OUT, ldo);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+cr_status box_scale_cols(const BoxBasis& bx, const double* c, double lam, const double* dbar,
+                         int ncols, double* XH, int64_t ld, hipStream_t st) {
+  if (ncols <= 0) return CR_OK;
+  const int64_t n = (int64_t)bx.dims[0] * bx.dims[1] * bx.dims[2];
+  const dim3 g((unsigned)((n + NT - 1) / NT), (unsigned)ncols);
+  hipLaunchKernelGGL(k_box_scale, g, dim3(NT), 0, st, bx.dims[0], bx.dims[1], bx.dims[2],
+                     bx.mu[0], bx.mu[1], bx.mu[2], c, lam, dbar, XH, ld);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
 // ---------------------------------------------------------------- v-system by SMW
 // The v-system of eq. ALS_linsys_v is S + X G X^T with S = lam (L_x^2 + 2 c L_x
 // + e I), diagonal in the source box's basis, and G = diag(g), g >= 0.  With
 // W = X G^1/2, the Sherman-Morrison-Woodbury identity gives
-//   (S + W W^T)^-1 b = t - Y G^1/2 K^-1 G^1/2 X^T t,
-//   t = S^-1 b,  Y = S^-1 X,  K = I + G^1/2 X^T Y G^1/2  (SPD, n_inj x n_inj),
+//   (S + W W^T)^-1 b = S^-1 (b + X k),  k = -G^1/2 K^-1 G^1/2 X^T S^-1 b,
+//   K = I + G^1/2 X^T S^-1 X G^1/2  (SPD, n_inj x n_inj),
 // the paper's SMW route for this system with the spectral solve in place of
-// a sparse factorisation.  K is factored (Cholesky) by one workgroup in LDS.
+// a sparse factorisation.  With S = Q diag(s) Q^T and Xh = Q^T X (fixed per
+// handle), X^T S^-1 X = Xh^T diag(1/s) Xh and X^T S^-1 b = Xh^T (bh / s), so
+// one solve needs single-column transforms only.  K is factored (Cholesky)
+// by one workgroup in LDS.
 
 // K (n x n, column-major, holds X^T Y on entry) <- lower Cholesky factor of
 // I + G^1/2 sym(X^T Y) G^1/2; a non-positive pivot leaves NaN in the factor
