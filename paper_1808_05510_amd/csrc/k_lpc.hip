@@ -83,6 +83,58 @@ __global__ __launch_bounds__(NT) void k_conv_fwd(Dims d, int CI, int CO, const f
   }
 }
 
+// Inference form of the same convolution: one thread per (voxel, group of G
+// output channels), the group on grid.y.  Taps and input channels are
+// unrolled at compile time (one z-plane of taps at a time), out-of-box taps
+// read the voxel itself with a zero factor, so the 9 * CI loads of a plane
+// are independent and in flight together.  At 40^3 the one-output-set-per-thread form had one wave per SIMD
+// and paid each load's latency in turn; splitting the outputs over G-groups
+// multiplies the waves.
+template <int CI, int G>
+__global__ __launch_bounds__(NT) void k_conv_fwd_g(Dims d, const float* __restrict__ in,
+                                                   const float* __restrict__ W,
+                                                   const float* __restrict__ bias,
+                                                   float* __restrict__ out, int relu) {
+  __shared__ float ws[G * CI * 27];
+  const int co0 = blockIdx.y * G;
+  for (int e = threadIdx.x; e < G * CI * 27; e += NT) ws[e] = W[co0 * CI * 27 + e];
+  __syncthreads();
+  const int N = d.nx * d.ny * d.nz;
+  const int v = blockIdx.x * NT + threadIdx.x;
+  if (v >= N) return;
+  const int x = v % d.nx;
+  const int t = v / d.nx;
+  const int y = t % d.ny;
+  const int z = t / d.ny;
+  float acc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g] = bias[co0 + g];
+  // one z-plane of taps (9 x CI loads) unrolled at a time: all taps at once
+  // held 216 loads in flight and 454+ VGPRs (one wave per SIMD, spills at G 2)
+#pragma unroll 1
+  for (int kz = 0; kz < 3; ++kz) {
+    const int zz = z + kz - 1;
+#pragma unroll
+    for (int kk = 0; kk < 9; ++kk) {
+      const int k = 9 * kz + kk;
+      const int dy = kk / 3 - 1, dx = kk % 3 - 1;
+      const int xx = x + dx, yy = y + dy;
+      const bool inside =
+          xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz;
+      const int u = inside ? xx + d.nx * (yy + d.ny * zz) : v;
+      const float f = inside ? 1.f : 0.f;
+#pragma unroll
+      for (int ci = 0; ci < CI; ++ci) {
+        const float val = f * in[ci * N + u];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] += ws[(g * CI + ci) * 27 + k] * val;
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) out[(co0 + g) * N + v] = relu ? fmaxf(acc[g], 0.f) : acc[g];
+}
+
 // ---------------------------------------------------------------- conv data gradient
 // din[ci][v] = sum_{co,k} W[co][ci][k] dout[co][v - off_k]
 __global__ __launch_bounds__(NT) void k_conv_dgrad(Dims d, int CI, int CO,
@@ -368,18 +420,36 @@ __global__ __launch_bounds__(NT) void k_adam(int n, float* __restrict__ w, float
 // ================================================================ host side
 static inline unsigned nb(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
+// one convolution layer: the unrolled form when CI is 4 or 8 and the output
+// count splits into groups of G (2 at full resolution, 1 on the coarse grid
+// and for the single output channel), else the general form
+static void conv(const Dims& d, int CI, int CO, bool fine, const float* in, const float* W,
+                 const float* B, float* out, int relu, hipStream_t st) {
+  const int64_t N = (int64_t)d.nx * d.ny * d.nz;
+  const int G = (fine && CO % 2 == 0) ? 2 : 1;
+  const dim3 grid(nb(N), (unsigned)(CO / G));
+#define CV(CC, GG)                                                                          \
+  if (CI == CC && G == GG && N <= INT32_MAX) {                                              \
+    hipLaunchKernelGGL((k_conv_fwd_g<CC, GG>), grid, dim3(NT), 0, st, d, in, W, B, out, relu); \
+    return;                                                                                 \
+  }
+  CV(4, 1) CV(4, 2) CV(8, 1) CV(8, 2)
+#undef CV
+  hipLaunchKernelGGL(k_conv_fwd, dim3(nb(N)), dim3(NT), 0, st, d, CI, CO, in, W, B, out, relu);
+}
+
 cr_status lpc_forward(const LpcNet& net, const float* in, LpcActs& a, hipStream_t st) {
   const Dims d{net.nx, net.ny, net.nz};
   const Dims c = coarse(d);
   const int64_t N = (int64_t)d.nx * d.ny * d.nz, Nc = (int64_t)c.nx * c.ny * c.nz;
   const int C = net.C;
-  hipLaunchKernelGGL(k_conv_fwd, dim3(nb(N)), dim3(NT), 0, st, d, 4, C, in, net.W[0], net.B[0], a.a0, 1);
-  hipLaunchKernelGGL(k_conv_fwd, dim3(nb(N)), dim3(NT), 0, st, d, C, C, a.a0, net.W[1], net.B[1], a.a1, 1);
+  conv(d, 4, C, true, in, net.W[0], net.B[0], a.a0, 1, st);
+  conv(d, C, C, true, a.a0, net.W[1], net.B[1], a.a1, 1, st);
   hipLaunchKernelGGL(k_pool_fwd, dim3(nb(Nc)), dim3(NT), 0, st, d, C, a.a1, a.p);
-  hipLaunchKernelGGL(k_conv_fwd, dim3(nb(Nc)), dim3(NT), 0, st, c, C, C, a.p, net.W[2], net.B[2], a.a2, 1);
-  hipLaunchKernelGGL(k_conv_fwd, dim3(nb(Nc)), dim3(NT), 0, st, c, C, C, a.a2, net.W[3], net.B[3], a.a3, 1);
+  conv(c, C, C, false, a.p, net.W[2], net.B[2], a.a2, 1, st);
+  conv(c, C, C, false, a.a2, net.W[3], net.B[3], a.a3, 1, st);
   hipLaunchKernelGGL(k_up_add, dim3(nb(N)), dim3(NT), 0, st, d, C, a.a3, a.a1, a.s);
-  hipLaunchKernelGGL(k_conv_fwd, dim3(nb(N)), dim3(NT), 0, st, d, C, 1, a.s, net.W[4], net.B[4], a.y, 0);
+  conv(d, C, 1, true, a.s, net.W[4], net.B[4], a.y, 0, st);
   CR_HIP(hipGetLastError());
   return CR_OK;
 }
