@@ -212,7 +212,10 @@ __global__ __launch_bounds__(NT) void k_gemv_t(int64_t n, Blocks<T> A, const TX*
   }
   const int nc = A.ncols();
   const bool full = (int64_t)(blockIdx.x + 1) * GT_RB <= n;
-  for (int c0 = wv; c0 < nc; c0 += 4 * 4) {
+  // grid.y splits the columns in groups of 16 (4 per wave): a tall product
+  // of a few hundred columns then launches nrb x ncols/16 workgroups instead
+  // of nrb (125 at 64,000 rows), enough loads in flight to reach HBM speed
+  for (int c0 = (int)blockIdx.y * 16 + wv; c0 < nc; c0 += 16 * (int)gridDim.y) {
     double acc[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -267,7 +270,8 @@ cr_status gemv_tx(int64_t n, const Blocks<T>& A, const TX* x, double* y, double*
     CR_HIP(hipMemsetAsync(y, 0, sizeof(double) * nc, st));
     return CR_OK;
   }
-  hipLaunchKernelGGL((k_gemv_t<T, TX>), dim3(nrb), dim3(NT), 0, st, n, A, x, part, nrb);
+  hipLaunchKernelGGL((k_gemv_t<T, TX>), dim3(nrb, (unsigned)((nc + 15) / 16)), dim3(NT), 0, st, n,
+                     A, x, part, nrb);
   CR_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_part, dim3((nc + 3) / 4), dim3(NT), 0, st, nc, nrb, part, y);
   CR_HIP(hipGetLastError());
