@@ -154,6 +154,11 @@ def bench_batch(count=16, max_rank=40, tau=1e-4, prec="mixed", precond="jacobi")
             p.set_precond(precond)
     opts = dict(max_rank=max_rank, tau_res=tau, seed=0,
                 pcg_rtol=MIXED_RTOL if prec == "mixed" else FP64_RTOL)
+    # PCG grid shapes from the tuning table (one autotune per size bucket)
+    t0 = time.perf_counter()
+    table = connreg.TuningTable()
+    shapes = [table.apply(p) for p in probs]
+    tune_s = time.perf_counter() - t0
     # warm-up (workspace allocation) then sequential timing
     connreg.greedy_solve_batch(probs[:1], [dict(opts, max_rank=2)])
     for p in probs:
@@ -168,6 +173,8 @@ def bench_batch(count=16, max_rank=40, tau=1e-4, prec="mixed", precond="jacobi")
     torch.cuda.synchronize()
     t_bat = time.perf_counter() - t0
     out = dict(problems=count, precision=prec, precond=precond, generation_s=gen,
+               tuning=dict(buckets=len(table.table), seconds=tune_s,
+                           vpt=[[e["vpt_u"], e["vpt_v"]] for e in shapes]),
                sequential_s=t_seq, batched_s=t_bat, speedup=t_seq / t_bat,
                sizes=[[p.n_y, p.n_x, p.n_inj] for p in probs],
                ranks_seq=[r["rank"] for r in seq], ranks_batch=[r["rank"] for r in bat],

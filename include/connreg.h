@@ -333,7 +333,8 @@ cr_status cr_greedy_solve_batch(int32_t count, cr_problem** probs, const cr_solv
  * voxels per thread 1, 2, 4, 8 (those whose grid fits in cu_share CUs;
  * cu_share <= 0: the whole device) and keeps the fastest for later solves
  * with pcg_vpt = 0.  Outputs [host], may be NULL: chosen values and
- * microseconds per iteration.  FP64 handles.  Synchronises. */
+ * microseconds per iteration.  FP64 and mixed handles (the mixed handle times
+ * its FP32 PCG).  Synchronises. */
 cr_status cr_autotune_pcg(cr_problem* p, int32_t cu_share, int32_t* vpt_u, int32_t* vpt_v,
                           double* us_u, double* us_v);
 /* Set the tuned values directly (e.g. from a cache); 0 = heuristic. */

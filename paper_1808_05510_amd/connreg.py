@@ -8,6 +8,8 @@ torch tensor of shape (n, k) with strides (1, ld).  ``colmajor`` makes one.
 from __future__ import annotations
 
 import ctypes
+import json
+import math
 import os
 from ctypes import POINTER, c_double, c_int32, c_int64, c_uint64, c_void_p
 
@@ -455,6 +457,51 @@ class Pc:
                                        coef.ctypes.data_as(POINTER(c_double)), lr,
                                        ctypes.byref(loss)))
         return loss.value
+
+
+class TuningTable:
+    """PCG grid shapes (voxels per thread of the u- and v-system grids) by
+    problem-size bucket, kept in a JSON file: the first problem of a bucket is
+    timed by cr_autotune_pcg, later problems of the bucket reuse the choice.
+    A bucket is the precision, n_y and n_x in half-octaves, n_inj rounded up
+    to a multiple of 16 and the CU share the grids are limited to."""
+
+    def __init__(self, path: str | None = None):
+        self.path = path
+        self.table = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.table = json.load(f)
+
+    @staticmethod
+    def bucket(prob: "Problem", cu_share: int = 0) -> str:
+        def half_octave(n):
+            return int(round(2 * math.log2(max(int(n), 1))))
+        inj = 16 * ((int(prob.n_inj) + 15) // 16)
+        return (f"{prob.precision}/ny{half_octave(prob.n_y)}/nx{half_octave(prob.n_x)}"
+                f"/inj{inj}/share{int(cu_share)}")
+
+    def apply(self, prob: "Problem", cu_share: int = 0, tune_missing: bool = True):
+        """Set the problem's PCG shapes from its bucket (tuning it first when
+        the bucket is new and tune_missing); returns the entry or None."""
+        key = self.bucket(prob, cu_share)
+        if key not in self.table:
+            if not tune_missing:
+                return None
+            vu, vv, tu, tv = prob.autotune(cu_share)
+            self.table[key] = dict(vpt_u=int(vu), vpt_v=int(vv), us_per_iter_u=float(tu),
+                                   us_per_iter_v=float(tv))
+            self.save()
+        e = self.table[key]
+        prob.set_tuning(int(e["vpt_u"]), int(e["vpt_v"]))
+        return e
+
+    def save(self):
+        if self.path:
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.table, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
 
 
 def greedy_solve_batch(problems, opts_list):

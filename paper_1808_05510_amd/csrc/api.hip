@@ -2282,12 +2282,9 @@ extern "C" cr_status cr_greedy_solve_batch(int32_t count, cr_problem** probs,
 // Autotuner: times 60 Jacobi-PCG iterations of a representative u- and
 // v-system for each admissible voxels-per-thread (1, 2, 4, 8) within the
 // handle's current workgroup cap and keeps the fastest for later solves.
-extern "C" cr_status cr_autotune_pcg(cr_problem* P, int32_t cu_share, int32_t* vpt_u,
-                                     int32_t* vpt_v, double* us_u, double* us_v) {
-  if (!P || P->prec != CR_PREC_FP64) {
-    set_error("cr_autotune_pcg needs an FP64 handle");
-    return CR_EINVAL;
-  }
+template <typename T>
+static cr_status autotune_impl(cr_problem* P, int32_t cu_share, int32_t* vpt_u, int32_t* vpt_v,
+                               double* us_u, double* us_v) {
   const int saved = P->cu_share;
   P->cu_share = cu_share > 0 ? cu_share : saved;
   cr_status status = CR_OK;
@@ -2297,7 +2294,7 @@ extern "C" cr_status cr_autotune_pcg(cr_problem* P, int32_t cu_share, int32_t* v
   CR_HIP(hipEventCreate(&e0));
   CR_HIP(hipEventCreate(&e1));
   for (int v = 1; v <= 8 && status == CR_OK; v *= 2) {
-    Ctx<double> c(P);
+    Ctx<T> c(P);
     status = c.alloc_rank(1);
     if (status != CR_OK) break;
     status = c.alloc_vectors(v);
@@ -2309,13 +2306,13 @@ extern "C" cr_status cr_autotune_pcg(cr_problem* P, int32_t cu_share, int32_t* v
     double hc[2] = {1.0, 0.5};
     CR_HIP(hipMemcpyAsync(c.cu, hc, sizeof(hc), hipMemcpyHostToDevice, c.st));
     CR_HIP(hipMemcpyAsync(c.cv, hc, sizeof(hc), hipMemcpyHostToDevice, c.st));
-    CR_TRY(splitmix_fill<double>(c.ny, 7, 1, c.rhs_u, c.st));
-    CR_TRY(splitmix_fill<double>(c.nx, 7, 2, c.rhs_v, c.st));
-    CR_TRY(splitmix_fill<double>(c.ny, 7, 3, c.dvec, c.st));
+    CR_TRY(splitmix_fill<T>(c.ny, 7, 1, c.rhs_u, c.st));
+    CR_TRY(splitmix_fill<T>(c.nx, 7, 2, c.rhs_v, c.st));
+    CR_TRY(splitmix_fill<T>(c.ny, 7, 3, c.dvec, c.st));
     std::vector<double> ones(c.ninj, 1.0);
     CR_HIP(hipMemcpyAsync(c.gw, ones.data(), sizeof(double) * c.ninj, hipMemcpyHostToDevice, c.st));
-    CR_TRY(pcg_diag<double>(P->gy, c.lam, c.cu, c.dvec, nullptr, 0, 0, nullptr, c.minv_u, c.st));
-    CR_TRY(pcg_diag<double>(P->gx, c.lam, c.cv, nullptr, c.X(), c.nx, c.ninj, c.gw, c.minv_v, c.st));
+    CR_TRY(pcg_diag<T>(P->gy, c.lam, c.cu, c.dvec, nullptr, 0, 0, nullptr, c.minv_u, c.st));
+    CR_TRY(pcg_diag<T>(P->gx, c.lam, c.cv, nullptr, c.X(), c.nx, c.ninj, c.gw, c.minv_v, c.st));
     for (int sys = 0; sys < 2; ++sys) {
       const bool us = sys == 0;
       double t = 0.0;
@@ -2348,6 +2345,16 @@ extern "C" cr_status cr_autotune_pcg(cr_problem* P, int32_t cu_share, int32_t* v
   if (us_u) *us_u = best[0];
   if (us_v) *us_v = best[1];
   return CR_OK;
+}
+
+extern "C" cr_status cr_autotune_pcg(cr_problem* P, int32_t cu_share, int32_t* vpt_u,
+                                     int32_t* vpt_v, double* us_u, double* us_v) {
+  if (!P) {
+    set_error("null handle");
+    return CR_EINVAL;
+  }
+  return P->prec == CR_PREC_FP64 ? autotune_impl<double>(P, cu_share, vpt_u, vpt_v, us_u, us_v)
+                                 : autotune_impl<float>(P, cu_share, vpt_u, vpt_v, us_u, us_v);
 }
 
 extern "C" cr_status cr_problem_set_tuning(cr_problem* P, int32_t vpt_u, int32_t vpt_v) {

@@ -156,38 +156,46 @@ cr_status box_scale_cols(const BoxBasis& bx, const double* c, double lam, const 
 // one solve needs single-column transforms only.  K is factored (Cholesky)
 // by one workgroup in LDS.
 
-// K (n x n, column-major, holds X^T Y on entry) <- lower Cholesky factor of
-// I + G^1/2 sym(X^T Y) G^1/2; a non-positive pivot leaves NaN in the factor
-// (the caller's residual check then rejects the solve).
-__global__ __launch_bounds__(NT) void k_smw_factor(int n, const double* __restrict__ g,
-                                                   double* __restrict__ K) {
+// K (n x n, column-major, holds the Gram X^T S^-1 X on entry) <- lower
+// Cholesky factor of I + G^1/2 sym(K) G^1/2; a non-positive pivot leaves NaN
+// in the factor (the caller's residual check then rejects the solve).
+// Right-looking, one barrier per column: step k updates the trailing lower
+// triangle with A_ik A_jk / A_kk (no square root needed there) and writes the
+// scaled column L_ik = A_ik / sqrt(A_kk) into the upper triangle, which no
+// thread reads; the diagonal goes to its own array.
+constexpr int SMW_NT = 1024;
+
+__global__ __launch_bounds__(SMW_NT) void k_smw_factor(int n, const double* __restrict__ g,
+                                                       double* __restrict__ K) {
   __shared__ double A[SMW_MAX][SMW_MAX + 1];
+  __shared__ double dg[SMW_MAX];
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += NT) {
+  for (int e = tid; e < n * n; e += SMW_NT) {
     const int i = e % n, j = e / n;
     const double v = 0.5 * (K[(int64_t)j * n + i] + K[(int64_t)i * n + j]);
     A[i][j] = sqrt(g[i] * g[j]) * v + (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      const double d = A[k][k];
-      A[k][k] = d > 0.0 ? sqrt(d) : __builtin_nan("");
-    }
-    __syncthreads();
-    const double dk = A[k][k];
-    for (int i = k + 1 + tid; i < n; i += NT) A[i][k] /= dk;
-    __syncthreads();
+    const double akk = A[k][k];
+    const double inv = 1.0 / akk;
+    const double rs = akk > 0.0 ? 1.0 / sqrt(akk) : __builtin_nan("");
     const int m = n - k - 1;
-    for (int e = tid; e < m * m; e += NT) {
-      const int i = k + 1 + e % m, j = k + 1 + e / m;
-      if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+    // trailing lower triangle (k < j <= i < n) over the m x m square
+    for (int e = tid; e < m * m; e += SMW_NT) {
+      const int a = e / m, b = e - a * m;
+      if (b <= a) {
+        const int i = k + 1 + a, j = k + 1 + b;
+        A[i][j] -= A[i][k] * A[j][k] * inv;
+      }
     }
+    for (int i = k + 1 + tid; i < n; i += SMW_NT) A[k][i] = A[i][k] * rs;
+    if (tid == 0) dg[k] = akk > 0.0 ? sqrt(akk) : __builtin_nan("");
     __syncthreads();
   }
-  for (int e = tid; e < n * n; e += NT) {
+  for (int e = tid; e < n * n; e += SMW_NT) {
     const int i = e % n, j = e / n;
-    K[(int64_t)j * n + i] = j <= i ? A[i][j] : 0.0;
+    K[(int64_t)j * n + i] = j < i ? A[j][i] : (j == i ? dg[i] : 0.0);
   }
 }
 
@@ -222,7 +230,7 @@ cr_status smw_factor(int n, const double* g, double* K, hipStream_t st) {
     set_error("SMW factor: n_inj out of range");
     return CR_EINVAL;
   }
-  hipLaunchKernelGGL(k_smw_factor, dim3(1), dim3(NT), 0, st, n, g, K);
+  hipLaunchKernelGGL(k_smw_factor, dim3(1), dim3(SMW_NT), 0, st, n, g, K);
   CR_HIP(hipGetLastError());
   return CR_OK;
 }

@@ -98,3 +98,28 @@ def test_autotune_picks_a_valid_shape_and_keeps_results():
     err = omet.diff_norm(b[0], b[1], b[2], a[0], a[1], a[2]) / omet.low_rank_norm(a[0], a[1], a[2])
     assert err < 1e-8
     g.set_tuning(0, 0)
+
+
+def test_mixed_autotune_through_the_tuning_table(tmp_path):
+    """cr_autotune_pcg on a mixed handle (its FP32 PCG), applied and reused
+    through the JSON tuning table; the tuned solve keeps its accuracy."""
+    d = synth.box_problem(box_y=(20, 18, 16), box_x=(14, 12, 10), offset=(2, 2, 2), n_inj=12,
+                          sigma=1.5, hole_r=1.5, wt_rank=4, wt_w=(2.0, 5.0), lam=100.0, seed=9)
+    o = dict(max_rank=4, als_fixed_sweeps=2, pcg_rtol=1e-6, galerkin_rtol=1e-10, seed=1)
+    g = connreg.Problem(d, "mixed", DEV)
+    base = g.greedy_solve(**o)
+    path = str(tmp_path / "tuning.json")
+    e = connreg.TuningTable(path).apply(g)
+    assert e["vpt_u"] in (1, 2, 4, 8) and e["vpt_v"] in (1, 2, 4, 8)
+    assert e["us_per_iter_u"] > 0 and e["us_per_iter_v"] > 0
+    tuned = g.greedy_solve(**o)
+    a = [_np(base[k]) for k in ("U", "Z", "V")]
+    b = [_np(tuned[k]) for k in ("U", "Z", "V")]
+    err = omet.diff_norm(b[0], b[1], b[2], a[0], a[1], a[2]) / omet.low_rank_norm(a[0], a[1], a[2])
+    assert err < 1e-4
+    # a second handle of the same bucket takes the stored shape
+    g2 = connreg.Problem(d, "mixed", DEV)
+    e2 = connreg.TuningTable(path).apply(g2, tune_missing=False)
+    assert e2 == e
+    g.close()
+    g2.close()
