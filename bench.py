@@ -320,6 +320,8 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--op-only", action="store_true", help="only the op_apply bandwidth part")
     ap.add_argument("--batch-only", action="store_true", help="only the 16-problem batch")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="only the mixed solves with the learned preconditioner and the base step")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-shells", action="store_true")
@@ -331,6 +333,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     connreg.load()
 
+    if a.learned_only:
+        d2 = synth.config2(lam=a.lam, seed=0)
+        mopts = dict(max_rank=a.max_rank, tau_res=a.tau, seed=0, pcg_rtol=MIXED_RTOL)
+        lr = bench_learned(d2, a.lam, mopts, a.steps, a.warmup)
+        log(f"[bench] mixed+learned: {lr['learned']['seconds']:.3f} s/solve (base step alone "
+            f"{lr['base']['seconds']:.3f} s)")
+        for kind in ("learned", "base"):
+            e = lr[kind]
+            log(f"[bench] {kind}: rank {e['rank']}, relres {e['relres']:.4e}, "
+                f"pcg iterations {e['pcg_iters']}")
+        return
     if a.batch_only:
         for pre in ("jacobi", "base"):
             b = bench_batch(precond=pre)
