@@ -79,7 +79,11 @@ typedef struct cr_problem cr_problem;
 /* Copies the Laplacians (host) and X, Y, Omega (device) into handle-owned
  * device storage: an ELL neighbour table per Laplacian, Omega as a bitmask
  * plus per-injection lists of unobserved voxels, Omega o Y and X in the
- * working precision.  `hip_stream` is a hipStream_t (NULL = default stream).
+ * working precision.  `hip_stream` is a hipStream_t (NULL = default stream):
+ * the handle's work is ordered on it, and X, Y, Omega are read after the work
+ * already queued on it has finished (writes from other streams must be complete
+ * before the call).  Set-up transfers are staged through pinned host memory on
+ * that stream; the call returns when the handle's data is on the device.
  * Errors: CR_EINVAL for bad sizes or a non-graph-Laplacian, CR_ENOMEM, CR_EHIP. */
 cr_status cr_problem_create(const cr_problem_desc* desc, cr_precision prec, void* hip_stream,
                             cr_problem** out);

@@ -1173,7 +1173,7 @@ struct Ctx {
 };
 
 // ===================================================================== create / destroy
-static cr_status build_geom(const cr_csr& L, Geom& g, const char* which) {
+static cr_status build_geom(const cr_csr& L, Geom& g, const char* which, hipStream_t st) {
   const int64_t n = L.n;
   if (n <= 0 || !L.rowptr || !L.colidx || !L.val) {
     set_error(std::string(which) + ": empty or null CSR");
@@ -1256,8 +1256,8 @@ static cr_status build_geom(const cr_csr& L, Geom& g, const char* which) {
     set_error("device allocation of the neighbour table failed");
     return CR_ENOMEM;
   }
-  CR_HIP(hipMemcpy(g.nbr, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice));
-  CR_HIP(hipMemcpy(g.deg, deg.data(), n, hipMemcpyHostToDevice));
+  CR_HIP(stage_to_device(g.nbr, nbr.data(), sizeof(int32_t) * nbr.size(), st));
+  CR_HIP(stage_to_device(g.deg, deg.data(), n, st));
   // window tables for the multi-column stencil (optional: left null when a
   // tile reads more than WIN_NI intervals or WIN_MAX voxels)
   const int64_t ntile = (n + NT - 1) / NT;
@@ -1312,8 +1312,8 @@ static cr_status build_geom(const cr_csr& L, Geom& g, const char* which) {
       set_error("device allocation of the window tables failed");
       return CR_ENOMEM;
     }
-    CR_HIP(hipMemcpy(g.witab, itab.data(), sizeof(int32_t) * itab.size(), hipMemcpyHostToDevice));
-    CR_HIP(hipMemcpy(g.wpos, wpos.data(), sizeof(uint16_t) * wpos.size(), hipMemcpyHostToDevice));
+    CR_HIP(stage_to_device(g.witab, itab.data(), sizeof(int32_t) * itab.size(), st));
+    CR_HIP(stage_to_device(g.wpos, wpos.data(), sizeof(uint16_t) * wpos.size(), st));
   }
   return CR_OK;
 }
@@ -1355,16 +1355,15 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
     set_error("lambda must be finite and >= 0");
     return CR_EINVAL;
   }
-  CR_TRY(build_geom(d->Ly, P->gy, "L_y"));
-  CR_TRY(build_geom(d->Lx, P->gx, "L_x"));
+  CR_TRY(build_geom(d->Ly, P->gy, "L_y", P->st));
+  CR_TRY(build_geom(d->Lx, P->gx, "L_x", P->st));
   const int64_t ny = P->ny, nx = P->nx, ni = P->ninj;
   std::vector<double> X((size_t)nx * ni), Y((size_t)ny * ni);
   std::vector<uint8_t> Om((size_t)ny * ni);
-  CR_HIP(hipMemcpy2D(X.data(), nx * sizeof(double), d->X, d->ldx * sizeof(double),
-                     nx * sizeof(double), ni, hipMemcpyDeviceToHost));
-  CR_HIP(hipMemcpy2D(Y.data(), ny * sizeof(double), d->Y, d->ldy * sizeof(double),
-                     ny * sizeof(double), ni, hipMemcpyDeviceToHost));
-  CR_HIP(hipMemcpy2D(Om.data(), ny, d->Omega, d->ldo, ny, ni, hipMemcpyDeviceToHost));
+  CR_HIP(hipStreamSynchronize(P->st));
+  CR_HIP(stage_to_host(X.data(), d->X, nx * sizeof(double), ni, d->ldx * sizeof(double), P->st));
+  CR_HIP(stage_to_host(Y.data(), d->Y, ny * sizeof(double), ni, d->ldy * sizeof(double), P->st));
+  CR_HIP(stage_to_host(Om.data(), d->Omega, ny, ni, d->ldo, P->st));
   for (double x : X)
     if (!std::isfinite(x)) {
       set_error("X has non-finite entries");
@@ -1403,14 +1402,14 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   CR_TRY(dev_alloc(P, &P->bits, (int64_t)nw * ny));
   CR_TRY(dev_alloc(P, &P->hptr, ni + 1));
   CR_TRY(dev_alloc(P, &P->hidx, std::max<int64_t>(P->nholes, 1)));
-  CR_HIP(hipMemcpy(P->X64, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice));
-  CR_HIP(hipMemcpy(P->X32, Xf.data(), sizeof(float) * Xf.size(), hipMemcpyHostToDevice));
-  CR_HIP(hipMemcpy(P->OY64, OY.data(), sizeof(double) * OY.size(), hipMemcpyHostToDevice));
-  CR_HIP(hipMemcpy(P->OY32, OYf.data(), sizeof(float) * OYf.size(), hipMemcpyHostToDevice));
-  CR_HIP(hipMemcpy(P->bits, bits.data(), sizeof(uint32_t) * bits.size(), hipMemcpyHostToDevice));
-  CR_HIP(hipMemcpy(P->hptr, hptr.data(), sizeof(int32_t) * hptr.size(), hipMemcpyHostToDevice));
+  CR_HIP(stage_to_device(P->X64, X.data(), sizeof(double) * X.size(), P->st));
+  CR_HIP(stage_to_device(P->X32, Xf.data(), sizeof(float) * Xf.size(), P->st));
+  CR_HIP(stage_to_device(P->OY64, OY.data(), sizeof(double) * OY.size(), P->st));
+  CR_HIP(stage_to_device(P->OY32, OYf.data(), sizeof(float) * OYf.size(), P->st));
+  CR_HIP(stage_to_device(P->bits, bits.data(), sizeof(uint32_t) * bits.size(), P->st));
+  CR_HIP(stage_to_device(P->hptr, hptr.data(), sizeof(int32_t) * hptr.size(), P->st));
   if (P->nholes)
-    CR_HIP(hipMemcpy(P->hidx, hidx.data(), sizeof(int32_t) * hidx.size(), hipMemcpyHostToDevice));
+    CR_HIP(stage_to_device(P->hidx, hidx.data(), sizeof(int32_t) * hidx.size(), P->st));
   CR_TRY(dev_alloc(P, &P->bar, BAR_WORDS));
   CR_HIP(hipMemset(P->bar, 0, BAR_WORDS * sizeof(unsigned)));
   if (const char* e = std::getenv("CONNREG_GRID_BARRIER"))
@@ -1948,7 +1947,7 @@ extern "C" cr_status cr_problem_set_box(cr_problem* P, int32_t which, const int3
   const int64_t n = geo.n;
   const int K = geo.K;
   std::vector<int32_t> nbr((size_t)K * n);
-  CR_HIP(hipMemcpy(nbr.data(), geo.nbr, sizeof(int32_t) * nbr.size(), hipMemcpyDeviceToHost));
+  CR_HIP(stage_to_host(nbr.data(), geo.nbr, sizeof(int32_t) * nbr.size(), 1, 0, P->st));
   const int d0 = dims[0], d1 = dims[1], d2 = dims[2];
   for (int64_t i = 0; i < n; ++i) {
     const int i0 = (int)(i % d0), i1 = (int)((i / d0) % d1), i2 = (int)(i / ((int64_t)d0 * d1));
@@ -1990,8 +1989,8 @@ extern "C" cr_status cr_problem_set_box(cr_problem* P, int32_t which, const int3
     }
     CR_TRY(dev_alloc(P, &bx.Q[a], (int64_t)m * m));
     CR_TRY(dev_alloc(P, &bx.mu[a], m));
-    CR_HIP(hipMemcpy(bx.Q[a], Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice));
-    CR_HIP(hipMemcpy(bx.mu[a], mu.data(), sizeof(double) * m, hipMemcpyHostToDevice));
+    CR_HIP(stage_to_device(bx.Q[a], Q.data(), sizeof(double) * Q.size(), P->st));
+    CR_HIP(stage_to_device(bx.mu[a], mu.data(), sizeof(double) * m, P->st));
   }
   (which == 0 ? P->boxy : P->boxx) = bx;
   if (which != 0) P->smw_xh_ready = false;

@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -28,6 +30,41 @@ void set_error(const std::string& msg);
     cr_status s_ = (call);           \
     if (s_ < 0) return s_;           \
   } while (0)
+
+// ---------------------------------------------------------------- set-up transfers
+// Host <-> device copies of set-up data (problem arrays, geometry tables,
+// spectral bases, network parameters) go through pinned staging memory, as
+// copies ordered on the handle's stream followed by a wait on that stream:
+// the pattern of every scalar read of the solvers.  Synchronous copies to or
+// from pageable memory came back with zeros in the copied arrays under a
+// kernel-tracing profiler, right after another handle was destroyed.
+// stage_to_host copies rows x width bytes, source rows spitch bytes apart
+// (0: contiguous), into dst packed
+inline hipError_t stage_to_host(void* dst, const void* src, size_t width, size_t rows,
+                                size_t spitch, hipStream_t st) {
+  if (width == 0 || rows == 0) return hipSuccess;
+  if (spitch == 0) spitch = width;
+  void* pin = nullptr;
+  hipError_t e = hipHostMalloc(&pin, width * rows);
+  if (e != hipSuccess) return e;
+  e = hipMemcpy2DAsync(pin, width, src, spitch, width, rows, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) std::memcpy(dst, pin, width * rows);
+  (void)hipHostFree(pin);
+  return e;
+}
+
+inline hipError_t stage_to_device(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  void* pin = nullptr;
+  hipError_t e = hipHostMalloc(&pin, bytes);
+  if (e != hipSuccess) return e;
+  std::memcpy(pin, src, bytes);
+  e = hipMemcpyAsync(dst, pin, bytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipHostFree(pin);
+  return e;
+}
 
 constexpr int WAVE = 64;
 constexpr int NT = 256;  // threads per workgroup for streaming kernels

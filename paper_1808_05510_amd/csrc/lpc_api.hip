@@ -110,8 +110,8 @@ extern "C" cr_status cr_pc_create(int32_t nx, int32_t ny, int32_t nz, int32_t ch
     k += co[l];
   }
   std::vector<float> z(3 * np, 0.f);
-  if (hipMemcpy(n.mem, h.data(), sizeof(float) * np, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(n.mem + np, z.data(), sizeof(float) * 3 * np, hipMemcpyHostToDevice) != hipSuccess) {
+  if (stage_to_device(n.mem, h.data(), sizeof(float) * np, pc->st) != hipSuccess ||
+      stage_to_device(n.mem + np, z.data(), sizeof(float) * 3 * np, pc->st) != hipSuccess) {
     (void)hipFree(n.mem);
     delete pc;
     set_error("upload of network parameters failed");
@@ -144,7 +144,7 @@ extern "C" cr_status cr_pc_get_params(cr_pc* pc, float* host_out) {
     return CR_EINVAL;
   }
   CR_HIP(hipStreamSynchronize(pc->st));
-  CR_HIP(hipMemcpy(host_out, pc->net.mem, sizeof(float) * pc->net.nparam, hipMemcpyDeviceToHost));
+  CR_HIP(stage_to_host(host_out, pc->net.mem, sizeof(float) * pc->net.nparam, 1, 0, pc->st));
   return CR_OK;
 }
 
@@ -154,9 +154,11 @@ extern "C" cr_status cr_pc_set_params(cr_pc* pc, const float* host_in) {
     return CR_EINVAL;
   }
   CR_HIP(hipStreamSynchronize(pc->st));
-  CR_HIP(hipMemcpy(pc->net.mem, host_in, sizeof(float) * pc->net.nparam, hipMemcpyHostToDevice));
+  CR_HIP(stage_to_device(pc->net.mem, host_in, sizeof(float) * pc->net.nparam, pc->st));
   pc->net.step = 0;
-  CR_HIP(hipMemset(pc->net.mem + pc->net.nparam, 0, sizeof(float) * 3 * pc->net.nparam));
+  CR_HIP(hipMemsetAsync(pc->net.mem + pc->net.nparam, 0, sizeof(float) * 3 * pc->net.nparam,
+                        pc->st));
+  CR_HIP(hipStreamSynchronize(pc->st));
   return CR_OK;
 }
 
@@ -184,7 +186,8 @@ extern "C" cr_status cr_pc_vjp(cr_pc* pc, const float* in, const float* dy, floa
   CR_HIP(hipMemcpyAsync(pc->acts.dy, dy, sizeof(float) * N, hipMemcpyDeviceToDevice, pc->st));
   CR_TRY(lpc_backward(pc->net, in, pc->acts, pc->st));
   CR_HIP(hipStreamSynchronize(pc->st));
-  CR_HIP(hipMemcpy(grad_host, pc->net.mem + np, sizeof(float) * np, hipMemcpyDeviceToHost));
-  CR_HIP(hipMemset(pc->net.mem + np, 0, sizeof(float) * np));
+  CR_HIP(stage_to_host(grad_host, pc->net.mem + np, sizeof(float) * np, 1, 0, pc->st));
+  CR_HIP(hipMemsetAsync(pc->net.mem + np, 0, sizeof(float) * np, pc->st));
+  CR_HIP(hipStreamSynchronize(pc->st));
   return CR_OK;
 }
