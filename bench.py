@@ -343,6 +343,12 @@ def main():
             e = lr[kind]
             log(f"[bench] {kind}: rank {e['rank']}, relres {e['relres']:.4e}, "
                 f"pcg iterations {e['pcg_iters']}")
+        log(f"[bench] pair collection {lr['collect_s']:.1f} s, training {lr['train_s']:.2f} s "
+            f"({lr['train_steps']} steps, {lr['pairs']} pairs, loss {lr['loss_first']:.3e} -> "
+            f"{lr['loss_last']:.3e})")
+        for kind, e in lr["inner_u_solves"].items():
+            log(f"[bench] inner u-solves {kind}: {e['mean_iters']:.1f} iterations, "
+                f"{e['mean_ms']:.2f} ms")
         return
     if a.batch_only:
         for pre in ("jacobi", "base"):

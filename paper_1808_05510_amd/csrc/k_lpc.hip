@@ -90,14 +90,26 @@ __global__ __launch_bounds__(NT) void k_conv_fwd(Dims d, int CI, int CO, const f
 // are independent and in flight together.  At 40^3 the one-output-set-per-thread form had one wave per SIMD
 // and paid each load's latency in turn; splitting the outputs over G-groups
 // multiplies the waves.
-template <int CI, int G>
+//
+// BWD: the data gradient din[c][v] = sum_{o,k} W[o][c][k] dout[o][v - off_k]
+// of a layer with nout = its input count, in the same form: off_{26-k} =
+// -off_k, so the staged weights are ws[g][o][k] = W[o][co0 + g][26 - k]
+// (flipped and transposed), CI is the layer's output count and no bias.
+template <int CI, int G, bool BWD>
 __global__ __launch_bounds__(NT) void k_conv_fwd_g(Dims d, const float* __restrict__ in,
                                                    const float* __restrict__ W,
                                                    const float* __restrict__ bias,
-                                                   float* __restrict__ out, int relu) {
+                                                   float* __restrict__ out, int relu, int nout) {
   __shared__ float ws[G * CI * 27];
   const int co0 = blockIdx.y * G;
-  for (int e = threadIdx.x; e < G * CI * 27; e += NT) ws[e] = W[co0 * CI * 27 + e];
+  for (int e = threadIdx.x; e < G * CI * 27; e += NT) {
+    if constexpr (BWD) {
+      const int g = e / (CI * 27), c = (e / 27) % CI, k = e % 27;
+      ws[e] = W[(c * nout + co0 + g) * 27 + 26 - k];
+    } else {
+      ws[e] = W[co0 * CI * 27 + e];
+    }
+  }
   __syncthreads();
   const int N = d.nx * d.ny * d.nz;
   const int v = blockIdx.x * NT + threadIdx.x;
@@ -108,7 +120,7 @@ __global__ __launch_bounds__(NT) void k_conv_fwd_g(Dims d, const float* __restri
   const int z = t / d.ny;
   float acc[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) acc[g] = bias[co0 + g];
+  for (int g = 0; g < G; ++g) acc[g] = BWD ? 0.f : bias[co0 + g];
   // one z-plane of taps (9 x CI loads) unrolled at a time: all taps at once
   // held 216 loads in flight and 454+ VGPRs (one wave per SIMD, spills at G 2)
 #pragma unroll 1
@@ -210,6 +222,80 @@ __global__ __launch_bounds__(NT) void k_conv_wgrad(Dims d, int CI, int CO,
   __syncthreads();
   for (int e = threadIdx.x; e < nw + CO; e += NT)
     partial[(int64_t)blockIdx.x * (nw + CO) + e] = acc[e];
+}
+
+// Register form of the weight gradient.  Grid (xb, 27): block (b, k) takes
+// tap k over the voxels v = b NT + t + j S (S = NT xb, j = 0, 1, ...); each
+// thread keeps the CO x CI products dout[co][v] in[ci][v + off_k] and the
+// CO bias terms of its voxels in registers, and the block sums them once at
+// the end (wave shuffles, then the waves through LDS) into
+// partial[b][(co CI + ci) 27 + k], the k = 0 blocks also into the bias slots
+// partial[b][CO CI 27 + co].  The generic kernel above reduced over the wave
+// for every product of every voxel.
+template <int CI, int CO>
+__global__ __launch_bounds__(NT) void k_conv_wgrad_t(Dims d, const float* __restrict__ in,
+                                                     const float* __restrict__ dout,
+                                                     float* __restrict__ partial) {
+  constexpr int NA = CO * CI + CO;
+  constexpr int NWV = NT / WAVE;
+  __shared__ float red[NWV][NA];
+  const int k = blockIdx.y;
+  const int N = d.nx * d.ny * d.nz;
+  const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+  const int off = dx + d.nx * (dy + d.ny * dz);
+  const int S = NT * gridDim.x;
+  // coordinates of the first voxel and of the stride S; the loop advances
+  // them digit by digit (x, y < their extents, so one carry each)
+  int v = blockIdx.x * NT + threadIdx.x;
+  int x = v % d.nx, t = v / d.nx;
+  int y = t % d.ny, z = t / d.ny;
+  const int sx = S % d.nx, st = S / d.nx;
+  const int sy = st % d.ny, sz = st / d.ny;
+  float acc[NA];
+#pragma unroll
+  for (int e = 0; e < NA; ++e) acc[e] = 0.f;
+  for (; v < N; v += S) {
+    const int xx = x + dx, yy = y + dy, zz = z + dz;
+    const bool inside =
+        xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz;
+    const int u = inside ? v + off : v;
+    const float f = inside ? 1.f : 0.f;
+    float a[CI], g[CO];
+#pragma unroll
+    for (int ci = 0; ci < CI; ++ci) a[ci] = f * in[ci * N + u];
+#pragma unroll
+    for (int co = 0; co < CO; ++co) g[co] = dout[co * N + v];
+#pragma unroll
+    for (int co = 0; co < CO; ++co) {
+#pragma unroll
+      for (int ci = 0; ci < CI; ++ci) acc[co * CI + ci] += g[co] * a[ci];
+      acc[CO * CI + co] += g[co];
+    }
+    x += sx;
+    const int cy = x >= d.nx;
+    x -= cy ? d.nx : 0;
+    y += sy + cy;
+    const int cz = y >= d.ny;
+    y -= cz ? d.ny : 0;
+    z += sz + cz;
+  }
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+#pragma unroll
+  for (int e = 0; e < NA; ++e) {
+    const float s = wsumf(acc[e]);
+    if (lane == 0) red[w][e] = s;
+  }
+  __syncthreads();
+  float* p = partial + (int64_t)blockIdx.x * (CO * CI * 27 + CO);
+  for (int e = threadIdx.x; e < NA; e += NT) {
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < NWV; ++i) s += red[i][e];
+    if (e < CO * CI)
+      p[e * 27 + k] = s;
+    else if (k == 0)
+      p[CO * CI * 27 + (e - CO * CI)] = s;
+  }
 }
 
 // gW[e] += sum_b partial[b][e]  (fixed order)
@@ -429,8 +515,9 @@ static void conv(const Dims& d, int CI, int CO, bool fine, const float* in, cons
   const int G = (fine && CO % 2 == 0) ? 2 : 1;
   const dim3 grid(nb(N), (unsigned)(CO / G));
 #define CV(CC, GG)                                                                          \
-  if (CI == CC && G == GG && N <= INT32_MAX) {                                              \
-    hipLaunchKernelGGL((k_conv_fwd_g<CC, GG>), grid, dim3(NT), 0, st, d, in, W, B, out, relu); \
+  if (CI == CC && G == GG && N * LPC_MAXC <= INT32_MAX) {                                \
+    hipLaunchKernelGGL((k_conv_fwd_g<CC, GG, false>), grid, dim3(NT), 0, st, d, in, W, B, out, \
+                       relu, CI);                                                             \
     return;                                                                                 \
   }
   CV(4, 1) CV(4, 2) CV(8, 1) CV(8, 2)
@@ -454,16 +541,55 @@ cr_status lpc_forward(const LpcNet& net, const float* in, LpcActs& a, hipStream_
   return CR_OK;
 }
 
+// voxels per thread of the register form of the weight gradient
+constexpr int WG_VPT = 8;
+
+// weight and bias gradients of one layer, accumulated into gW / gB: the
+// register form for the channel counts of the network at 4 and 8 channels,
+// else the generic kernel; partial needs nb(N) * (CO CI 27 + CO) floats
 static cr_status wgrad(const Dims& d, int CI, int CO, const float* in, const float* dout,
                        float* gW, float* gB, float* partial, hipStream_t st) {
   const int64_t N = (int64_t)d.nx * d.ny * d.nz;
-  const unsigned blocks = nb(N);
   const int m = CO * CI * 27 + CO;
-  hipLaunchKernelGGL(k_conv_wgrad, dim3(blocks), dim3(NT), 0, st, d, CI, CO, in, dout, partial);
+  unsigned blocks = nb(N);
+  bool done = false;
+  if (N * LPC_MAXC <= INT32_MAX) {
+    const unsigned xb = (unsigned)std::max<int64_t>(1, (N + NT * WG_VPT - 1) / (NT * WG_VPT));
+#define WG(A, B)                                                                          \
+  if (!done && CI == A && CO == B) {                                                       \
+    hipLaunchKernelGGL((k_conv_wgrad_t<A, B>), dim3(xb, 27), dim3(NT), 0, st, d, in, dout, \
+                       partial);                                                          \
+    blocks = xb;                                                                          \
+    done = true;                                                                          \
+  }
+    WG(4, 8) WG(8, 8) WG(8, 1) WG(4, 4) WG(4, 1)
+#undef WG
+  }
+  if (!done)
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(blocks), dim3(NT), 0, st, d, CI, CO, in, dout, partial);
   hipLaunchKernelGGL(k_sum_partials, dim3((m + NT - 1) / NT), dim3(NT), 0, st, (int)blocks, m,
                      partial, gW, gB, CO * CI * 27);
   CR_HIP(hipGetLastError());
   return CR_OK;
+}
+
+// data gradient din = conv^T(dout) of a layer with CI inputs and CO outputs:
+// the unrolled forward form with flipped, transposed weights when CO is 1, 4
+// or 8, else the generic kernel; din is overwritten
+static void dgrad(const Dims& d, int CI, int CO, bool fine, const float* dout, const float* W,
+                  float* din, hipStream_t st) {
+  const int64_t N = (int64_t)d.nx * d.ny * d.nz;
+  const int G = (fine && CI % 2 == 0) ? 2 : 1;
+  const dim3 grid(nb(N), (unsigned)(CI / G));
+#define DG(CC, GG)                                                                          \
+  if (CO == CC && G == GG && N * LPC_MAXC <= INT32_MAX) {                                \
+    hipLaunchKernelGGL((k_conv_fwd_g<CC, GG, true>), grid, dim3(NT), 0, st, d, dout, W,      \
+                       (const float*)nullptr, din, 0, CI);                                  \
+    return;                                                                                 \
+  }
+  DG(1, 1) DG(1, 2) DG(4, 1) DG(4, 2) DG(8, 1) DG(8, 2)
+#undef DG
+  hipLaunchKernelGGL(k_conv_dgrad, dim3(nb(N)), dim3(NT), 0, st, d, CI, CO, dout, W, din);
 }
 
 // backward from dy; gradients accumulated into net.gW / net.gB
@@ -475,23 +601,23 @@ cr_status lpc_backward(LpcNet& net, const float* in, LpcActs& a, hipStream_t st)
   float* P = a.partial;
   // L4: y = conv(s)
   CR_TRY(wgrad(d, C, 1, a.s, a.dy, net.gW[4], net.gB[4], P, st));
-  hipLaunchKernelGGL(k_conv_dgrad, dim3(nb(N)), dim3(NT), 0, st, d, C, 1, a.dy, net.W[4], a.ds);
+  dgrad(d, C, 1, true, a.dy, net.W[4], a.ds, st);
   // s = up(a3) + a1 : da1 = ds (skip), da3 = up^T ds
   hipLaunchKernelGGL(k_up_bwd, dim3(nb(Nc)), dim3(NT), 0, st, d, C, a.ds, a.da3);
   // L3
   hipLaunchKernelGGL(k_relu_bwd, dim3(nb(C * Nc)), dim3(NT), 0, st, (int64_t)C * Nc, a.a3, a.da3);
   CR_TRY(wgrad(c, C, C, a.a2, a.da3, net.gW[3], net.gB[3], P, st));
-  hipLaunchKernelGGL(k_conv_dgrad, dim3(nb(Nc)), dim3(NT), 0, st, c, C, C, a.da3, net.W[3], a.da2);
+  dgrad(c, C, C, false, a.da3, net.W[3], a.da2, st);
   // L2
   hipLaunchKernelGGL(k_relu_bwd, dim3(nb(C * Nc)), dim3(NT), 0, st, (int64_t)C * Nc, a.a2, a.da2);
   CR_TRY(wgrad(c, C, C, a.p, a.da2, net.gW[2], net.gB[2], P, st));
-  hipLaunchKernelGGL(k_conv_dgrad, dim3(nb(Nc)), dim3(NT), 0, st, c, C, C, a.da2, net.W[2], a.dp);
+  dgrad(c, C, C, false, a.da2, net.W[2], a.dp, st);
   // pool: da1 = ds + pool^T dp
   hipLaunchKernelGGL(k_pool_bwd, dim3(nb(N)), dim3(NT), 0, st, d, C, a.dp, a.ds);
   // L1 (a.ds now holds da1)
   hipLaunchKernelGGL(k_relu_bwd, dim3(nb(C * N)), dim3(NT), 0, st, (int64_t)C * N, a.a1, a.ds);
   CR_TRY(wgrad(d, C, C, a.a0, a.ds, net.gW[1], net.gB[1], P, st));
-  hipLaunchKernelGGL(k_conv_dgrad, dim3(nb(N)), dim3(NT), 0, st, d, C, C, a.ds, net.W[1], a.da0);
+  dgrad(d, C, C, true, a.ds, net.W[1], a.da0, st);
   // L0
   hipLaunchKernelGGL(k_relu_bwd, dim3(nb(C * N)), dim3(NT), 0, st, (int64_t)C * N, a.a0, a.da0);
   CR_TRY(wgrad(d, 4, C, in, a.da0, net.gW[0], net.gB[0], P, st));

@@ -27,7 +27,12 @@ def box(seed=0, by=(8, 6, 4), bx=(6, 4, 4), n_inj=5, lam=50.0):
                              hole_r=1.0, wt_rank=3, wt_w=(1.5, 3.0), lam=lam, seed=seed)
 
 
-@pytest.mark.parametrize("dims,C", [((8, 6, 4), 8), ((7, 5, 3), 4)])
+# 8 and 4 channels take the register weight-gradient and the flipped-weight
+# data-gradient kernels (several voxel blocks from 24x20x18 on, the training
+# grid at 40^3); 3 and 1 channels the generic kernels
+@pytest.mark.parametrize("dims,C", [((8, 6, 4), 8), ((7, 5, 3), 4), ((24, 20, 18), 8),
+                                    ((33, 17, 9), 4), ((40, 40, 40), 8), ((9, 7, 5), 3),
+                                    ((6, 5, 4), 1)])
 def test_pc_forward_and_vjp_match_reference(dims, C):
     pc = connreg.Pc(dims, channels=C, seed=3)
     w = pc.get_params().astype(np.float64)
