@@ -90,6 +90,36 @@ __device__ __forceinline__ void grid_barrier(const BarrierArg& b, cgrp::grid_gro
   __syncthreads();
 }
 
+// Wave sums of WAVE per-lane values at once, lane l receiving the sum over
+// the wave of value l: a butterfly that halves the values held at each step
+// (lanes with bit o set keep the upper half and send the lower), 63
+// exchanges per lane instead of 6 for each of the 64 values.  val(j) gives
+// this lane's value j.
+template <typename F>
+__device__ __forceinline__ double wave_transpose_sum(F val) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  double v[WAVE / 2];
+  {
+    const bool up = (lane & 32) != 0;
+#pragma unroll
+    for (int j = 0; j < WAVE / 2; ++j) {
+      const double lo = val(j), hi = val(j + WAVE / 2);
+      v[j] = (up ? hi : lo) + __shfl_xor(up ? lo : hi, 32, WAVE);
+    }
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) {
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int j = 0; j < o; ++j) {
+      const double send = up ? v[j] : v[j + o];
+      const double keep = up ? v[j + o] : v[j];
+      v[j] = keep + __shfl_xor(send, o, WAVE);
+    }
+  }
+  return v[0];
+}
+
 constexpr int PCG_MAX_VPT = 8;
 constexpr int PCG_MAX_NINJ = 1024;
 // Partial-sum slots.  Every slot has one writer phase per use and is never
@@ -169,11 +199,19 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   // per-workgroup partials of X^T z into lrpart (z of this thread's voxels)
   auto lr_part = [&](const double* zv) {
     if (NXR > 0) {
+      static_assert(NXR == 0 || NXR == WAVE, "the transposed wave sum covers WAVE injections");
       const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      const double zv0 = zv[0];
+      if constexpr (BS == NT) {
+        // one butterfly for all injections (278 registers at 256 threads)
+        lred[wv][lane] = wave_transpose_sum([&](int al) { return xr[al] * zv0; });
+      } else {
+        // 512-thread groups have 256 registers: a wave sum per injection
 #pragma unroll
-      for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) {
-        const double v = wsum(xr[al] * zv[0]);
-        if (lane == 0) lred[wv][al] = v;
+        for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) {
+          const double v = wsum(xr[al] * zv0);
+          if (lane == 0) lred[wv][al] = v;
+        }
       }
       __syncthreads();
       for (int al = threadIdx.x; al < ninj; al += BS) {
