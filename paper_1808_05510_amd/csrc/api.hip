@@ -77,7 +77,7 @@ struct cr_problem {
   // faster mixed solves on the 40^3 / 30^3 problem than 256); CONNREG_PCG_BS=256
   // restores 256.  Batched solves use 256 (their CU shares are sized for it).
   int pcg_bs = 1024;
-  int pcg_xbs = 0;           // v-system group size with register-resident X (0: by precision;
+  int pcg_xbs = 0;           // v-system group size with register-resident X (0: 256;
                              // CONNREG_PCG_XBS=256 or 512)
   bool no_xreg = false;     // CONNREG_PCG_XREG=0: v-system PCG streams X (no register-resident rows)
   int bar_mode = 1;
@@ -457,11 +457,11 @@ struct Ctx {
       const int tuned = P->tuned_vpt_v;
       const int want = vpt_opt > 0 ? vpt_opt : tuned;
       if (ninj <= PCG_NXR && want <= 1 && !P->no_xreg) {
-        // FP32 data: 512-thread groups first (half the grid barrier's
-        // arrivals; mixed 40^3/30^3 solve 4.17 s against 4.34 s); FP64 data
-        // keeps 256 (3.80 s against 3.90 s: its halo traffic gains from the
-        // voxels spread over twice the CUs)
-        const int xbs = P->pcg_xbs > 0 ? P->pcg_xbs : (std::is_same<T, float>::value ? 512 : NT);
+        // 256-thread groups, whose kernel sums the X^T z partials with one
+        // butterfly per wave (512-thread groups have no registers for it and
+        // take a wave sum per injection: mixed 40^3/30^3 solve 2.22 s against
+        // 1.61 s at 256; CONNREG_PCG_XBS=512 selects them)
+        const int xbs = P->pcg_xbs > 0 ? P->pcg_xbs : NT;
         for (int bs : {xbs, NT}) {
           PcgArgs<T> probe{};
           probe.g = P->gx;

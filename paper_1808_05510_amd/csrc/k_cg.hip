@@ -36,6 +36,43 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Two workgroup sums in one pass (the wave sums interleave, one LDS round);
+// red holds 2 BS / WAVE doubles.
+template <int BS = NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+  a = wsum(a);
+  b = wsum(b);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[wv] = a;
+    red[BS / WAVE + wv] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int k = 0; k < BS / WAVE; ++k) {
+    sa += red[k];
+    sb += red[BS / WAVE + k];
+  }
+  a = sa;
+  b = sb;
+}
+
+// Grid totals of slots sa and sb, both loads issued before the reduction.
+template <int BS = NT>
+__device__ __forceinline__ void grid_total2(const double* part, int sa, int sb, int nwg,
+                                            double* red, double& ta, double& tb) {
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nwg; k += BS) {
+    a += part[(int64_t)sa * nwg + k];
+    b += part[(int64_t)sb * nwg + k];
+  }
+  block_sum2<BS>(a, b, red);
+  ta = a;
+  tb = b;
+}
+
 // Grid total of slot `slot` of the partial array (part[slot*nwg + b]),
 // summed in the same order by every workgroup.
 template <int BS = NT>
@@ -171,7 +208,7 @@ template <typename T, int K, bool LR, int VPT, int BS, int NXR>
 __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   static_assert(NXR == 0 || (LR && VPT == 1), "register-resident X needs LR and VPT 1");
   cgrp::grid_group grid = cgrp::this_grid();
-  __shared__ double red[BS / WAVE];
+  __shared__ double red[2 * BS / WAVE];
   __shared__ double zs[BS * VPT];
   __shared__ double slr[LR ? PCG_MAX_NINJ : 1];
   __shared__ double lred[NXR > 0 ? BS / WAVE : 1][NXR > 0 ? NXR : 1];
@@ -257,15 +294,14 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   }
   __syncthreads();
   if (LR) lr_part(z);
-  rz = block_sum<BS>(rz, red);
-  bb = block_sum<BS>(bb, red);
+  block_sum2<BS>(rz, bb, red);
   if (threadIdx.x == 0) {
     part[1 * nwg + blockIdx.x] = rz;
     part[3 * nwg + blockIdx.x] = bb;
   }
   grid_barrier(a.bar, grid);
-  double rz_cur = grid_total<BS>(part, 1, nwg, red);
-  const double bnorm2 = grid_total<BS>(part, 3, nwg, red);
+  double rz_cur, bnorm2;
+  grid_total2<BS>(part, 1, 3, nwg, red, rz_cur, bnorm2);
   int status = 0, it = 0;
   double rr = bnorm2;
   const double tol2 = a.rtol * a.rtol * bnorm2;
@@ -351,8 +387,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       }
       __syncthreads();
       if (LR) lr_part(z);
-      rzn = block_sum<BS>(rzn, red);
-      rrn = block_sum<BS>(rrn, red);
+      block_sum2<BS>(rzn, rrn, red);
       if (threadIdx.x == 0) {
         part[1 * nwg + blockIdx.x] = rzn;
         part[2 * nwg + blockIdx.x] = rrn;
@@ -360,8 +395,8 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       grid_barrier(a.bar, grid);
 
       // ---- phase D: beta, convergence, p = z + beta p, t = L z + beta t
-      const double rz_new = grid_total<BS>(part, 1, nwg, red);
-      rr = grid_total<BS>(part, 2, nwg, red);
+      double rz_new;
+      grid_total2<BS>(part, 1, 2, nwg, red, rz_new, rr);
       if (rr <= tol2) {
         ++it;
         break;
