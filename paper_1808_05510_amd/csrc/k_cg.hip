@@ -332,6 +332,16 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
 
     for (it = 0; it < a.maxit; ++it) {
       // ---- phase B: q = A p, partial p.q
+      // (the neighbour t values are loaded before the low-rank set-up's
+      // workgroup barrier, so the two latencies overlap)
+      constexpr int KP = VPT <= 2 ? K : 1;
+      double tn[VPT <= 2 ? VPT : 1][KP];
+      if constexpr (VPT <= 2) {
+#pragma unroll
+        for (int m = 0; m < VPT; ++m)
+#pragma unroll
+          for (int k = 0; k < K; ++k) tn[m][k] = ok[m] ? (double)tg[nb[m][k]] : 0.0;
+      }
       if (LR) {
         for (int al = threadIdx.x; al < ninj; al += BS) slr[al] = a.gw[al] * a.sbuf[al];
         __syncthreads();
@@ -344,8 +354,13 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         if (ok[m]) {
           const int64_t i = lo + threadIdx.x + BS * m;
           double lt = (double)K * t[m];
+          if constexpr (VPT <= 2) {
 #pragma unroll
-          for (int k = 0; k < K; ++k) lt -= (double)tg[nb[m][k]];
+            for (int k = 0; k < K; ++k) lt -= tn[m][k];
+          } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) lt -= (double)tg[nb[m][k]];
+          }
           double qi = lam * (lt + c1 * t[m] + c0 * p[m]) + dd[m] * p[m];
           if (LR) {
             double s = 0.0;
@@ -395,6 +410,18 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       grid_barrier(a.bar, grid);
 
       // ---- phase D: beta, convergence, p = z + beta p, t = L z + beta t
+      // (the neighbour z values and this workgroup's first low-rank partial
+      // sum are loaded before the reduction, so their latency overlaps it)
+      double zn[VPT <= 2 ? VPT : 1][KP];
+      if constexpr (VPT <= 2) {
+#pragma unroll
+        for (int m = 0; m < VPT; ++m)
+#pragma unroll
+          for (int k = 0; k < K; ++k) zn[m][k] = ok[m] ? (double)zg[nb[m][k]] : 0.0;
+      }
+      double ls0 = 0.0;
+      if (LR && (int)blockIdx.x < ninj)
+        for (int b = threadIdx.x; b < nwg; b += BS) ls0 += lrpart[(int64_t)blockIdx.x * nwg + b];
       double rz_new;
       grid_total2<BS>(part, 1, 2, nwg, red, rz_new, rr);
       if (rr <= tol2) {
@@ -407,8 +434,13 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       for (int m = 0; m < VPT; ++m) {
         if (ok[m]) {
           double lz = (double)K * z[m];
+          if constexpr (VPT <= 2) {
 #pragma unroll
-          for (int k = 0; k < K; ++k) lz -= (double)zg[nb[m][k]];
+            for (int k = 0; k < K; ++k) lz -= zn[m][k];
+          } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) lz -= (double)zg[nb[m][k]];
+          }
           p[m] = (double)(T)(z[m] + beta * p[m]);
           t[m] = (double)(T)(lz + beta * t[m]);
           tg[lo + threadIdx.x + BS * m] = (T)t[m];
@@ -417,7 +449,11 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       if (LR) {
         for (int al = blockIdx.x; al < ninj; al += nwg) {
           double s = 0.0;
-          for (int b = threadIdx.x; b < nwg; b += BS) s += lrpart[(int64_t)al * nwg + b];
+          if (al == (int)blockIdx.x) {
+            s = ls0;
+          } else {
+            for (int b = threadIdx.x; b < nwg; b += BS) s += lrpart[(int64_t)al * nwg + b];
+          }
           s = block_sum<BS>(s, red);
           if (threadIdx.x == 0) a.sbuf[al] = s + beta * a.sbuf[al];
         }
