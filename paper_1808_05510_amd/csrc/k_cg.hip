@@ -209,6 +209,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   static_assert(NXR == 0 || (LR && VPT == 1), "register-resident X needs LR and VPT 1");
   cgrp::grid_group grid = cgrp::this_grid();
   __shared__ double red[2 * BS / WAVE];
+  __shared__ double redc[2 * BS / WAVE];  // phase C's own reduction slots (no leading barrier)
   __shared__ double zs[BS * VPT];
   __shared__ double slr[LR ? PCG_MAX_NINJ : 1];
   __shared__ double lred[NXR > 0 ? BS / WAVE : 1][NXR > 0 ? NXR : 1];
@@ -398,11 +399,50 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
           rzn += r[m] * z[m];
           rrn += r[m] * r[m];
         }
-        zs[threadIdx.x + BS * m] = z[m];
+        if (LR && NXR == 0) zs[threadIdx.x + BS * m] = z[m];
       }
-      __syncthreads();
-      if (LR) lr_part(z);
-      block_sum2<BS>(rzn, rrn, red);
+      if constexpr (LR && NXR == 0) {
+        __syncthreads();
+        lr_part(z);
+        block_sum2<BS>(rzn, rrn, red);
+      } else {
+        // the wave sums of r.z, r.r (and the X^T z partials) meet at one
+        // workgroup barrier; redc and lred are written in this phase only
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const double wa = wsum(rzn), wb = wsum(rrn);
+        if constexpr (LR) {
+          const double zv0 = z[0];
+          if constexpr (BS == NT) {
+            lred[wv][lane] = wave_transpose_sum([&](int al) { return xr[al] * zv0; });
+          } else {
+#pragma unroll
+            for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) {
+              const double v = wsum(xr[al] * zv0);
+              if (lane == 0) lred[wv][al] = v;
+            }
+          }
+        }
+        if (lane == 0) {
+          redc[wv] = wa;
+          redc[BS / WAVE + wv] = wb;
+        }
+        __syncthreads();
+        rzn = 0.0;
+        rrn = 0.0;
+#pragma unroll
+        for (int k = 0; k < BS / WAVE; ++k) {
+          rzn += redc[k];
+          rrn += redc[BS / WAVE + k];
+        }
+        if constexpr (LR) {
+          for (int al = threadIdx.x; al < ninj; al += BS) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < BS / WAVE; ++w) t += lred[w][al];
+            lrpart[(int64_t)al * nwg + blockIdx.x] = t;
+          }
+        }
+      }
       if (threadIdx.x == 0) {
         part[1 * nwg + blockIdx.x] = rzn;
         part[2 * nwg + blockIdx.x] = rrn;
