@@ -23,11 +23,14 @@ __device__ __forceinline__ double wsum(double v) {
 }
 
 // Sum of v over a workgroup of BS threads; result returned to every thread.
-template <int BS = NT>
+// LEAD: the leading workgroup barrier, which keeps red from being rewritten
+// while a slower wave still reads a previous sum; a sum that is the first use
+// of red after a grid barrier (which starts and ends with one) drops it.
+template <int BS = NT, bool LEAD = true>
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wsum(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
+  if (LEAD) __syncthreads();
   if (lane == 0) red[wv] = v;
   __syncthreads();
   double s = 0.0;
@@ -38,12 +41,12 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // Two workgroup sums in one pass (the wave sums interleave, one LDS round);
 // red holds 2 BS / WAVE doubles.
-template <int BS = NT>
+template <int BS = NT, bool LEAD = true>
 __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
   a = wsum(a);
   b = wsum(b);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
+  if (LEAD) __syncthreads();
   if (lane == 0) {
     red[wv] = a;
     red[BS / WAVE + wv] = b;
@@ -60,7 +63,7 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
 }
 
 // Grid totals of slots sa and sb, both loads issued before the reduction.
-template <int BS = NT>
+template <int BS = NT, bool LEAD = true>
 __device__ __forceinline__ void grid_total2(const double* part, int sa, int sb, int nwg,
                                             double* red, double& ta, double& tb) {
   double a = 0.0, b = 0.0;
@@ -68,18 +71,18 @@ __device__ __forceinline__ void grid_total2(const double* part, int sa, int sb, 
     a += part[(int64_t)sa * nwg + k];
     b += part[(int64_t)sb * nwg + k];
   }
-  block_sum2<BS>(a, b, red);
+  block_sum2<BS, LEAD>(a, b, red);
   ta = a;
   tb = b;
 }
 
 // Grid total of slot `slot` of the partial array (part[slot*nwg + b]),
 // summed in the same order by every workgroup.
-template <int BS = NT>
+template <int BS = NT, bool LEAD = true>
 __device__ __forceinline__ double grid_total(const double* part, int slot, int nwg, double* red) {
   double s = 0.0;
   for (int b = threadIdx.x; b < nwg; b += BS) s += part[(int64_t)slot * nwg + b];
-  return block_sum<BS>(s, red);
+  return block_sum<BS, LEAD>(s, red);
 }
 
 // ------------------------------------------------------------ grid barrier
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   }
   grid_barrier(a.bar, grid);
   double rz_cur, bnorm2;
-  grid_total2<BS>(part, 1, 3, nwg, red, rz_cur, bnorm2);
+  grid_total2<BS, false>(part, 1, 3, nwg, red, rz_cur, bnorm2);
   int status = 0, it = 0;
   double rr = bnorm2;
   const double tol2 = a.rtol * a.rtol * bnorm2;
@@ -377,12 +380,12 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
           pq += p[m] * q[m];
         }
       }
-      pq = block_sum<BS>(pq, red);
+      pq = block_sum<BS, false>(pq, red);
       if (threadIdx.x == 0) part[0 * nwg + blockIdx.x] = pq;
       grid_barrier(a.bar, grid);
 
       // ---- phase C: x += alpha p, r -= alpha q, z = M^-1 r
-      const double pq_tot = grid_total<BS>(part, 0, nwg, red);
+      const double pq_tot = grid_total<BS, false>(part, 0, nwg, red);
       if (!(pq_tot > 0.0)) {
         status = 2;
         break;
@@ -463,7 +466,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       if (LR && (int)blockIdx.x < ninj)
         for (int b = threadIdx.x; b < nwg; b += BS) ls0 += lrpart[(int64_t)blockIdx.x * nwg + b];
       double rz_new;
-      grid_total2<BS>(part, 1, 2, nwg, red, rz_new, rr);
+      grid_total2<BS, false>(part, 1, 2, nwg, red, rz_new, rr);
       if (rr <= tol2) {
         ++it;
         break;
@@ -510,7 +513,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   xx = block_sum<BS>(xx, red);
   if (threadIdx.x == 0) part[4 * nwg + blockIdx.x] = xx;
   grid_barrier(a.bar, grid);
-  const double xnorm2 = grid_total<BS>(part, 4, nwg, red);
+  const double xnorm2 = grid_total<BS, false>(part, 4, nwg, red);
   const double xn = sqrt(xnorm2);
   const double inv = xn > 0.0 ? 1.0 / xn : 0.0;
 #pragma unroll
