@@ -80,6 +80,7 @@ struct cr_problem {
   int pcg_xbs = 0;           // v-system group size with register-resident X (0: 256;
                              // CONNREG_PCG_XBS=256 or 512)
   bool no_xreg = false;     // CONNREG_PCG_XREG=0: v-system PCG streams X (no register-resident rows)
+  bool pcg_warm = true;     // FP64 ALS half-steps warm-started (CONNREG_PCG_WARM=0: from zero)
   int bar_mode = 1;
   std::map<std::string, DevBuf> ws;
   std::vector<void*> owned;
@@ -606,7 +607,10 @@ struct Ctx {
   }
 
   // ------------------------------------------------------------ ALS
-  cr_status pcg(bool usys, const T* b, T* xout, double rtol, int maxit, double* scal) {
+  // x0 / xbuf / bref: warm start (xbuf receives the unnormalised solution,
+  // default the work vector), see pcg_warm
+  cr_status pcg(bool usys, const T* b, T* xout, double rtol, int maxit, double* scal,
+                const T* x0 = nullptr, T* xbuf = nullptr, const double* bref = nullptr) {
     PcgArgs<T> a{};
     a.g = usys ? P->gy : P->gx;
     a.lam = lam;
@@ -626,6 +630,9 @@ struct Ctx {
     a.t = w[4];
     a.q = w[5];
     a.xout = xout;
+    a.x0 = x0;
+    a.bref = bref;
+    if (xbuf) a.x = xbuf;
     a.part = pcgpart;
     a.sbuf = sbuf;
     a.scal = scal;
@@ -638,6 +645,37 @@ struct Ctx {
     a.bar.mode = P->bar_mode;
     a.bar.coop = P->coop;
     return pcg_solve<T>(a, usys ? pcg_nwg_u : pcg_nwg_v, st);
+  }
+
+  // FP64 Jacobi-PCG of an ALS half-step, warm-started from the previous
+  // sweep's unnormalised solution of the same system (the system changes
+  // with the other factor, its solution little once the sweeps settle): the
+  // kernel solves A e = b - A x0 from x0, to ||b - A x|| <= rtol ||b||.  The
+  // first solve of each system in an ALS starts from zero.
+  bool warm_u_ok = false, warm_v_ok = false;
+  cr_status pcg_warm(bool usys, const T* b, T* xout, double rtol, int maxit, double* scal) {
+    const int64_t n = usys ? ny : nx;
+    T* xw = WS(T, usys ? "warm_u" : "warm_v", n);
+    bool& valid = usys ? warm_u_ok : warm_v_ok;
+    if constexpr (std::is_same<T, double>::value) {
+      if (valid && P->pcg_warm) {
+        double* r0 = WS(double, "warm_r", n);
+        double* t0 = WS(double, "warm_t", n);
+        double* bref = tmp + 12;
+        CR_TRY(dot(n, b, b, bref));
+        if (!usys) {
+          Blocks<T> A;
+          A.clear();
+          A.add(X(), nx, ninj);
+          CR_TRY((gemv_tx<T, double>(nx, A, xw, y0, part, st)));
+        }
+        CR_TRY(als_residual<T>(usys ? P->gy : P->gx, lam, usys ? cu : cv, usys ? dvec : nullptr,
+                               usys ? nullptr : X(), nx, ninj, gw, y0, b, xw, t0, r0, st));
+        return pcg(usys, r0, xout, rtol, maxit, scal, xw, xw, bref);
+      }
+    }
+    valid = true;
+    return pcg(usys, b, xout, rtol, maxit, scal, nullptr, xw, nullptr);
   }
 
   struct SolveOut {
@@ -776,7 +814,7 @@ struct Ctx {
     }
     if (std::is_same<T, double>::value) {
       deferred = true;
-      return pcg(usys, b, xout, rtol, maxit, dsc);
+      return pcg_warm(usys, b, xout, rtol, maxit, dsc);
     }
     deferred = false;
     const int64_t n = usys ? ny : nx;
@@ -975,6 +1013,7 @@ struct Ctx {
 
   cr_status als(int r, T* v, T* u, const cr_solve_opts& o, cr_als_stats* stats, bool& zero_rhs) {
     zero_rhs = false;
+    warm_u_ok = warm_v_ok = false;
     int sweeps = 0;
     double delta = 0.0;
     SolveOut su, sv;
@@ -1339,6 +1378,7 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   if (const char* e = std::getenv("CONNREG_PCG_BS")) P->pcg_bs = std::atoi(e) == NT ? NT : 1024;
   if (const char* e = std::getenv("CONNREG_PCG_XREG")) P->no_xreg = std::atoi(e) == 0;
   if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
+  if (const char* e = std::getenv("CONNREG_PCG_WARM")) P->pcg_warm = std::atoi(e) != 0;
   P->ny = d->Ly.n;
   P->nx = d->Lx.n;
   P->ninj = (int)d->n_inj;

@@ -211,6 +211,8 @@ struct PcgArgs {
   const T* b;
   T* x; T* r; T* z; T* p; T* t; T* q;
   T* xout;
+  const T* x0 = nullptr;        // initial iterate (null: zero); b is then b - A x0
+  const double* bref = nullptr;  // device ||b||^2 of the original system (null: ||b||^2 of b)
   double* part;         // >= nwg*5 + ninj*nwg
   double* sbuf;         // >= ninj
   double* scal;         // >= 4

@@ -286,7 +286,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       mi[m] = (double)a.minv[i];
       if (a.dvec) dd[m] = (double)a.dvec[i];
     }
-    x[m] = 0.0;
+    x[m] = (a.x0 && ok[m]) ? (double)a.x0[i] : 0.0;
     r[m] = (double)(T)bi;
     z[m] = (double)(T)(mi[m] * r[m]);
     p[m] = 0.0;
@@ -304,14 +304,16 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
     part[3 * nwg + blockIdx.x] = bb;
   }
   grid_barrier(a.bar, grid);
-  double rz_cur, bnorm2;
-  grid_total2<BS, false>(part, 1, 3, nwg, red, rz_cur, bnorm2);
+  double rz_cur, rr;
+  grid_total2<BS, false>(part, 1, 3, nwg, red, rz_cur, rr);
   int status = 0, it = 0;
-  double rr = bnorm2;
+  // from a warm start x0 the kernel's b is the residual b - A x0: the
+  // tolerance stays relative to the original right-hand side
+  const double bnorm2 = a.bref ? *a.bref : rr;
   const double tol2 = a.rtol * a.rtol * bnorm2;
   if (!(bnorm2 > 0.0)) status = 2;  // zero or non-finite right-hand side
 
-  if (status == 0) {
+  if (status == 0 && !(rr <= tol2)) {
     // ---- p = z, t = L z, s = X^T z
 #pragma unroll
     for (int m = 0; m < VPT; ++m) {
