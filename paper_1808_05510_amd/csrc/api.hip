@@ -828,14 +828,23 @@ struct Ctx {
     *out = SolveOut{};
     double h[4], q[2];
     CR_TRY(dot(n, b, b, tmp + 9));
-    CR_TRY(pcg(usys, b, xout, in_rtol, maxit, dsc));
-    CR_TRY(read_scalars(dsc, 4, h));
-    out->iters += (int)h[2];
-    if (h[3] == 2.0) {
-      out->status = 2;
-      return CR_OK;
+    // warm start: from the second sweep of an ALS on, the FP64 iterate starts
+    // at the previous sweep's solution of this system and the loop below
+    // begins with its residual; else a first FP32 solve from zero
+    double* xw64 = WS(double, usys ? "mwarm_u" : "mwarm_v", n);
+    bool& warm = usys ? warm_u_ok : warm_v_ok;
+    if (warm && P->pcg_warm) {
+      CR_HIP(hipMemcpyAsync(x64, xw64, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    } else {
+      CR_TRY(pcg(usys, b, xout, in_rtol, maxit, dsc));
+      CR_TRY(read_scalars(dsc, 4, h));
+      out->iters += (int)h[2];
+      if (h[3] == 2.0) {
+        out->status = 2;
+        return CR_OK;
+      }
+      CR_TRY(accumulate<T>(n, w[0], x64, true, st));
     }
-    CR_TRY(accumulate<T>(n, w[0], x64, true, st));
     double rr = 0.0, bb = 0.0, rr_prev = -1.0;
     for (int k = 0; k < 12; ++k) {
       if (!usys) {
@@ -866,6 +875,8 @@ struct Ctx {
     }
     out->relres = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     out->status = (rr <= rtol * rtol * bb) ? 0 : 1;
+    CR_HIP(hipMemcpyAsync(xw64, x64, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    warm = true;
     CR_TRY(dot64(n, x64, x64, tmp + 11));
     CR_TRY(normalize_out<T>(n, x64, tmp + 11, xout, st));
     CR_TRY(read_scalars(tmp + 11, 1, h));
