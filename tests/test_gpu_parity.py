@@ -279,3 +279,24 @@ def test_masked_gram_fp64_and_bf16(case, r):
     Gbf = np_(g.masked_gram(U, "bf16"))
     # entry bound: 2^-8 ||U_a|| ||U_b|| (orthonormal columns: 2^-8) + FP32 accumulation
     assert np.abs(Gbf - ref).max() <= 2.0 ** -8 + 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-7), ("mixed", 1e-4)])
+def test_warm_started_sweeps_match_cold_starts(monkeypatch, prec, tol):
+    """ALS sweeps after the first start each PCG from the previous sweep's
+    solution; the tolerance stays relative to the original right-hand side, so
+    the factors agree with cold starts to the inner tolerance, in fewer
+    iterations."""
+    d = mid_box()
+    out = {}
+    for warm in ("0", "1"):
+        monkeypatch.setenv("CONNREG_PCG_WARM", warm)
+        g = connreg.Problem(d, prec, DEV)
+        out[warm] = g.greedy_solve(max_rank=6, als_fixed_sweeps=3, pcg_rtol=1e-10,
+                                   pcg_maxit=20000, galerkin_rtol=1e-13, seed=3)
+        g.close()
+    c, w = out["0"], out["1"]
+    assert c["rank"] == w["rank"] == 6
+    err = _wdiff(np_(w["U"]), np_(w["Z"]), np_(w["V"]), np_(c["U"]), np_(c["Z"]), np_(c["V"]))
+    assert err <= tol, err
+    assert w["stats"]["pcg_iters"] < c["stats"]["pcg_iters"]
