@@ -457,19 +457,25 @@ struct Ctx {
     {
       const int tuned = P->tuned_vpt_v;
       const int want = vpt_opt > 0 ? vpt_opt : tuned;
-      if (ninj <= PCG_NXR && want <= 1 && !P->no_xreg) {
+      // rows of X in registers: 64 for either type, 128 for FP32 data
+      const int nxr_sel = ninj <= PCG_NXR ? PCG_NXR
+                          : (std::is_same<T, float>::value && ninj <= PCG_NXR2) ? PCG_NXR2 : 0;
+      if (nxr_sel > 0 && want <= 1 && !P->no_xreg) {
         // 256-thread groups, whose kernel sums the X^T z partials with one
         // butterfly per wave (512-thread groups have no registers for it and
         // take a wave sum per injection: mixed 40^3/30^3 solve 2.22 s against
         // 1.61 s at 256; CONNREG_PCG_XBS=512 selects them)
+        // (128 FP32 rows need 288 registers at 256 threads, one wave per SIMD;
+        // at 512 threads they fit in 255, two waves per SIMD, with a wave sum
+        // per injection, so a grid that does not fit at 256 tries 512)
         const int xbs = P->pcg_xbs > 0 ? P->pcg_xbs : NT;
-        for (int bs : {xbs, NT}) {
+        for (int bs : {xbs, NT, 512}) {
           PcgArgs<T> probe{};
           probe.g = P->gx;
           probe.Xm = X();
           probe.vpt = 1;
           probe.bs = bs;
-          probe.nxr = PCG_NXR;
+          probe.nxr = nxr_sel;
           int maxwg = pcg_max_wg<T>(probe);
           if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
           const int64_t w = std::max<int64_t>(1, (nx + bs - 1) / bs);
@@ -477,7 +483,7 @@ struct Ctx {
             pcg_vpt_v = 1;
             pcg_nwg_v = (int)w;
             pcg_bs_v = bs;
-            pcg_nxr_v = PCG_NXR;
+            pcg_nxr_v = nxr_sel;
             break;
           }
         }

@@ -220,10 +220,11 @@ struct PcgArgs {
   int maxit;
   int vpt;              // voxels per thread
   int bs = NT;          // threads per workgroup (NT or 1024)
-  int nxr = 0;          // PCG_NXR: X rows in registers (low-rank term, vpt 1, bs NT)
+  int nxr = 0;          // PCG_NXR or PCG_NXR2: X rows in registers (low-rank term, vpt 1)
   BarrierArg bar;
 };
 constexpr int PCG_NXR = 64;  // injections held in registers by the X-resident PCG
+constexpr int PCG_NXR2 = 128;  // the same for FP32 data up to 128 injections
 template <typename T>
 cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st);
 template <typename T>

@@ -10,6 +10,8 @@
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cr_internal.hpp"
 
 namespace cgrp = cooperative_groups;
@@ -205,8 +207,9 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // updates), phase D (p = z + beta p, t = L z + beta t, needs z at
 // neighbours), each ended by a grid barrier.
 // NXR > 0 (low-rank term, one voxel per thread, n_inj <= NXR): each thread
-// keeps its voxel's row of X in registers, so the X^T z partials and the
-// X (g o s) products read no memory.
+// keeps its voxel's row of X in registers (in the data type T), so the X^T z
+// partials and the X (g o s) products read no memory.  NXR is 64, or 128 for
+// FP32 data (128 registers of X).
 template <typename T, int K, bool LR, int VPT, int BS, int NXR>
 __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   static_assert(NXR == 0 || (LR && VPT == 1), "register-resident X needs LR and VPT 1");
@@ -229,28 +232,40 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   const int64_t ldx = a.ldx;
   const int ninj = a.ninj;
 
-  double xr[NXR > 0 ? NXR : 1];
+  // 64 rows are held in FP64; 128 rows (FP32 data) stay FP32 and their
+  // products are formed in FP32, so the compiler cannot hoist 128 converted
+  // values into registers
+  using XR = typename std::conditional<(NXR > PCG_NXR), T, double>::type;
+  XR xr[NXR > 0 ? NXR : 1];
+  auto xz = [&](int al, double zv) -> double {
+    if constexpr (std::is_same<XR, double>::value)
+      return xr[al] * zv;
+    else
+      return (double)(xr[al] * (XR)zv);
+  };
   if (NXR > 0) {
     const int64_t i0 = lo + threadIdx.x;
 #pragma unroll
     for (int al = 0; al < NXR; ++al)
-      xr[al] = (i0 < n && al < ninj) ? (double)Xm[(int64_t)al * ldx + i0] : 0.0;
+      xr[al] = (i0 < n && al < ninj) ? (XR)Xm[(int64_t)al * ldx + i0] : (XR)0;
     for (int al = threadIdx.x; al < NXR; al += BS) slr[al] = 0.0;
   }
   // per-workgroup partials of X^T z into lrpart (z of this thread's voxels)
   auto lr_part = [&](const double* zv) {
     if (NXR > 0) {
-      static_assert(NXR == 0 || NXR == WAVE, "the transposed wave sum covers WAVE injections");
+      static_assert(NXR % WAVE == 0, "the transposed wave sums cover WAVE injections each");
       const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
       const double zv0 = zv[0];
       if constexpr (BS == NT) {
-        // one butterfly for all injections (278 registers at 256 threads)
-        lred[wv][lane] = wave_transpose_sum([&](int al) { return xr[al] * zv0; });
+        // one butterfly per 64 injections (256-thread groups)
+        lred[wv][lane] = wave_transpose_sum([&](int al) { return xz(al, zv0); });
+        if constexpr (NXR > WAVE)
+          lred[wv][WAVE + lane] = wave_transpose_sum([&](int al) { return xz(WAVE + al, zv0); });
       } else {
         // 512-thread groups have 256 registers: a wave sum per injection
 #pragma unroll
         for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) {
-          const double v = wsum(xr[al] * zv0);
+          const double v = wsum(xz(al, zv0));
           if (lane == 0) lred[wv][al] = v;
         }
       }
@@ -372,7 +387,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
             double s = 0.0;
             if (NXR > 0) {
 #pragma unroll
-              for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) s += xr[al] * slr[al];
+              for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) s += xz(al, slr[al]);
             } else {
               for (int al = 0; al < ninj; ++al) s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
             }
@@ -418,11 +433,14 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         if constexpr (LR) {
           const double zv0 = z[0];
           if constexpr (BS == NT) {
-            lred[wv][lane] = wave_transpose_sum([&](int al) { return xr[al] * zv0; });
+            lred[wv][lane] = wave_transpose_sum([&](int al) { return xz(al, zv0); });
+            if constexpr (NXR > WAVE)
+              lred[wv][WAVE + lane] =
+                  wave_transpose_sum([&](int al) { return xz(WAVE + al, zv0); });
           } else {
 #pragma unroll
             for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) {
-              const double v = wsum(xr[al] * zv0);
+              const double v = wsum(xz(al, zv0));
               if (lane == 0) lred[wv][al] = v;
             }
           }
@@ -548,7 +566,14 @@ static void* pcg_fn_vb(int vpt) {
 template <typename T, int K, bool LR>
 static void* pcg_fn_v(int vpt, int bs, int nxr) {
   if (nxr > 0) {  // register-resident X: one voxel per thread, 256- or 512-thread groups
-    if (!LR || vpt != 1 || nxr != PCG_NXR) return nullptr;
+    if (!LR || vpt != 1) return nullptr;
+    if (nxr == PCG_NXR2) {  // 128 rows: FP32 data only
+      if constexpr (std::is_same<T, float>::value)
+        return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR2>
+                         : bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR2> : nullptr;
+      return nullptr;
+    }
+    if (nxr != PCG_NXR) return nullptr;
     return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR>
                      : bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR> : nullptr;
   }

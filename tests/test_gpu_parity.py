@@ -300,3 +300,24 @@ def test_warm_started_sweeps_match_cold_starts(monkeypatch, prec, tol):
     err = _wdiff(np_(w["U"]), np_(w["Z"]), np_(w["V"]), np_(c["U"]), np_(c["Z"]), np_(c["V"]))
     assert err <= tol, err
     assert w["stats"]["pcg_iters"] < c["stats"]["pcg_iters"]
+
+
+@pytest.mark.parametrize("xbs", ["256", "512"])
+def test_fp32_register_rows_up_to_128_injections(monkeypatch, xbs):
+    """Mixed precision with 64 < n_inj <= 128: the v-system PCG keeps 128 FP32
+    rows of X in registers (256- or 512-thread groups); lockstep with the
+    oracle at the mixed-precision bar."""
+    d = mid_box(seed=8, n_inj=100)
+    P = oop.problem_from_arrays(d)
+    R = 6
+    ores = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(
+        max_rank=R, als_fixed_sweeps=3, galerkin="dense", seed=5, u_method="dense",
+        v_method="dense"))
+    monkeypatch.setenv("CONNREG_PCG_XBS", xbs)
+    g = connreg.Problem(d, "mixed", DEV)
+    res = g.greedy_solve(max_rank=R, als_fixed_sweeps=3, pcg_rtol=1e-13, pcg_maxit=20000,
+                         galerkin_rtol=1e-13, galerkin_maxit=20000, seed=5)
+    g.close()
+    assert res["rank"] == R
+    err = _wdiff(np_(res["U"]), np_(res["Z"]), np_(res["V"]), ores.U, ores.Z, ores.V)
+    assert err <= 1e-4, err
