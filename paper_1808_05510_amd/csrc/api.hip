@@ -377,6 +377,7 @@ struct Ctx {
   double *sc = nullptr, *part = nullptr, *pcgpart = nullptr, *sbuf = nullptr, *gpart = nullptr;
   double* tmp = nullptr;
   int pcg_vpt_u = 1, pcg_vpt_v = 1, pcg_nwg_u = 1, pcg_nwg_v = 1, pcg_bs = NT;
+  int pcg_xtail_v = 0;  // v-system: register rows plus a streamed tail of X
   int pcg_bs_v = NT, pcg_nxr_v = 0;  // v-system: X rows in registers when n_inj <= PCG_NXR
   // stats of the last ALS
   int it_u = 0, it_v = 0, notconv = 0;
@@ -454,6 +455,7 @@ struct Ctx {
     // more in barrier arrivals than the 1024-thread kernel's register spills)
     pcg_bs_v = pcg_bs;
     pcg_nxr_v = 0;
+    pcg_xtail_v = 0;
     {
       const int tuned = P->tuned_vpt_v;
       const int want = vpt_opt > 0 ? vpt_opt : tuned;
@@ -486,6 +488,27 @@ struct Ctx {
             pcg_nxr_v = nxr_sel;
             break;
           }
+        }
+      }
+      // more injections than register rows: 64 rows in registers and the
+      // rest streamed, in 512-thread groups (252 VGPRs, two waves per SIMD)
+      if (pcg_nxr_v == 0 && ninj > PCG_NXR && want <= 1 && !P->no_xreg) {
+        PcgArgs<T> probe{};
+        probe.g = P->gx;
+        probe.Xm = X();
+        probe.vpt = 1;
+        probe.bs = 512;
+        probe.nxr = PCG_NXR;
+        probe.xtail = 1;
+        int maxwg = pcg_max_wg<T>(probe);
+        if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
+        const int64_t w = std::max<int64_t>(1, (nx + 511) / 512);
+        if (maxwg > 0 && w <= maxwg) {
+          pcg_vpt_v = 1;
+          pcg_nwg_v = (int)w;
+          pcg_bs_v = 512;
+          pcg_nxr_v = PCG_NXR;
+          pcg_xtail_v = 1;
         }
       }
     }
@@ -647,6 +670,7 @@ struct Ctx {
     a.vpt = usys ? pcg_vpt_u : pcg_vpt_v;
     a.bs = usys ? pcg_bs : pcg_bs_v;
     a.nxr = usys ? 0 : pcg_nxr_v;
+    a.xtail = usys ? 0 : pcg_xtail_v;
     a.bar.bar = P->bar;
     a.bar.mode = P->bar_mode;
     a.bar.coop = P->coop;

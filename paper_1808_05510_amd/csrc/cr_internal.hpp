@@ -221,6 +221,7 @@ struct PcgArgs {
   int vpt;              // voxels per thread
   int bs = NT;          // threads per workgroup (NT or 1024)
   int nxr = 0;          // PCG_NXR or PCG_NXR2: X rows in registers (low-rank term, vpt 1)
+  int xtail = 0;        // 1: more injections than nxr, the rest streamed
   BarrierArg bar;
 };
 constexpr int PCG_NXR = 64;  // injections held in registers by the X-resident PCG

@@ -182,10 +182,10 @@ __device__ __forceinline__ double lap(const T* __restrict__ w, const int32_t* __
 // partial X^T z over this workgroup's voxels, z staged in LDS
 template <typename T, int BS>
 __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, int64_t n, int nwg,
-                           double* lrpart) {
+                           double* lrpart, int al0 = 0) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int per = a.vpt * (BS / WAVE);  // rows per lane
-  for (int al = wv; al < a.ninj; al += BS / WAVE) {
+  for (int al = al0 + wv; al < a.ninj; al += BS / WAVE) {
     const T* xc = a.Xm + (int64_t)al * a.ldx;
     double acc = 0.0;
     for (int k = 0; k < per; ++k) {
@@ -209,9 +209,12 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // NXR > 0 (low-rank term, one voxel per thread, n_inj <= NXR): each thread
 // keeps its voxel's row of X in registers (in the data type T), so the X^T z
 // partials and the X (g o s) products read no memory.  NXR is 64, or 128 for
-// FP32 data (128 registers of X).
-template <typename T, int K, bool LR, int VPT, int BS, int NXR>
+// FP32 data (128 registers of X).  XTAIL: more injections than NXR; the
+// first NXR rows are in registers and the rest are streamed (z staged in LDS
+// for their partials), which halves the X traffic at 128 injections.
+template <typename T, int K, bool LR, int VPT, int BS, int NXR, bool XTAIL = false>
 __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
+  static_assert(!XTAIL || NXR > 0, "a streamed tail follows register rows");
   static_assert(NXR == 0 || (LR && VPT == 1), "register-resident X needs LR and VPT 1");
   cgrp::grid_group grid = cgrp::this_grid();
   __shared__ double red[2 * BS / WAVE];
@@ -270,12 +273,13 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         }
       }
       __syncthreads();
-      for (int al = threadIdx.x; al < ninj; al += BS) {
+      for (int al = threadIdx.x; al < (XTAIL ? NXR : ninj); al += BS) {
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < BS / WAVE; ++w) t += lred[w][al];
         lrpart[(int64_t)al * nwg + blockIdx.x] = t;
       }
+      if constexpr (XTAIL) lr_partial<T, BS>(a, zs, lo, n, nwg, lrpart, NXR);
     } else {
       lr_partial<T, BS>(a, zs, lo, n, nwg, lrpart);
     }
@@ -388,6 +392,9 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
             if (NXR > 0) {
 #pragma unroll
               for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) s += xz(al, slr[al]);
+              if constexpr (XTAIL)
+                for (int al = NXR; al < ninj; ++al)
+                  s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
             } else {
               for (int al = 0; al < ninj; ++al) s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
             }
@@ -419,9 +426,9 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
           rzn += r[m] * z[m];
           rrn += r[m] * r[m];
         }
-        if (LR && NXR == 0) zs[threadIdx.x + BS * m] = z[m];
+        if (LR && (NXR == 0 || XTAIL)) zs[threadIdx.x + BS * m] = z[m];
       }
-      if constexpr (LR && NXR == 0) {
+      if constexpr (LR && (NXR == 0 || XTAIL)) {
         __syncthreads();
         lr_part(z);
         block_sum2<BS>(rzn, rrn, red);
@@ -564,9 +571,13 @@ static void* pcg_fn_vb(int vpt) {
 }
 
 template <typename T, int K, bool LR>
-static void* pcg_fn_v(int vpt, int bs, int nxr) {
+static void* pcg_fn_v(int vpt, int bs, int nxr, int xtail) {
   if (nxr > 0) {  // register-resident X: one voxel per thread, 256- or 512-thread groups
     if (!LR || vpt != 1) return nullptr;
+    if (xtail) {  // 64 register rows and a streamed tail, 512-thread groups
+      if (nxr != PCG_NXR) return nullptr;
+      return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR, true> : nullptr;
+    }
     if (nxr == PCG_NXR2) {  // 128 rows: FP32 data only
       if constexpr (std::is_same<T, float>::value)
         return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR2>
@@ -582,11 +593,12 @@ static void* pcg_fn_v(int vpt, int bs, int nxr) {
 }
 
 template <typename T>
-static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr) {
+static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr, int xtail) {
   switch (K) {
-#define CASE(KK) \
-  case KK:       \
-    return lr ? pcg_fn_v<T, KK, true>(vpt, bs, nxr) : pcg_fn_v<T, KK, false>(vpt, bs, nxr);
+#define CASE(KK)                                                                     \
+  case KK:                                                                           \
+    return lr ? pcg_fn_v<T, KK, true>(vpt, bs, nxr, xtail)                           \
+              : pcg_fn_v<T, KK, false>(vpt, bs, nxr, xtail);
     CASE(2) CASE(4) CASE(6) CASE(8)
 #undef CASE
     default:
@@ -596,7 +608,7 @@ static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr) {
 
 template <typename T>
 int pcg_max_wg(const PcgArgs<T>& a) {
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail);
   if (!fn) return 0;
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -620,7 +632,7 @@ cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
     set_error("pcg: grid does not cover the voxels");
     return CR_EINVAL;
   }
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail);
   if (!fn) {
     set_error("pcg: unsupported stencil width or voxels per thread");
     return CR_EINVAL;
