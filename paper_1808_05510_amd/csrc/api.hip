@@ -2261,9 +2261,39 @@ extern "C" cr_status cr_masked_gram(cr_problem* P, int64_t r, const double* U, i
 }
 
 // ===================================================================== batched solves, autotuning
+// The v-system counts as fitting only in the form it takes alone: with its
+// rows of X in registers when n_inj allows (64 rows, 128 FP32 rows, or 64 and
+// a streamed tail), since losing them to a share cost more than concurrency
+// gained (16-problem batch: 15.4 s one at a time against 16.8 s batched).
+template <typename T>
+static bool xreg_fits_share(cr_problem* P, int share) {
+  const int ninj = P->ninj;
+  const int nxr = ninj <= PCG_NXR ? PCG_NXR
+                  : (std::is_same<T, float>::value && ninj <= PCG_NXR2) ? PCG_NXR2 : PCG_NXR;
+  const int xtail = (ninj > nxr) ? 1 : 0;
+  for (int bs : {NT, 512}) {
+    PcgArgs<T> probe{};
+    probe.g = P->gx;
+    probe.Xm = P->X<T>();
+    probe.vpt = 1;
+    probe.bs = bs;
+    probe.nxr = nxr;
+    probe.xtail = xtail;
+    const int m = pcg_max_wg<T>(probe);
+    const int64_t w = (P->gx.n + bs - 1) / bs;
+    if (m > 0 && w <= (share > 0 ? share_cap(m, share) : m)) return true;
+  }
+  return false;
+}
+
 // does every persistent PCG grid of problem P fit in `share` CUs?
 template <typename T>
 static bool fits_share_t(cr_problem* P, int share) {
+  if (!P->no_xreg && !xreg_fits_share<T>(P, 0)) {
+    // (no register form even alone: the streamed form decides below)
+  } else if (!P->no_xreg && !xreg_fits_share<T>(P, share)) {
+    return false;
+  }
   for (int sys = 0; sys < 2; ++sys) {
     const Geom& g = sys ? P->gx : P->gy;
     bool ok = false;
