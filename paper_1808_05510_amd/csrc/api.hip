@@ -335,6 +335,12 @@ __global__ void k_fcg_update(int64_t n, const double* __restrict__ S, const doub
   r[i] -= a * q[i];
 }
 
+// a zero or non-finite right-hand side ends the flexible CG as a breakdown
+// (every later scalar kernel of the iteration is then a no-op)
+__global__ void k_fcg_init(double* S) {
+  if (!(S[FS_BB] > 0.0)) S[FS_STATE] = 2.0;
+}
+
 __global__ void k_fcg_check(double* S, double tol2) {
   if (S[FS_STATE] != 0.0) return;
   S[FS_IT] += 1.0;
@@ -946,14 +952,11 @@ struct Ctx {
       hipLaunchKernelGGL(k_scale1, dim3(1), dim3(1), 0, st, S + FS_DBAR, 1.0 / (double)n);
       CR_HIP(hipGetLastError());
     }
+    // (the zero right-hand side is detected on the device: no host read here)
+    hipLaunchKernelGGL(k_fcg_init, dim3(1), dim3(1), 0, st, S);
+    CR_HIP(hipGetLastError());
     double h[FS_N];
-    CR_TRY(read_scalars(S, 1, h));
-    const double bb = h[0];
     *out = SolveOut{};
-    if (!(bb > 0.0)) {
-      out->status = 2;
-      return CR_OK;
-    }
     const double tol2 = rtol * rtol;
     int it = 0;
     for (; it < maxit; ++it) {
@@ -1009,14 +1012,16 @@ struct Ctx {
         if (h[FS_STATE] != 0.0) break;
       }
     }
+    // ||x||^2 goes into the slot of ||w||^2 (free after the loop), so one
+    // read brings every final scalar
+    CR_TRY(dot64(n, xsol, xsol, S + FS_WW));
     CR_TRY(read_scalars(S, FS_N, h));
+    const double bb = h[FS_BB];
     out->iters = (int)h[FS_IT];
-    out->relres = std::sqrt(std::max(h[FS_RR], 0.0) / bb);
+    out->relres = bb > 0.0 ? std::sqrt(std::max(h[FS_RR], 0.0) / bb) : 0.0;
     out->status = h[FS_STATE] == 2.0 ? 2 : h[FS_STATE] == 1.0 ? 0 : 1;
     *fallbacks = (int)h[FS_FB];
-    CR_TRY(dot64(n, xsol, xsol, S + FS_WW));
-    CR_TRY(read_scalars(S + FS_WW, 1, h));
-    out->norm = std::sqrt(h[0]);
+    out->norm = std::sqrt(std::max(h[FS_WW], 0.0));
     return CR_OK;
   }
 
