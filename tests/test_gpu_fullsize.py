@@ -1,0 +1,77 @@
+"""Parity at the benchmark's full sizes, in the launch configurations that
+bench.py times.
+
+* op_apply on the cortex-shell workload (n_y 262,136, n_x 131,068, n_inj 128)
+  at r = 100, FP64 and FP32 handles: every output element against the FP64
+  oracle (sparse products and one dense product, under a second each at this
+  size), at the bars of the small cases (1e-13 / 1e-12 FP64, 2e-6 FP32).
+* The greedy solve on the 40^3 / 30^3 grids (n_y 64,000, n_x 27,000, n_inj
+  64): three ranks in lockstep with the oracle (same initial vectors, two ALS
+  sweeps per rank, inner solves to 1e-12 on both sides), W within 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import greedy as ogreedy
+from oracle import metrics as omet
+from oracle import operator as oop
+from paper_1808_05510_amd import connreg, synth
+from tests.helpers import rel
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def np_(t):
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+@pytest.fixture(scope="module")
+def shells():
+    d = synth.config3(seed=0)
+    return d, oop.problem_from_arrays(d)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_op_apply_full_shells_r100(shells, fp32):
+    d, P = shells
+    r = 100
+    rng = np.random.default_rng(21)
+    U = rng.standard_normal((P.n_y, r))
+    V = rng.standard_normal((P.n_x, r))
+    Z = rng.standard_normal((r, r))
+    if fp32:  # the FP32 path takes FP32 inputs: compare on the rounded values
+        U, V, Z = (a.astype(np.float32).astype(np.float64) for a in (U, V, Z))
+    g = connreg.Problem(d, "mixed" if fp32 else "fp64", DEV)
+    F, G = g.op_apply(U, Z, V, fp32=fp32)
+    F, G = np_(F), np_(G)
+    g.close()
+    f = oop.op_apply(P, U, Z, V)
+    assert F.shape == (P.n_y, 2 * r + P.n_inj) and G.shape == (P.n_x, 2 * r)
+    tol, tol_m = (2e-6, 2e-6) if fp32 else (1e-13, 1e-12)
+    assert rel(F[:, :r], f.LyU) < tol
+    assert rel(F[:, r:2 * r], f.Ly2U) < tol
+    assert rel(G[:, :r], f.LxV) < tol
+    assert rel(G[:, r:], f.Lx2V) < tol
+    assert rel(F[:, 2 * r:], f.M) < tol_m
+
+
+def test_greedy_full_grid_lockstep():
+    d = synth.config2(lam=1e3, seed=0)
+    P = oop.problem_from_arrays(d)
+    R = 3
+    ores = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(
+        max_rank=R, als_fixed_sweeps=2, galerkin="dense", seed=0, u_method="cg", v_method="cg",
+        inner_rtol=1e-12))
+    g = connreg.Problem(d, "fp64", DEV)
+    res = g.greedy_solve(max_rank=R, als_fixed_sweeps=2, pcg_rtol=1e-12, pcg_maxit=200000,
+                         galerkin_rtol=1e-13, galerkin_maxit=20000, seed=0)
+    g.close()
+    assert res["rank"] == R
+    U, V, Z = np_(res["U"]), np_(res["V"]), np_(res["Z"])
+    err = (omet.diff_norm(U, Z, V, ores.U, ores.Z, ores.V)
+           / omet.low_rank_norm(ores.U, ores.Z, ores.V))
+    assert err <= 1e-6, err
+    for hg, ho in zip(res["history"], ores.history):
+        assert abs(hg["relres"] - ho["relres"]) <= 1e-6 * ho["relres"]
