@@ -7,7 +7,8 @@ bench.py times.
   size), at the bars of the small cases (1e-13 / 1e-12 FP64, 2e-6 FP32).
 * The greedy solve on the 40^3 / 30^3 grids (n_y 64,000, n_x 27,000, n_inj
   64): three ranks in lockstep with the oracle (same initial vectors, two ALS
-  sweeps per rank, inner solves to 1e-12 on both sides), W within 1e-6.
+  sweeps per rank, inner solves to 1e-12 on both sides), W within 1e-6 (FP64)
+  and 1e-4 (mixed precision).
 """
 import numpy as np
 import pytest
@@ -57,14 +58,21 @@ def test_op_apply_full_shells_r100(shells, fp32):
     assert rel(F[:, 2 * r:], f.M) < tol_m
 
 
-def test_greedy_full_grid_lockstep():
+@pytest.fixture(scope="module")
+def grid_oracle():
     d = synth.config2(lam=1e3, seed=0)
     P = oop.problem_from_arrays(d)
-    R = 3
     ores = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(
-        max_rank=R, als_fixed_sweeps=2, galerkin="dense", seed=0, u_method="cg", v_method="cg",
+        max_rank=3, als_fixed_sweeps=2, galerkin="dense", seed=0, u_method="cg", v_method="cg",
         inner_rtol=1e-12))
-    g = connreg.Problem(d, "fp64", DEV)
+    return d, ores
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-6), ("mixed", 1e-4)])
+def test_greedy_full_grid_lockstep(grid_oracle, prec, tol):
+    d, ores = grid_oracle
+    R = 3
+    g = connreg.Problem(d, prec, DEV)
     res = g.greedy_solve(max_rank=R, als_fixed_sweeps=2, pcg_rtol=1e-12, pcg_maxit=200000,
                          galerkin_rtol=1e-13, galerkin_maxit=20000, seed=0)
     g.close()
@@ -72,6 +80,6 @@ def test_greedy_full_grid_lockstep():
     U, V, Z = np_(res["U"]), np_(res["V"]), np_(res["Z"])
     err = (omet.diff_norm(U, Z, V, ores.U, ores.Z, ores.V)
            / omet.low_rank_norm(ores.U, ores.Z, ores.V))
-    assert err <= 1e-6, err
+    assert err <= tol, err
     for hg, ho in zip(res["history"], ores.history):
-        assert abs(hg["relres"] - ho["relres"]) <= 1e-6 * ho["relres"]
+        assert abs(hg["relres"] - ho["relres"]) <= (1e-6 if prec == "fp64" else 1e-3) * ho["relres"]
