@@ -9,16 +9,20 @@ bench.py times.
   64): three ranks in lockstep with the oracle (same initial vectors, two ALS
   sweeps per rank, inner solves to 1e-12 on both sides), W within 1e-6 (FP64)
   and 1e-4 (mixed precision).
+* A u-system of that grid (eq. ALS_linsys, n_y 64,000) solved by Jacobi-PCG,
+  by flexible CG with the spectral base step and with the (untrained)
+  network, against the oracle's Jacobi-CG solution at 1e-13.
 """
 import numpy as np
 import pytest
 import torch
 
+from oracle import als as oals
 from oracle import greedy as ogreedy
 from oracle import metrics as omet
 from oracle import operator as oop
 from paper_1808_05510_amd import connreg, synth
-from tests.helpers import rel
+from tests.helpers import rand_orth, rel
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -83,3 +87,31 @@ def test_greedy_full_grid_lockstep(grid_oracle, prec, tol):
     assert err <= tol, err
     for hg, ho in zip(res["history"], ores.history):
         assert abs(hg["relres"] - ho["relres"]) <= (1e-6 if prec == "fp64" else 1e-3) * ho["relres"]
+
+
+def test_u_solves_full_grid():
+    d = synth.config2(lam=1e3, seed=0)
+    P = oop.problem_from_arrays(d)
+    rng = np.random.default_rng(31)
+    r = 3
+    U = rand_orth(rng, P.n_y, r)
+    V = rand_orth(rng, P.n_x, r)
+    Z = rng.standard_normal((r, r))
+    v = rng.standard_normal(P.n_x)
+    v /= np.linalg.norm(v)
+    g = connreg.Problem(d, "fp64", DEV)
+    g.set_box(d["box_y"])
+    rhs, dd, coef = g.u_system(U, Z, V, v)
+    xref = oals.solve_u(P, v, rhs.cpu().numpy(), method="cg", rtol=1e-13, maxit=200000)
+    xs = {}
+    for kind in ("jacobi", "base"):
+        x, it, rr, fb, st = g.u_solve(dd, coef, rhs, rtol=1e-13, maxit=200000, precond=kind)
+        assert st == "ok", (kind, st)
+        xs[kind] = x.cpu().numpy()
+        assert rel(xs[kind], xref) < 1e-7, kind
+    pc = connreg.Pc(d["box_y"], channels=8, seed=7)
+    x, it, rr, fb, st = g.u_solve(dd, coef, rhs, rtol=1e-13, maxit=200000, pc=pc)
+    assert st in ("ok", "pc_fallback") and rel(x.cpu().numpy(), xref) < 1e-7
+    assert rel(xs["base"], xs["jacobi"]) < 1e-7
+    pc.close()
+    g.close()
