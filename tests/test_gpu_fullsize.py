@@ -12,6 +12,9 @@ bench.py times.
 * A u-system of that grid (eq. ALS_linsys, n_y 64,000) solved by Jacobi-PCG,
   by flexible CG with the spectral base step and with the (untrained)
   network, against the oracle's Jacobi-CG solution at 1e-13.
+* An ALS step of that grid with both boxes declared (flexible CG with the
+  spectral base step for u, the SMW direct solve for v: the solvers of the
+  mixed + learned-preconditioner benchmark) in lockstep with the oracle's ALS.
 """
 import numpy as np
 import pytest
@@ -115,3 +118,28 @@ def test_u_solves_full_grid():
     assert rel(xs["base"], xs["jacobi"]) < 1e-7
     pc.close()
     g.close()
+
+
+def test_als_step_full_grid_spectral_and_smw():
+    d = synth.config2(lam=1e3, seed=0)
+    P = oop.problem_from_arrays(d)
+    rng = np.random.default_rng(41)
+    r = 3
+    U = rand_orth(rng, P.n_y, r)
+    V = rand_orth(rng, P.n_x, r)
+    Z = rng.standard_normal((r, r))
+    F, G = oop.residual_factors(P, U, Z, V)
+    v0 = ogreedy.init_v(P, F, G, 7, r)
+    a = oals.als(P, F, G, v0, fixed_sweeps=2, u_method="cg", v_method="cg", rtol=1e-13)
+    g = connreg.Problem(d, "fp64", DEV)
+    g.set_box(d["box_y"])
+    g.set_box(d["box_x"], which="source")
+    g.set_precond("base")
+    u, v, st = g.als_step(U, Z, V, v0, als_fixed_sweeps=2, pcg_rtol=1e-13, pcg_maxit=200000)
+    g.close()
+    assert st["sweeps"] == 2 and st["status"] == "ok"
+    assert abs(abs(float(np_(u) @ a.u)) - 1.0) < 1e-9
+    assert abs(abs(float(np_(v) @ a.v)) - 1.0) < 1e-9
+    # (solutions to 1e-13 of systems with condition numbers up to about 1e6)
+    assert abs(st["unorm"] - a.unorm) <= 1e-7 * a.unorm
+    assert abs(st["vnorm"] - a.vnorm) <= 1e-7 * a.vnorm
