@@ -15,6 +15,9 @@ bench.py times.
 * An ALS step of that grid with both boxes declared (flexible CG with the
   spectral base step for u, the SMW direct solve for v: the solvers of the
   mixed + learned-preconditioner benchmark) in lockstep with the oracle's ALS.
+* The benchmark's 16-problem batch (n_y 20k-120k, n_inj 16-128): one batched
+  call against the same problems solved one at a time (a property at any
+  size: the same factors to the inner tolerance), three ranks in FP64.
 """
 import numpy as np
 import pytest
@@ -143,3 +146,23 @@ def test_als_step_full_grid_spectral_and_smw():
     # (solutions to 1e-13 of systems with condition numbers up to about 1e6)
     assert abs(st["unorm"] - a.unorm) <= 1e-7 * a.unorm
     assert abs(st["vnorm"] - a.vnorm) <= 1e-7 * a.vnorm
+
+
+def test_batch_full_size_matches_one_at_a_time():
+    specs = synth.config4_specs(0, 16)
+    ds = [synth.box_problem(box_y=sp.box_y, box_x=sp.box_x,
+                            offset=tuple((np.array(sp.box_y) - np.array(sp.box_x)) // 2),
+                            n_inj=sp.n_inj, lam=sp.lam, max_rank=3, seed=sp.seed) for sp in specs]
+    streams = [torch.cuda.Stream() for _ in ds]
+    probs = [connreg.Problem(d, "fp64", DEV, stream=st) for d, st in zip(ds, streams)]
+    o = dict(max_rank=3, als_fixed_sweeps=2, pcg_rtol=1e-12, pcg_maxit=200000,
+             galerkin_rtol=1e-12, galerkin_maxit=20000, seed=5)
+    seq = [p.greedy_solve(**o) for p in probs]
+    bat = connreg.greedy_solve_batch(probs, [o] * len(probs))
+    for a, b in zip(seq, bat):
+        x = [np_(a[k]) for k in ("U", "Z", "V")]
+        y = [np_(b[k]) for k in ("U", "Z", "V")]
+        err = omet.diff_norm(y[0], y[1], y[2], x[0], x[1], x[2]) / omet.low_rank_norm(*x)
+        assert b["status"] == "ok" and b["rank"] == a["rank"] == 3 and err < 1e-8, err
+    for p in probs:
+        p.close()
