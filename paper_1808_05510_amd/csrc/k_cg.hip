@@ -207,9 +207,9 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // updates), phase D (p = z + beta p, t = L z + beta t, needs z at
 // neighbours), each ended by a grid barrier.
 // NXR > 0 (low-rank term, one voxel per thread, n_inj <= NXR): each thread
-// keeps its voxel's row of X in registers (in the data type T), so the X^T z
-// partials and the X (g o s) products read no memory.  NXR is 64, or 128 for
-// FP32 data (128 registers of X).  XTAIL: more injections than NXR; the
+// keeps its voxel's row of X in registers, so the X^T z partials and the
+// X (g o s) products read no memory.  NXR is 64 (rows held in FP64), or 128
+// for FP32 data (rows held in FP32, 128 registers).  XTAIL: more injections than NXR; the
 // first NXR rows are in registers and the rest are streamed (z staged in LDS
 // for their partials), which halves the X traffic at 128 injections.
 template <typename T, int K, bool LR, int VPT, int BS, int NXR, bool XTAIL = false>
