@@ -497,7 +497,7 @@ struct Ctx {
         }
       }
       // more injections than register rows: 64 rows in registers and the
-      // rest streamed, in 512-thread groups (252 VGPRs, two waves per SIMD)
+      // rest streamed, in 512-thread groups (253 VGPRs, two waves per SIMD)
       if (pcg_nxr_v == 0 && ninj > PCG_NXR && want <= 1 && !P->no_xreg) {
         PcgArgs<T> probe{};
         probe.g = P->gx;
@@ -686,8 +686,9 @@ struct Ctx {
   // FP64 Jacobi-PCG of an ALS half-step, warm-started from the previous
   // sweep's unnormalised solution of the same system (the system changes
   // with the other factor, its solution little once the sweeps settle): the
-  // kernel solves A e = b - A x0 from x0, to ||b - A x|| <= rtol ||b||.  The
-  // first solve of each system in an ALS starts from zero.
+  // kernel starts at x0 with the residual b - A x0 and stops at
+  // ||b - A x|| <= rtol ||b||.  The first solve of each system in an ALS
+  // starts from zero.
   bool warm_u_ok = false, warm_v_ok = false;
   cr_status pcg_warm(bool usys, const T* b, T* xout, double rtol, int maxit, double* scal) {
     const int64_t n = usys ? ny : nx;
