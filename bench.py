@@ -61,6 +61,82 @@ def op_traffic():
     return t["traffic_bytes"] if t.get("sources_sha") == traffic.sources_hash() else None
 
 
+def sig(x, n=4):
+    """x rounded to n significant digits (compact JSON)."""
+    if x is None or not np.isfinite(x) or x == 0:
+        return x
+    return float(f"{x:.{n}g}")
+
+
+def w_rel_diff(a, b):
+    """||W_a - W_b||_F / ||W_b||_F for two results W = U Z V^T (torch, FP64,
+    through thin QR of the stacked factors; measurement only)."""
+    def fro(F, G):
+        rf = torch.linalg.qr(F, mode="r")[1]
+        rg = torch.linalg.qr(G, mode="r")[1]
+        return float(torch.linalg.norm(rf @ rg.T))
+    Ua, Za, Va = (a[k].to(torch.float64) for k in ("U", "Z", "V"))
+    Ub, Zb, Vb = (b[k].to(torch.float64) for k in ("U", "Z", "V"))
+    d = fro(torch.cat([Ua @ Za, -(Ub @ Zb)], 1), torch.cat([Va, Vb], 1))
+    return d / fro(Ub @ Zb, Vb)
+
+
+def write_detail(path, detail):
+    """Curves, per-problem arrays and every figure behind the summary line."""
+    if not path:
+        return
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(detail, f, indent=1, default=float)
+    log(f"[bench] details written to {path}")
+
+
+def compact_cpu(cpu):
+    if cpu is None:
+        return None
+    keep = ("value", "unit", "cores", "kind", "sample")
+    out = {k: cpu[k] for k in keep}
+    out["value"] = sig(out["value"])
+    return out
+
+
+def summarize(mixed, learned, shells, batch, op):
+    """Scalar figures of every leg for the one-line result (seconds, relres,
+    W error against the FP64 GPU solve, bandwidths)."""
+    s = {}
+    if mixed:
+        s["mixed"] = dict(s=sig(mixed["seconds"]), relres=sig(mixed["relres"]),
+                          w_err_vs_fp64=sig(mixed.get("w_err_vs_fp64")),
+                          fp64_same_rtol_s=sig(mixed["fp64_same_rtol"]["seconds"]))
+    if learned:
+        s["mixed_learned_pc"] = dict(
+            s=sig(learned["learned"]["seconds"]), relres=sig(learned["learned"]["relres"]),
+            w_err_vs_fp64=sig(learned["learned"].get("w_err_vs_fp64")),
+            base_step_s=sig(learned["base"]["seconds"]),
+            train_s=sig(learned["train_s"]), pairs=learned["pairs"],
+            inner_iters={k: sig(v["mean_iters"], 3) for k, v in learned["inner_u_solves"].items()},
+            inner_ms={k: sig(v["mean_ms"], 3) for k, v in learned["inner_u_solves"].items()})
+    if shells:
+        s["shells"] = {k: dict(s=sig(v["seconds"]), rank=v["rank"], relres=sig(v["relres"]))
+                       for k, v in shells.items() if isinstance(v, dict) and "seconds" in v}
+        if "w_err_mixed_vs_fp64" in shells:
+            s["shells"]["w_err_mixed_vs_fp64"] = sig(shells["w_err_mixed_vs_fp64"])
+    if batch:
+        s["batch"] = dict(seq_s=sig(batch["sequential_s"]), batched_s=sig(batch["batched_s"]),
+                          speedup=sig(batch["speedup"], 3))
+        if batch.get("with_base_step"):
+            bb = batch["with_base_step"]
+            s["batch"]["base_step"] = dict(seq_s=sig(bb["sequential_s"]),
+                                           batched_s=sig(bb["batched_s"]),
+                                           speedup=sig(bb["speedup"], 3))
+    if op:
+        s["op_apply_GBps"] = {k: round(v["GBps_mean"]) for k, v in op.items() if "GBps_mean" in v}
+        if "gram" in op:
+            s["gram_bf16_TFLOPs"] = {k: round(v["TFLOPs"]) for k, v in op["gram"].items()}
+    return s
+
+
 def time_solves(prob, steps, warmup, opts):
     res = None
     for _ in range(warmup):
@@ -185,7 +261,8 @@ def bench_batch(count=16, max_rank=40, tau=1e-4, prec="mixed", precond="jacobi")
     return out
 
 
-def bench_learned(d2, lam, opts, steps, warmup, train_seeds=(100, 101), train_steps=300):
+def bench_learned(d2, lam, opts, steps, warmup, train_seeds=(100, 101), train_steps=300,
+                  ref=None):
     """Mixed precision with the learned u-system preconditioner on the same
     workload: the network (spectral base step + 3-D conv refinement) is
     trained on u-systems dumped from FP64 greedy runs of other seeds (same
@@ -240,6 +317,8 @@ def bench_learned(d2, lam, opts, steps, warmup, train_seeds=(100, 101), train_st
                          relres=mres["stats"]["relres"], pcg_iters=mres["stats"]["pcg_iters"],
                          reached_tau=bool(mres["stats"]["relres"] <= opts["tau_res"]),
                          curve=[[h["rank"], h["relres"], h["seconds"]] for h in mres["history"]])
+        if ref is not None:
+            out[kind]["w_err_vs_fp64"] = w_rel_diff(mres, ref)
         pm.set_pc(None)
         pm.close()
     for h in handles:
@@ -249,31 +328,46 @@ def bench_learned(d2, lam, opts, steps, warmup, train_seeds=(100, 101), train_st
 
 
 def bench_shells(steps=1):
-    """Greedy solve on the cortex-shell workload (plain FP64 and mixed), to
-    relres 1e-4 or the rank cap of 100: one timed solve each after a short
-    warm-up that allocates the workspace."""
+    """Greedy solve on the cortex-shell workload, to relres 1e-4 or the rank
+    cap of 100: plain FP64 (inner rtol 1e-8 and, for comparison at equal
+    tolerance, 1e-4) and mixed (1e-4); one timed solve each after a short
+    warm-up that allocates the workspace.  The mixed W error is taken
+    against the plain FP64 solve."""
     d3 = synth.config3(seed=0)
     out = {}
-    for prec in ("fp64", "mixed"):
+    results = {}
+    for key, prec, rtol in (("fp64", "fp64", FP64_RTOL), ("fp64_rtol1e-4", "fp64", MIXED_RTOL),
+                            ("mixed", "mixed", MIXED_RTOL)):
         p = connreg.Problem(d3, prec, "cuda:0")
-        rtol = MIXED_RTOL if prec == "mixed" else FP64_RTOL
         p.greedy_solve(max_rank=2, tau_res=1e-4, seed=0, pcg_rtol=rtol)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = p.greedy_solve(max_rank=int(d3["max_rank"]), tau_res=1e-4, seed=0, pcg_rtol=rtol)
         torch.cuda.synchronize()
-        out[prec] = dict(seconds=time.perf_counter() - t0, rank=res["rank"],
-                         relres=res["stats"]["relres"], pcg_iters=res["stats"]["pcg_iters"],
-                         reached_tau=bool(res["stats"]["relres"] <= 1e-4),
-                         curve=[[h["rank"], h["relres"], h["seconds"]] for h in res["history"]])
+        out[key] = dict(seconds=time.perf_counter() - t0, rank=res["rank"], pcg_rtol=rtol,
+                        relres=res["stats"]["relres"], pcg_iters=res["stats"]["pcg_iters"],
+                        reached_tau=bool(res["stats"]["relres"] <= 1e-4),
+                        curve=[[h["rank"], h["relres"], h["seconds"]] for h in res["history"]])
+        results[key] = res
         p.close()
+    out["w_err_mixed_vs_fp64"] = w_rel_diff(results["mixed"], results["fp64"])
     return out
 
 
+def blas_threads():
+    from threadpoolctl import threadpool_info
+    n = [i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"]
+    return max(n) if n else 1
+
+
 def cpu_baseline(d, lam, ranks_needed, sample_ranks):
-    """FP64 oracle (NumPy/SciPy, Jacobi-CG inner solves) on the first
-    ``sample_ranks`` greedy steps of the same workload; seconds per rank times
-    the ranks the GPU needed.  Also: the same sample's first rank on one host
+    """FP64 oracle (NumPy/SciPy, Jacobi-CG inner solves to 1e-8, dense
+    projected solve) on the first ``sample_ranks`` greedy steps of the same
+    workload, on the host's BLAS threads.  A rank costs more as the basis
+    grows (the residual factors have n_inj + 3j columns), so the seconds of
+    the later half of the sample are fitted linearly in j and summed over
+    the ranks the GPU solve needed; with sample_ranks >= ranks_needed the
+    value is the measured time itself.  Also: the first rank on one host
     thread, and the full 1-D toy solve (rank 20, dense inner solves)."""
     from threadpoolctl import threadpool_limits
 
@@ -281,10 +375,24 @@ def cpu_baseline(d, lam, ranks_needed, sample_ranks):
     from oracle import operator as oop
     P = oop.problem_from_arrays(d, lam=lam)
     opts = dict(u_method="cg", v_method="cg", inner_rtol=1e-8, galerkin="dense", tau_res=1e-4)
+    threads = blas_threads()
     t0 = time.perf_counter()
     res = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(max_rank=sample_ranks, **opts))
     dt = time.perf_counter() - t0
-    per_rank = dt / max(1, len(res.history))
+    done = len(res.history)
+    ends = np.array([h["seconds"] for h in res.history])
+    per = np.diff(np.concatenate([[0.0], ends]))
+    if done >= ranks_needed:
+        value = float(ends[ranks_needed - 1])
+        how = f"measured over all {ranks_needed} ranks"
+    else:
+        js = np.arange(1, done + 1)
+        half = max(0, done // 2 - 1)
+        b, a = np.polyfit(js[half:], per[half:], 1) if done - half >= 2 else (0.0, per.mean())
+        rest = np.arange(done + 1, ranks_needed + 1)
+        value = float(ends[-1] + np.sum(np.maximum(a + b * rest, per[-1])))
+        how = (f"first {done} ranks measured ({dt:.1f} s); ranks {done + 1}-{ranks_needed} "
+               f"extrapolated from a linear fit of seconds per rank over ranks {half + 1}-{done}")
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         ogreedy.greedy_solve(P, ogreedy.GreedyOptions(max_rank=1, **opts))
@@ -296,11 +404,10 @@ def cpu_baseline(d, lam, ranks_needed, sample_ranks):
         max_rank=int(d1["max_rank"]), tau_res=float(d1["tau_res"]), u_method="dense",
         v_method="dense", galerkin="dense"))
     toy_s = time.perf_counter() - t0
-    return dict(value=per_rank * ranks_needed, unit="s", cores=os.cpu_count(), kind="oracle",
-                sample=f"first {len(res.history)} greedy ranks of the same workload on the host "
-                       f"({dt:.1f} s, {per_rank:.2f} s/rank), scaled by the {ranks_needed} ranks "
-                       f"the GPU solve needed (extrapolated; later ranks cost more on the CPU)",
-                seconds_per_rank=per_rank, one_thread_first_rank_s=one_thread_rank,
+    return dict(value=value, unit="s", cores=threads, kind="oracle",
+                sample=f"FP64 oracle greedy solve of the same 40^3/30^3 workload to rank "
+                       f"{ranks_needed} on {threads} host threads: {how}",
+                seconds_per_rank=[float(x) for x in per], one_thread_first_rank_s=one_thread_rank,
                 toy_1d_full_solve_s=toy_s, toy_1d_rank=len(r1.history))
 
 
@@ -315,6 +422,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-op", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-ranks", type=int, default=12,
+                    help="oracle ranks timed for cpu_baseline (the rest extrapolated)")
     ap.add_argument("--op-reps", type=int, default=100)
     ap.add_argument("--op-warm", type=int, default=20)
     ap.add_argument("--verbose", action="store_true")
@@ -325,6 +434,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-shells", action="store_true")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for curves and per-problem arrays ('' = none)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the solver is a "
@@ -392,8 +503,10 @@ def main():
         op["gram"] = gram
         o = op["f64_r100"]
         # achieved: algorithmic bytes over the mean event-timed call
-        roof = dict(bound="hbm", achieved=o["GBps_mean"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=o["GBps_mean"] / HBM_PEAK_GBS, traffic=op_traffic(),
+        tr = op_traffic()
+        roof = dict(bound="hbm", achieved=round(o["GBps_mean"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(o["GBps_mean"] / HBM_PEAK_GBS, 4),
+                    traffic=None if tr is None else int(tr),
                     kernel="cr_op_apply (FP64, r=100, shells)")
         del d3
 
@@ -413,7 +526,8 @@ def main():
         mt, mtimes, mres = time_solves(pm, a.steps, a.warmup, mopts)
         mixed = dict(seconds=float(np.mean(mtimes)), rank=mres["rank"],
                      relres=mres["stats"]["relres"], pcg_iters=mres["stats"]["pcg_iters"],
-                     galerkin_iters=mres["stats"]["galerkin_iters"], pcg_rtol=MIXED_RTOL)
+                     galerkin_iters=mres["stats"]["galerkin_iters"], pcg_rtol=MIXED_RTOL,
+                     w_err_vs_fp64=w_rel_diff(mres, res))
         log(f"[bench] mixed: {mixed['seconds']:.3f} s/solve, rank {mixed['rank']}")
         pm.close()
         # context: plain FP64 at the mixed runs' inner tolerance, which shows
@@ -428,7 +542,7 @@ def main():
     learned = None
     if not a.no_learned:
         log("[bench] mixed precision + learned u-system preconditioner")
-        learned = bench_learned(d2, a.lam, mopts, a.steps, a.warmup)
+        learned = bench_learned(d2, a.lam, mopts, a.steps, a.warmup, ref=res)
         log(f"[bench] mixed+learned: {learned['learned']['seconds']:.3f} s/solve "
             f"(base step alone {learned['base']['seconds']:.3f} s; training "
             f"{learned['train_s']:.1f} s on {learned['pairs']} pairs)")
@@ -454,43 +568,44 @@ def main():
     cpu = None
     if not a.no_cpu:
         log("[bench] CPU oracle sample")
-        cpu = cpu_baseline(d2, a.lam, ranks, 2)
+        cpu = cpu_baseline(d2, a.lam, ranks, a.cpu_ranks)
 
     secs = float(np.mean(times))
-    out = {
+    curve = [[h["rank"], h["relres"], h["seconds"]] for h in hist]
+    detail = {
+        "fp64": dict(seconds=times, rank=ranks, relres=res["stats"]["relres"],
+                     pcg_iters=res["stats"]["pcg_iters"],
+                     galerkin_iters=res["stats"]["galerkin_iters"], relres_curve=curve),
+        "mixed": mixed, "mixed_learned_pc": learned, "shells": shells, "op_apply": op,
+        "batch": batch, "roofline": roof, "cpu_baseline": cpu,
+    }
+    write_detail(a.detail, detail)
+    line = {
         "metric": METRIC,
-        "value": secs,
+        "value": round(secs, 5),
         "unit": "s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": secs * 1e3,
+        "ms_per_step": round(secs * 1e3, 3),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "3D grids: 40^3 target (n_y 64,000), 30^3 source (n_x 27,000), "
-                               "n_inj 64, lambda 1e3, rank cap 60, plain FP64, Jacobi-PCG",
-                   "tau_res": a.tau, "seed": 0, "pcg_rtol": FP64_RTOL},
+        "config": {"workload": "3D grids 40^3 target / 30^3 source, n_inj 64, lambda 1e3, "
+                               "rank cap 60, plain FP64 Jacobi-PCG (inner rtol 1e-8)",
+                   "tau_res": a.tau, "seed": 0},
         "reached_tau": bool(reached),
-        "value_note": ("seconds to relres <= tau" if reached else
-                       "relres tau not reached within the rank cap: seconds to the rank cap "
-                       "(relres at the cap in 'relres', full curve in 'relres_curve')"),
         "rank": ranks,
-        "relres": res["stats"]["relres"],
+        "relres": sig(res["stats"]["relres"]),
         "pcg_iters": res["stats"]["pcg_iters"],
-        "galerkin_iters": res["stats"]["galerkin_iters"],
-        "relres_curve": [[h["rank"], h["relres"], h["seconds"]] for h in hist],
-        "mixed": mixed,
-        "mixed_learned_pc": learned,
-        "shells": shells,
-        "op_apply": op,
-        "batch": batch,
         "roofline": roof,
-        "cpu_baseline": cpu,
+        "cpu_baseline": compact_cpu(cpu),
+        "summary": summarize(mixed, learned, shells, batch, op),
+        "detail_file": a.detail,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(line, separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":

@@ -109,6 +109,20 @@ cr_status cr_op_apply_f32(cr_problem* p, int64_t r, const float* U, int64_t ldu,
                           int64_t ldz, const float* V, int64_t ldv, float* F, int64_t ldf,
                           float* G, int64_t ldg);
 
+/* The same operator application returned as one factor pair (eq.
+ * multitermSylv with every term kept in low-rank form, L_x symmetric):
+ *   A(U Z V^T) = F G^T,  k = 3r + n_inj columns,
+ *   F [dev] n_y x k (ldf) = [ lambda U | 2 lambda L_y U | lambda L_y^2 U | Omega o (U Z H) ],
+ *   G [dev] n_x x k (ldg) = [ L_x^2 V Z^T | L_x V Z^T | V Z^T | X ],   H = V^T X,
+ * so the caller needs no lambda or Z arithmetic to use the result.  U, Z, V
+ * as for cr_op_apply; r = 0 gives F = [Omega o 0], G = [X].  FP64 on any
+ * handle.  Asynchronous; the handle's workspace may grow (allocation).
+ * Errors: CR_EINVAL (null pointers, negative r, leading dimensions below the
+ * row counts), CR_ENOMEM, CR_EHIP. */
+cr_status cr_op_apply_factors(cr_problem* p, int64_t r, const double* U, int64_t ldu,
+                              const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                              double* F, int64_t ldf, double* G, int64_t ldg);
+
 /* Solver options (Algorithm 1 and its sub-solvers).  Obtain defaults from
  * cr_solve_opts_default() and override fields. */
 typedef struct {
@@ -162,8 +176,10 @@ cr_status cr_galerkin_project(cr_problem* p, int64_t r, const double* U, int64_t
                               const double* V, int64_t ldv, double* Z_io, int64_t ldz,
                               double rtol, int32_t maxit, int32_t* iters_out);
 
-/* FP64 residual norm ||D - A(U Z V^T)||_F and its value relative to ||D||_F
- * (the outer stopping test), from the factored residual R = F_R G_R^T with
+/* FP64 residual norm ||D - A(U Z V^T)||_F and its value relative to ||D||_F,
+ * the residual that Algorithm 1 updates after each Galerkin step ("update
+ * residual"; the paper stops on delta W, this norm is the added relative-
+ * residual stopping test), from the factored residual R = F_R G_R^T with
  * F_R = [Omega o (Y - U Z H) | U | L_y U | L_y^2 U] and
  * G_R = [X | -lambda L_x^2 V Z^T | -2 lambda L_x V Z^T | -lambda V Z^T]
  * via ||R||_F^2 = trace((F_R^T F_R)(G_R^T G_R)).  The Gram form loses about

@@ -17,6 +17,7 @@ relative residual ||R_j||_F / ||D||_F <= tau_res.
 """
 from __future__ import annotations
 
+import time
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -80,6 +81,7 @@ def greedy_solve(P: Problem, opt: GreedyOptions) -> GreedyResult:
     tau = opt.tau_res if opt.tau_res > 0 else opt.tau_dW
     g_rtol = opt.galerkin_rtol if opt.galerkin_rtol is not None else max(tau, 1e-14) / 2
     res = GreedyResult(U, V, Z)
+    t_start = time.perf_counter()
     for j in range(opt.max_rank):
         v0 = init_v(P, F, G, j, opt.seed)
         a = als(P, F, G, v0, opt.als_delta, opt.als_max_sweeps, opt.als_fixed_sweeps,
@@ -102,7 +104,8 @@ def greedy_solve(P: Problem, opt: GreedyOptions) -> GreedyResult:
         rel = fro_factored(F, G) / dn
         res.history.append(dict(rank=j + 1, relres=rel, dW=dW, energy=energy(P, U, Z, V),
                                 sweeps=a.sweeps, als_delta=a.delta, galerkin_iters=git,
-                                unorm=a.unorm, vnorm=a.vnorm))
+                                unorm=a.unorm, vnorm=a.vnorm,
+                                seconds=time.perf_counter() - t_start))
         res.U, res.V, res.Z = U, V, Z
         if (opt.tau_res > 0 and rel <= opt.tau_res) or (opt.tau_dW > 0 and dW <= opt.tau_dW):
             break

@@ -7,10 +7,12 @@ torch tensor of shape (n, k) with strides (1, ld).  ``colmajor`` makes one.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import json
 import math
 import os
+import weakref
 from ctypes import POINTER, c_double, c_int32, c_int64, c_uint64, c_void_p
 
 import numpy as np
@@ -26,7 +28,7 @@ STATUS_NAMES = {0: "ok", -1: "einval", -2: "enomem", -3: "ehip", -4: "enonfinite
 PREC = {"fp64": 0, "mixed": 1}
 
 EXPORTS = ["cr_problem_create", "cr_problem_destroy", "cr_rhs_norm", "cr_op_apply",
-           "cr_op_apply_f32", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
+           "cr_op_apply_f32", "cr_op_apply_factors", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
            "cr_residual_norm", "cr_greedy_solve", "cr_last_error", "cr_version",
            "cr_u_system", "cr_u_solve", "cr_problem_set_pc", "cr_pc_create", "cr_pc_destroy",
            "cr_pc_num_params", "cr_pc_get_params", "cr_pc_set_params", "cr_pc_forward",
@@ -74,6 +76,21 @@ class SolveStats(ctypes.Structure):
 RANK_CB = ctypes.CFUNCTYPE(None, POINTER(RankInfo), c_void_p)
 
 _lib = None
+# every open Problem / Pc handle; closed by an exit hook registered when the
+# library is loaded (after torch's, so it runs before them: exit hooks run in
+# reverse order), so that no handle is destroyed from a finaliser while the
+# interpreter, torch or the HIP runtime are being torn down
+_live = weakref.WeakSet()
+
+
+def close_all():
+    """Destroy every open handle (networks after the problems that use them)."""
+    objs = list(_live)
+    for o in objs:
+        if isinstance(o, Problem):
+            o.close()
+    for o in objs:
+        o.close()
 
 
 def load(path: str = LIB_PATH):
@@ -93,6 +110,7 @@ def load(path: str = LIB_PATH):
     L.cr_op_apply.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, c_int64, P,
                               c_int64]
     L.cr_op_apply_f32.argtypes = L.cr_op_apply.argtypes
+    L.cr_op_apply_factors.argtypes = L.cr_op_apply.argtypes
     L.cr_solve_opts_default.argtypes = [POINTER(SolveOpts)]
     L.cr_solve_opts_default.restype = None
     L.cr_als_step.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, P,
@@ -135,6 +153,7 @@ def load(path: str = LIB_PATH):
                         "cr_version", "cr_pc_destroy", "cr_pc_num_params"):
             L[name].restype = ctypes.c_int
     _lib = L
+    atexit.register(close_all)
     return L
 
 
@@ -225,12 +244,21 @@ class Problem:
                                    c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.h = h
         self._dtype = torch.float64
+        _live.add(self)
 
     # -------------------------------------------------------------- helpers
     def close(self):
         if getattr(self, "h", None):
+            torch.cuda.synchronize(self.device)
             load().cr_problem_destroy(self.h)
             self.h = None
+        _live.discard(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:
@@ -262,6 +290,18 @@ class Problem:
         _check(fn(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1), _ptr(V), _ld(V),
                   _ptr(F), _ld(F), _ptr(G), _ld(G)))
         return F, G[:, : 2 * r]
+
+    def op_apply_factors(self, U, Z, V):
+        """Returns (F, G), n_y x k and n_x x k with k = 3r + n_inj and
+        F G^T = A(U Z V^T) (column-major FP64 device tensors)."""
+        r = int(U.shape[1])
+        U, Z, V = self._col(U), self._col(Z), self._col(V)
+        k = 3 * r + self.n_inj
+        F = empty_colmajor(self.n_y, k, self.device)
+        G = empty_colmajor(self.n_x, k, self.device)
+        _check(load().cr_op_apply_factors(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1),
+                                          _ptr(V), _ld(V), _ptr(F), _ld(F), _ptr(G), _ld(G)))
+        return F, G
 
     def als_step(self, U, Z, V, v0, **opts):
         r = int(U.shape[1])
@@ -405,11 +445,14 @@ class Pc:
                                    ctypes.byref(h)))
         self.h = h
         self.n = int(np.prod(self.dims))
+        _live.add(self)
 
     def close(self):
         if getattr(self, "h", None):
+            torch.cuda.synchronize(self.device)
             load().cr_pc_destroy(self.h)
             self.h = None
+        _live.discard(self)
 
     def __del__(self):
         try:

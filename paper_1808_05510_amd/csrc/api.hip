@@ -1679,6 +1679,91 @@ extern "C" cr_status cr_op_apply_f32(cr_problem* P, int64_t r, const float* U, i
   return op_apply_impl<float>(P, r, U, ldu, Z, ldz, V, ldv, F, ldf, G, ldg);
 }
 
+// out[:, c] = s * (M Z^T)[:, c] = s * sum_k M[:, k] Z[c, k] for c < r; with
+// Z == nullptr, out = s * M.  One thread per row, 32 output columns per
+// workgroup column, Z staged in LDS in chunks of 128 k (in place is allowed
+// only for Z == nullptr).
+__global__ __launch_bounds__(256) void k_tall_zt(int64_t n, int r, const double* __restrict__ M,
+                                                 int64_t ldm, const double* __restrict__ Z,
+                                                 int64_t ldz, double s, double* out, int64_t ldo) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c0 = blockIdx.y * 32;
+  const int nc = min(32, r - c0);
+  if (!Z) {
+    if (i < n)
+      for (int c = 0; c < nc; ++c) out[(int64_t)(c0 + c) * ldo + i] = s * M[(int64_t)(c0 + c) * ldm + i];
+    return;
+  }
+  __shared__ double zs[128][33];
+  double acc[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) acc[c] = 0.0;
+  for (int k0 = 0; k0 < r; k0 += 128) {
+    const int nk = min(128, r - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * 128; e += 256) {
+      const int c = e % 32, k = e / 32;
+      zs[k][c] = (c < nc && k < nk) ? Z[(int64_t)(k0 + k) * ldz + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    if (i < n)
+      for (int k = 0; k < nk; ++k) {
+        const double m = M[(int64_t)(k0 + k) * ldm + i];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc[c] += m * zs[k][c];
+      }
+  }
+  if (i < n)
+#pragma unroll
+    for (int c = 0; c < 32; ++c)
+      if (c < nc) out[(int64_t)(c0 + c) * ldo + i] = s * acc[c];
+}
+
+static cr_status tall_zt(int64_t n, int r, const double* M, int64_t ldm, const double* Z,
+                         int64_t ldz, double s, double* out, int64_t ldo, hipStream_t st) {
+  if (n == 0 || r == 0) return CR_OK;
+  hipLaunchKernelGGL(k_tall_zt, dim3(nblk(n), (unsigned)((r + 31) / 32)), dim3(256), 0, st, n, r,
+                     M, ldm, Z, ldz, s, out, ldo);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// A(U Z V^T) = F G^T with k = 3r + n_inj columns (eq. multitermSylv, each
+// term kept in factored form):
+//   F = [lam U | 2 lam L_y U | lam L_y^2 U | Omega o (U Z H)],
+//   G = [L_x^2 V Z^T | L_x V Z^T | V Z^T | X].
+// The operator's products come from op_apply_impl (written straight into F's
+// middle blocks); G's stencil blocks pass through workspace.
+extern "C" cr_status cr_op_apply_factors(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                         const double* Z, int64_t ldz, const double* V,
+                                         int64_t ldv, double* F, int64_t ldf, double* G,
+                                         int64_t ldg) {
+  if (!P || r < 0 || (r > 0 && (!U || !Z || !V)) || !F || !G) {
+    set_error("null argument or negative rank");
+    return CR_EINVAL;
+  }
+  const int64_t ny = P->ny, nx = P->nx;
+  if (ldf < ny || ldg < nx || (r > 0 && (ldu < ny || ldv < nx || ldz < r))) {
+    set_error("leading dimension too small");
+    return CR_EINVAL;
+  }
+  hipStream_t st = P->st;
+  const int rr = (int)r;
+  double* Gs = WS(double, "G_fac", nx * std::max<int64_t>(2 * r, 1));
+  CR_TRY(op_apply_impl<double>(P, r, U, ldu, Z, ldz, V, ldv, F + r * ldf, ldf, Gs, nx));
+  const double lam = P->lam;
+  if (r > 0) {
+    CR_TRY(tall_zt(ny, rr, U, ldu, nullptr, 0, lam, F, ldf, st));
+    CR_TRY(tall_zt(ny, rr, F + r * ldf, ldf, nullptr, 0, 2.0 * lam, F + r * ldf, ldf, st));
+    CR_TRY(tall_zt(ny, rr, F + 2 * r * ldf, ldf, nullptr, 0, lam, F + 2 * r * ldf, ldf, st));
+    CR_TRY(tall_zt(nx, rr, Gs + r * nx, nx, Z, ldz, 1.0, G, ldg, st));
+    CR_TRY(tall_zt(nx, rr, Gs, nx, Z, ldz, 1.0, G + r * ldg, ldg, st));
+    CR_TRY(tall_zt(nx, rr, V, ldv, Z, ldz, 1.0, G + 2 * r * ldg, ldg, st));
+  }
+  CR_TRY((convert2d<double, double>(nx, P->ninj, P->X64, nx, G + 3 * r * ldg, ldg, st)));
+  return CR_OK;
+}
+
 // ===================================================================== iterate setup
 // Bring an external iterate (double U, Z, V) into ctx: bases in T (copied when
 // T is float or the leading dimensions differ), core copied to ld r, derived

@@ -28,7 +28,7 @@ from oracle import greedy as ogreedy
 from oracle import metrics as omet
 from oracle import operator as oop
 from paper_1808_05510_amd import connreg, synth
-from tests.helpers import rand_orth, rel
+from tests.helpers import max_rel, rand_orth, rel
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -66,6 +66,38 @@ def test_op_apply_full_shells_r100(shells, fp32):
     assert rel(G[:, :r], f.LxV) < tol
     assert rel(G[:, r:], f.Lx2V) < tol
     assert rel(F[:, 2 * r:], f.M) < tol_m
+    # every element, relative to its block's largest entry
+    for a, b in ((F[:, :r], f.LyU), (F[:, r:2 * r], f.Ly2U), (G[:, :r], f.LxV),
+                 (G[:, r:], f.Lx2V)):
+        assert max_rel(a, b) < tol
+    assert max_rel(F[:, 2 * r:], f.M) < tol_m
+
+
+def test_op_apply_factors_full_shells_r100(shells):
+    """The factor pair F G^T = A(U Z V^T) at full size: sampled entries of
+    A(W) from the oracle's factors, and ||A(W)||_F by thin QR of both pairs."""
+    d, P = shells
+    r = 100
+    rng = np.random.default_rng(22)
+    U = rng.standard_normal((P.n_y, r))
+    V = rng.standard_normal((P.n_x, r))
+    Z = rng.standard_normal((r, r))
+    g = connreg.Problem(d, "fp64", DEV)
+    F, G = g.op_apply_factors(U, Z, V)
+    F, G = np_(F), np_(G)
+    g.close()
+    f = oop.op_apply(P, U, Z, V)
+    rows = rng.choice(P.n_y, 400, replace=False)
+    cols = rng.choice(P.n_x, 300, replace=False)
+    # oracle entries A(W)[i, k] of eq. multitermSylv, term by term
+    want = (P.lam * (U[rows] @ Z @ f.Lx2V[cols].T + 2.0 * f.LyU[rows] @ Z @ f.LxV[cols].T
+                     + f.Ly2U[rows] @ Z @ V[cols].T) + f.M[rows] @ P.X[cols].T)
+    got = F[rows] @ G[cols].T
+    assert max_rel(got, want) < 1e-12
+    Fo = np.hstack([P.lam * U, 2.0 * P.lam * f.LyU, P.lam * f.Ly2U, f.M])
+    Go = np.hstack([f.Lx2V @ Z.T, f.LxV @ Z.T, V @ Z.T, P.X])
+    n_or = omet.fro_factored(Fo, Go)
+    assert abs(omet.fro_factored(F, G) - n_or) <= 1e-11 * n_or
 
 
 @pytest.fixture(scope="module")

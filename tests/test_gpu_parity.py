@@ -21,7 +21,7 @@ from oracle import galerkin as ogal
 from oracle import greedy as ogreedy
 from oracle import metrics as omet
 from oracle import operator as oop
-from tests.helpers import rand_orth, rel
+from tests.helpers import max_rel, rand_orth, rel
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -110,6 +110,11 @@ def test_op_apply_fp64(case, r):
         assert rel(G[:, :r], f.LxV) < 1e-13
         assert rel(G[:, r:], f.Lx2V) < 1e-13
         assert rel(F[:, 2 * r:], f.M) < 1e-12
+        # element by element (relative to the block's largest entry)
+        for a, b in ((F[:, :r], f.LyU), (F[:, r:2 * r], f.Ly2U), (G[:, :r], f.LxV),
+                     (G[:, r:], f.Lx2V)):
+            assert max_rel(a, b) < 1e-13
+        assert max_rel(F[:, 2 * r:], f.M) < 1e-12
     else:
         assert np.abs(F).max() == 0.0
     if name == "tiny3d" and r:
@@ -118,6 +123,27 @@ def test_op_apply_fp64(case, r):
         A = (P.lam * (U @ Z @ G[:, r:].T + 2 * F[:, :r] @ Z @ G[:, :r].T + F[:, r:2 * r] @ Z @ V.T)
              + F[:, 2 * r:] @ P.X.T)
         assert rel(A, oop.apply_A(P, Wd)) < 1e-12
+
+
+@pytest.mark.parametrize("r", [0, 1, 7, 40, 100])
+def test_op_apply_factors(case, r):
+    """cr_op_apply_factors: F G^T is A(U Z V^T) with no lambda or Z
+    arithmetic left to the caller (k = 3r + n_inj columns)."""
+    name, d, P = case
+    r = min(r, P.n_x)
+    rng = np.random.default_rng(r + 31)
+    U = rng.standard_normal((P.n_y, r))
+    V = rng.standard_normal((P.n_x, r))
+    Z = rng.standard_normal((r, r))
+    g = connreg.Problem(d, "fp64", DEV)
+    F, G = g.op_apply_factors(U, Z, V)
+    F, G = np_(F), np_(G)
+    g.close()
+    k = 3 * r + P.n_inj
+    assert F.shape == (P.n_y, k) and G.shape == (P.n_x, k)
+    A = oop.apply_A(P, U @ Z @ V.T)
+    assert rel(F @ G.T, A) < 1e-12
+    assert max_rel(F @ G.T, A) < 1e-12
 
 
 # FP32 sweeps of 8 or more columns take the LDS-window stencil where the
