@@ -123,6 +123,21 @@ cr_status cr_op_apply_factors(cr_problem* p, int64_t r, const double* U, int64_t
                               const double* Z, int64_t ldz, const double* V, int64_t ldv,
                               double* F, int64_t ldf, double* G, int64_t ldg);
 
+/* cr_op_apply (FP64) for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, outputs and errors as cr_op_apply; the call
+ * itself allocates nothing.  Its workspace (T = Z H and the split-K
+ * partials of H = V^T X) is a static 16 MiB device array that each device
+ * holds for the life of the process, looked up when a handle is first
+ * created on that device.  Limits: r <= 256 and n_inj <= 256, else
+ * CR_EINVAL with a message.  Every call on one device uses the same array
+ * (no state carries over between calls: all of it is written before it is
+ * read), so calls that overlap on one device -- on two streams or two
+ * handles -- race; serialise them.  Asynchronous. */
+cr_status cr_op_apply_noalloc(cr_problem* p, int64_t r, const double* U, int64_t ldu,
+                              const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                              double* F, int64_t ldf, double* G, int64_t ldg);
+
 /* Solver options (Algorithm 1 and its sub-solvers).  Obtain defaults from
  * cr_solve_opts_default() and override fields. */
 typedef struct {

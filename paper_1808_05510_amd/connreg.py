@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "ok", -1: "einval", -2: "enomem", -3: "ehip", -4: "enonfinite
 PREC = {"fp64": 0, "mixed": 1}
 
 EXPORTS = ["cr_problem_create", "cr_problem_destroy", "cr_rhs_norm", "cr_op_apply",
-           "cr_op_apply_f32", "cr_op_apply_factors", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
+           "cr_op_apply_f32", "cr_op_apply_factors",
+           "cr_op_apply_noalloc", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
            "cr_residual_norm", "cr_greedy_solve", "cr_last_error", "cr_version",
            "cr_u_system", "cr_u_solve", "cr_problem_set_pc", "cr_pc_create", "cr_pc_destroy",
            "cr_pc_num_params", "cr_pc_get_params", "cr_pc_set_params", "cr_pc_forward",
@@ -111,6 +112,7 @@ def load(path: str = LIB_PATH):
                               c_int64]
     L.cr_op_apply_f32.argtypes = L.cr_op_apply.argtypes
     L.cr_op_apply_factors.argtypes = L.cr_op_apply.argtypes
+    L.cr_op_apply_noalloc.argtypes = L.cr_op_apply.argtypes
     L.cr_solve_opts_default.argtypes = [POINTER(SolveOpts)]
     L.cr_solve_opts_default.restype = None
     L.cr_als_step.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, P,
@@ -278,15 +280,23 @@ class Problem:
         return out.value
 
     # -------------------------------------------------------------- entry points
-    def op_apply(self, U, Z, V, fp32: bool = False):
+    def op_apply(self, U, Z, V, fp32: bool = False, out=None, noalloc: bool = False):
         """Returns (F, G) with F = [L_y U | L_y^2 U | Omega o (U Z H)] and
-        G = [L_x V | L_x^2 V] (column-major device tensors)."""
+        G = [L_x V | L_x^2 V] (column-major device tensors).  out: (F, G)
+        to write into; noalloc: the allocation-free entry point (FP64)."""
         dt = torch.float32 if fp32 else torch.float64
         r = int(U.shape[1])
         U, Z, V = self._col(U, dt), self._col(Z, dt), self._col(V, dt)
-        F = empty_colmajor(self.n_y, 2 * r + self.n_inj, self.device, dt)
-        G = empty_colmajor(self.n_x, max(2 * r, 1), self.device, dt)
-        fn = load().cr_op_apply_f32 if fp32 else load().cr_op_apply
+        if out is None:
+            F = empty_colmajor(self.n_y, 2 * r + self.n_inj, self.device, dt)
+            G = empty_colmajor(self.n_x, max(2 * r, 1), self.device, dt)
+        else:
+            F, G = out
+        if noalloc:
+            assert not fp32
+            fn = load().cr_op_apply_noalloc
+        else:
+            fn = load().cr_op_apply_f32 if fp32 else load().cr_op_apply
         _check(fn(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1), _ptr(V), _ld(V),
                   _ptr(F), _ld(F), _ptr(G), _ld(G)))
         return F, G[:, : 2 * r]

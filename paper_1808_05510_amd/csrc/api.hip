@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <string>
 #include <type_traits>
@@ -41,6 +42,7 @@ static bool poison_workspace() {
 }
 
 struct cr_problem {
+  int dev = -1;               // device the handle was created on
   hipStream_t st = nullptr;
   hipStream_t aux = nullptr;  // library-owned second stream (default priority) for fork/join
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -1414,10 +1416,14 @@ static cr_status dev_alloc(cr_problem* P, T** p, int64_t count) {
   return CR_OK;
 }
 
+static cr_status scratch_setup(int dev);
+
 static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* stream,
                              cr_problem* P) {
   P->st = (hipStream_t)stream;
   P->prec = prec;
+  CR_HIP(hipGetDevice(&P->dev));
+  CR_TRY(scratch_setup(P->dev));
   CR_HIP(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
   CR_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
   CR_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
@@ -1605,29 +1611,36 @@ extern "C" void cr_solve_opts_default(cr_solve_opts* o) {
 
 // ===================================================================== op_apply
 template <typename T>
-static cr_status op_apply_impl(cr_problem* P, int64_t r, const T* U, int64_t ldu, const T* Z,
-                               int64_t ldz, const T* V, int64_t ldv, T* F, int64_t ldf, T* G,
-                               int64_t ldg) {
+static cr_status op_apply_check(cr_problem* P, int64_t r, const T* U, int64_t ldu, const T* Z,
+                                int64_t ldz, const T* V, int64_t ldv, T* F, int64_t ldf, T* G,
+                                int64_t ldg) {
   if (!P || r < 0 || (r > 0 && (!U || !Z || !V)) || !F || (r > 0 && !G)) {
     set_error("null argument or negative rank");
     return CR_EINVAL;
   }
-  const int64_t ny = P->ny, nx = P->nx;
-  const int ninj = P->ninj;
-  if ((r > 0 && (ldu < ny || ldv < nx || ldz < r || ldg < nx)) || ldf < ny) {
+  if ((r > 0 && (ldu < P->ny || ldv < P->nx || ldz < r || ldg < P->nx)) || ldf < P->ny) {
     set_error("leading dimension too small");
     return CR_EINVAL;
   }
+  return CR_OK;
+}
+
+// The operator application on given workspace: Tm (r x n_inj, T = Z H), and
+// for r > ZH_RMAX also Ht (n_inj x r) and Zd (r x r); gpart holds up to cap
+// doubles of split-K partials of H = V^T X.
+template <typename T>
+static cr_status op_apply_run(cr_problem* P, int64_t r, const T* U, int64_t ldu, const T* Z,
+                              int64_t ldz, const T* V, int64_t ldv, T* F, int64_t ldf, T* G,
+                              int64_t ldg, double* Tm, double* Ht, double* Zd, double* gpart,
+                              int64_t cap) {
+  const int64_t ny = P->ny, nx = P->nx;
+  const int ninj = P->ninj;
   hipStream_t st = P->st;
   const int rr = (int)r;
-  // workspace first (allocation may synchronise), then fork: the data term
-  // (H^T = X^T V, T = Z H, the masked product, MFMA-heavy) runs on the
-  // auxiliary stream while the four stencil sweeps (gather-heavy) run on the
-  // caller's stream; the caller's stream then waits for both.
-  double* Tm = WS(double, "Tm_op", std::max<int64_t>(r, 1) * ninj);
-  double* Ht = WS(double, "Ht_op", (int64_t)ninj * std::max<int64_t>(r, 1));
-  double* Zd = WS(double, "Zd_op", std::max<int64_t>(r * r, 1));
-  double* gpart = WS(double, "gpart", gemm_part_cap(P));
+  // fork: the data term (H^T = X^T V, T = Z H, the masked product,
+  // MFMA-heavy) runs on the auxiliary stream while the four stencil sweeps
+  // (gather-heavy) run on the caller's stream; the caller's stream then waits
+  // for both.
   CR_HIP(hipEventRecord(P->ev_fork, st));
   CR_HIP(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
   auto data_term = [&]() -> cr_status {
@@ -1642,10 +1655,10 @@ static cr_status op_apply_impl(cr_problem* P, int64_t r, const T* U, int64_t ldu
         // H = V^T X (V as the left operand: each column of H contiguous in
         // the partials), then T = Z H in one kernel
         int ks = 0;
-        CR_TRY(gemm_tn<T>(nx, B, A, nullptr, nullptr, 0, Ht, rr, gpart, gemm_part_cap(P), as, &ks));
+        CR_TRY(gemm_tn<T>(nx, B, A, nullptr, nullptr, 0, Ht, rr, gpart, cap, as, &ks));
         CR_TRY(zh_from_partials<T>(ninj, rr, ks, gpart, Z, ldz, Tm, r, as));
       } else {
-        CR_TRY(gemm_tn<T>(nx, A, B, nullptr, nullptr, 0, Ht, ninj, gpart, gemm_part_cap(P), as));
+        CR_TRY(gemm_tn<T>(nx, A, B, nullptr, nullptr, 0, Ht, ninj, gpart, cap, as));
         CR_TRY((convert2d<double, T>(r, r, Z, ldz, Zd, r, as)));
         CR_TRY(small_gemm(rr, ninj, rr, Zd, r, false, Ht, ninj, true, 1.0, Tm, r, as));
       }
@@ -1665,6 +1678,74 @@ static cr_status op_apply_impl(cr_problem* P, int64_t r, const T* U, int64_t ldu
   CR_HIP(hipEventRecord(P->ev_join, P->aux));
   CR_HIP(hipStreamWaitEvent(st, P->ev_join, 0));
   return sd != CR_OK ? sd : ss;
+}
+
+template <typename T>
+static cr_status op_apply_impl(cr_problem* P, int64_t r, const T* U, int64_t ldu, const T* Z,
+                               int64_t ldz, const T* V, int64_t ldv, T* F, int64_t ldf, T* G,
+                               int64_t ldg) {
+  CR_TRY(op_apply_check<T>(P, r, U, ldu, Z, ldz, V, ldv, F, ldf, G, ldg));
+  const int ninj = P->ninj;
+  // workspace first (allocation may synchronise)
+  double* Tm = WS(double, "Tm_op", std::max<int64_t>(r, 1) * ninj);
+  double* Ht = WS(double, "Ht_op", (int64_t)ninj * std::max<int64_t>(r, 1));
+  double* Zd = WS(double, "Zd_op", std::max<int64_t>(r * r, 1));
+  double* gpart = WS(double, "gpart", gemm_part_cap(P));
+  return op_apply_run<T>(P, r, U, ldu, Z, ldz, V, ldv, F, ldf, G, ldg, Tm, Ht, Zd, gpart,
+                         gemm_part_cap(P));
+}
+
+// ------------------------------------------------- allocation-free operator application
+// cr_op_apply_noalloc keeps its workspace (T = Z H and the split-K partials
+// of H = V^T X) in this device array instead of handle workspace.  Each
+// device holds its own copy for the life of the process; its address on the
+// device is looked up once per device when a handle is created there
+// (hipGetSymbolAddress: the array's name in host code is not a device
+// address).  Calls that overlap on one device share it and race.
+constexpr int64_t NA_MAX_R = 256, NA_MAX_INJ = 256;
+constexpr int64_t NA_T_DOUBLES = NA_MAX_R * NA_MAX_INJ;  // T = Z H: 512 KiB
+constexpr int64_t NA_SCRATCH_DOUBLES = (int64_t)2 << 20;  // 16 MiB in all
+constexpr int NA_MAX_DEV = 64;
+static __device__ __align__(256) double scratch[NA_SCRATCH_DOUBLES];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[NA_MAX_DEV] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+static cr_status scratch_setup(int dev) {
+  if (dev < 0 || dev >= NA_MAX_DEV) {
+    set_error("device ordinal out of range for the scratch table");
+    return CR_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return CR_OK;
+  double* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    set_error(std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    return CR_EHIP;
+  }
+  g_scratch_ptr[dev] = p;
+  return CR_OK;
+}
+
+extern "C" cr_status cr_op_apply_noalloc(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                         const double* Z, int64_t ldz, const double* V,
+                                         int64_t ldv, double* F, int64_t ldf, double* G,
+                                         int64_t ldg) {
+  CR_TRY(op_apply_check<double>(P, r, U, ldu, Z, ldz, V, ldv, F, ldf, G, ldg));
+  if (r > NA_MAX_R || P->ninj > NA_MAX_INJ) {
+    set_error("cr_op_apply_noalloc: r = " + std::to_string(r) + ", n_inj = " +
+              std::to_string(P->ninj) + " beyond the static scratch limits (r <= " +
+              std::to_string(NA_MAX_R) + ", n_inj <= " + std::to_string(NA_MAX_INJ) + ")");
+    return CR_EINVAL;
+  }
+  double* base = (P->dev >= 0 && P->dev < NA_MAX_DEV) ? g_scratch_ptr[P->dev] : nullptr;
+  if (!base) {
+    set_error("cr_op_apply_noalloc: scratch address of the handle's device not set up");
+    return CR_EHIP;
+  }
+  return op_apply_run<double>(P, r, U, ldu, Z, ldz, V, ldv, F, ldf, G, ldg, base, nullptr, nullptr,
+                              base + NA_T_DOUBLES, NA_SCRATCH_DOUBLES - NA_T_DOUBLES);
 }
 
 extern "C" cr_status cr_op_apply(cr_problem* P, int64_t r, const double* U, int64_t ldu,
