@@ -229,33 +229,69 @@ def test_greedy_with_flexible_cg_keeps_the_answer(kind, source_box):
     pc.close()
 
 
-def test_trained_network_gain_over_jacobi(capsys):
-    """The network is trained on u-systems of random low-rank iterates and
-    evaluated on unseen ones: the flexible CG with the trained network needs
-    far fewer iterations than Jacobi-PCG for the same answer.  Iterations of
-    the base step alone are printed beside them (no claim on that ratio)."""
+def _trained_setup(rng_seed=31, steps=150):
     d = box(seed=7, by=(12, 10, 8), bx=(8, 6, 6), n_inj=6, lam=1e3)
     P = oop.problem_from_arrays(d)
     g = connreg.Problem(d, "fp64", DEV)
     g.set_box(d["box_y"])
-    rng = np.random.default_rng(31)
+    rng = np.random.default_rng(rng_seed)
     b, x, dd, cf = _pairs(g, P, rng, 24)
     pc = connreg.Pc(d["box_y"], channels=8, seed=1)
-    for s in range(150):
+    untrained = connreg.Pc(d["box_y"], channels=8, seed=1)
+    for s in range(steps):
         idx = rng.choice(24, size=8, replace=False)
         it = torch.tensor(idx, device=DEV)
-        pc.train_step(g, b[it], x[it], dd[it], cf[idx], lr=3e-3 * 0.1 ** (s / 150))
+        pc.train_step(g, b[it], x[it], dd[it], cf[idx], lr=3e-3 * 0.1 ** (s / steps))
     eb, ex, ed, ec = _pairs(g, P, np.random.default_rng(77), 6)
-    its = {"jacobi": [], "base": [], "learned": []}
-    for i in range(6):
-        for kind in its:
-            xs, n_it, rr, fb, st = g.u_solve(ed[i], tuple(ec[i]), eb[i], rtol=1e-9, maxit=20000,
-                                             pc=pc if kind == "learned" else None, precond=kind)
-            assert st in ("ok", "pc_fallback") and rr <= 1e-9
+    return g, pc, untrained, (eb, ex, ed, ec)
+
+
+def _solve_stats(g, pcs, ev, rtol=1e-9):
+    import time
+    eb, ex, ed, ec = ev
+    its = {k: [] for k in pcs}
+    secs = {k: [] for k in pcs}
+    for i in range(eb.shape[0]):
+        for kind, (pc, precond) in pcs.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xs, n_it, rr, fb, st = g.u_solve(ed[i], tuple(ec[i]), eb[i], rtol=rtol, maxit=20000,
+                                             pc=pc, precond=precond)
+            torch.cuda.synchronize()
+            secs[kind].append(time.perf_counter() - t0)
+            assert st in ("ok", "pc_fallback") and rr <= rtol
             assert rel(xs.cpu().numpy(), ex[i].cpu().numpy()) < 1e-6
             its[kind].append(n_it)
-    m = {k: float(np.mean(v)) for k, v in its.items()}
+    return ({k: float(np.mean(v)) for k, v in its.items()},
+            {k: float(np.median(v)) for k, v in secs.items()})
+
+
+def test_learned_flexible_cg_beats_jacobi_pcg(capsys):
+    """Flexible CG with the (trained) network on unseen u-systems needs far
+    fewer iterations than Jacobi-PCG for the same answer; iterations of the
+    base step alone are printed beside them."""
+    g, pc, untrained, ev = _trained_setup()
+    m, _ = _solve_stats(g, {"jacobi": (None, "jacobi"), "base": (None, "base"),
+                            "learned": (pc, "learned")}, ev)
     with capsys.disabled():
         print(f"\n[lpc] mean iterations on unseen u-systems: {m}")
     assert m["learned"] < 0.5 * m["jacobi"]
     pc.close()
+    untrained.close()
+
+
+@pytest.mark.xfail(reason="the trained network does not improve on its untrained start, the "
+                          "spectral base step (about 2 flexible-CG iterations already)",
+                   strict=False)
+def test_trained_network_beats_untrained(capsys):
+    """What training gains: the same network trained against untrained (its
+    zero last layer returns the base step alone) on unseen u-systems, in
+    flexible-CG iterations and in wall time."""
+    g, pc, untrained, ev = _trained_setup()
+    m, t = _solve_stats(g, {"untrained": (untrained, "learned"), "trained": (pc, "learned")}, ev)
+    with capsys.disabled():
+        print(f"\n[lpc] trained vs untrained: iterations {m}, median seconds {t}")
+    pc.close()
+    untrained.close()
+    assert m["trained"] < m["untrained"]
+    assert t["trained"] < t["untrained"]
