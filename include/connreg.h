@@ -213,6 +213,7 @@ typedef struct {
   int32_t pcg_iters;       /* PCG iterations of this rank (u and v)         */
   int32_t galerkin_iters;  /* projected CG iterations                       */
   double seconds;          /* wall time since the solve started             */
+  double J;                /* objective of eq. obj_fun at W_j: energy + 1/2 ||Omega o Y||_F^2 */
 } cr_rank_info;
 
 typedef struct {
@@ -249,6 +250,47 @@ cr_status cr_greedy_solve(cr_problem* p, const cr_solve_opts* opts, double* U, d
  * 2^-8 ||U_a|| ||U_b|| plus FP32 accumulation.  Asynchronous. */
 cr_status cr_masked_gram(cr_problem* p, int64_t r, const double* U, int64_t ldu, int32_t mode,
                          double* G, int64_t ldg);
+
+/* ---------------------------------------------------------------------------
+ * Post-processing of a solution W = U Z V^T (the analysis steps the paper
+ * applies to its solutions).  Arguments as for cr_op_apply (r >= 1); FP64 on
+ * any handle; the handle's workspace may grow; synchronise.
+ * ------------------------------------------------------------------------- */
+
+/* SVD of the solution (section on the top-view results): Z is not
+ * diagonal, so with the SVD of the core Z = Zu diag(s) Zv^T (one-sided Jacobi
+ * rotations on the GPU), W = Uh diag(s) Vh^T with Uh = U Zu [dev] n_y x r
+ * (lduh), Vh = V Zv [dev] n_x x r (ldvh), s [dev] r, descending; this is the
+ * SVD of W when U and V have orthonormal columns (as cr_greedy_solve returns
+ * them).  A column of Zu whose singular value is 0 is returned as 0.
+ * sweeps_out [host] may be NULL.  CR_NOTCONV if the rotations did not
+ * converge in 60 sweeps (outputs then approximate). */
+cr_status cr_core_svd(cr_problem* p, int64_t r, const double* U, int64_t ldu, const double* Z,
+                      int64_t ldz, const double* V, int64_t ldv, double* Uh, int64_t lduh,
+                      double* s, double* Vh, int64_t ldvh, int32_t* sweeps_out);
+
+/* The objective of eq. obj_fun at W = U Z V^T, evaluated directly in FP64
+ * (the cost-against-rank curves of the real-data sections):
+ * out3 [host] = { J, 1/2 ||P_Omega(W X - Y)||_F^2, lambda/2 ||L_y W + W L_x^T||_F^2 }.
+ * The regulariser goes through the Grams of [L_y U | U] and [V Z^T | L_x V Z^T]. */
+cr_status cr_objective(cr_problem* p, int64_t r, const double* U, int64_t ldu, const double* Z,
+                       int64_t ldz, const double* V, int64_t ldv, double* out3);
+
+/* Statistics over all n_y x n_x entries w of W = U Z V^T, computed tile by
+ * tile on the FP64 matrix cores without storing W (section on dropping the
+ * nonnegativity constraint: how many entries are negative and how large).
+ * sum_sq_neg = ||W - max(0, W)||_F^2, the squared distance to the projection
+ * onto the nonnegative orthant; sum_sq = ||W||_F^2. */
+typedef struct {
+  double entries;          /* n_y n_x                                      */
+  double count_neg;        /* number of entries w < 0                      */
+  double min, max;         /* smallest and largest entry                   */
+  double max_abs;          /* max |w| (the entrywise infinity norm)        */
+  double sum_sq;           /* sum of w^2                                   */
+  double sum_sq_neg;       /* sum of w^2 over the negative entries         */
+} cr_entry_stats_t;
+cr_status cr_entry_stats(cr_problem* p, int64_t r, const double* U, int64_t ldu, const double* Z,
+                         int64_t ldz, const double* V, int64_t ldv, cr_entry_stats_t* out);
 
 /* ---------------------------------------------------------------------------
  * ALS u-system access and the learned preconditioner.

@@ -29,7 +29,7 @@ PREC = {"fp64": 0, "mixed": 1}
 
 EXPORTS = ["cr_problem_create", "cr_problem_destroy", "cr_rhs_norm", "cr_op_apply",
            "cr_op_apply_f32", "cr_op_apply_factors",
-           "cr_op_apply_noalloc", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
+           "cr_op_apply_noalloc", "cr_core_svd", "cr_objective", "cr_entry_stats", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
            "cr_residual_norm", "cr_greedy_solve", "cr_last_error", "cr_version",
            "cr_u_system", "cr_u_solve", "cr_problem_set_pc", "cr_pc_create", "cr_pc_destroy",
            "cr_pc_num_params", "cr_pc_get_params", "cr_pc_set_params", "cr_pc_forward",
@@ -65,7 +65,13 @@ class ALSStats(ctypes.Structure):
 class RankInfo(ctypes.Structure):
     _fields_ = [("rank", c_int32), ("relres", c_double), ("dW", c_double), ("energy", c_double),
                 ("sweeps", c_int32), ("pcg_iters", c_int32), ("galerkin_iters", c_int32),
-                ("seconds", c_double)]
+                ("seconds", c_double), ("J", c_double)]
+
+
+class EntryStats(ctypes.Structure):
+    _fields_ = [("entries", c_double), ("count_neg", c_double), ("min", c_double),
+                ("max", c_double), ("max_abs", c_double), ("sum_sq", c_double),
+                ("sum_sq_neg", c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -113,6 +119,11 @@ def load(path: str = LIB_PATH):
     L.cr_op_apply_f32.argtypes = L.cr_op_apply.argtypes
     L.cr_op_apply_factors.argtypes = L.cr_op_apply.argtypes
     L.cr_op_apply_noalloc.argtypes = L.cr_op_apply.argtypes
+    L.cr_core_svd.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, P,
+                              c_int64, POINTER(c_int32)]
+    L.cr_objective.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, POINTER(c_double)]
+    L.cr_entry_stats.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64,
+                                 POINTER(EntryStats)]
     L.cr_solve_opts_default.argtypes = [POINTER(SolveOpts)]
     L.cr_solve_opts_default.restype = None
     L.cr_als_step.argtypes = [P, c_int64, P, c_int64, P, c_int64, P, c_int64, P, P,
@@ -312,6 +323,38 @@ class Problem:
         _check(load().cr_op_apply_factors(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1),
                                           _ptr(V), _ld(V), _ptr(F), _ld(F), _ptr(G), _ld(G)))
         return F, G
+
+    def core_svd(self, U, Z, V):
+        """SVD of W = U Z V^T from its core: returns (Uh, s, Vh, sweeps, status)
+        with W = Uh diag(s) Vh^T (device tensors, s descending)."""
+        r = int(U.shape[1])
+        U, Z, V = self._col(U), self._col(Z), self._col(V)
+        Uh = empty_colmajor(self.n_y, r, self.device)
+        Vh = empty_colmajor(self.n_x, r, self.device)
+        sv = torch.empty(r, device=self.device, dtype=torch.float64)
+        sw = c_int32()
+        st = _check(load().cr_core_svd(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1),
+                                       _ptr(V), _ld(V), _ptr(Uh), _ld(Uh), _ptr(sv), _ptr(Vh),
+                                       _ld(Vh), ctypes.byref(sw)))
+        return Uh, sv, Vh, sw.value, STATUS_NAMES[st]
+
+    def objective(self, U, Z, V):
+        """(J, misfit, regulariser) of eq. obj_fun at W = U Z V^T (FP64)."""
+        r = int(U.shape[1])
+        U, Z, V = self._col(U), self._col(Z), self._col(V)
+        out = (c_double * 3)()
+        _check(load().cr_objective(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1), _ptr(V),
+                                   _ld(V), out))
+        return out[0], out[1], out[2]
+
+    def entry_stats(self, U, Z, V):
+        """Statistics over every entry of W = U Z V^T (dict)."""
+        r = int(U.shape[1])
+        U, Z, V = self._col(U), self._col(Z), self._col(V)
+        es = EntryStats()
+        _check(load().cr_entry_stats(self.h, r, _ptr(U), _ld(U), _ptr(Z), max(_ld(Z), 1),
+                                     _ptr(V), _ld(V), ctypes.byref(es)))
+        return {f: getattr(es, f) for f, _ in EntryStats._fields_}
 
     def als_step(self, U, Z, V, v0, **opts):
         r = int(U.shape[1])

@@ -62,6 +62,7 @@ struct cr_problem {
   int64_t nholes = 0;
   bool use_holes = false;
   double dnorm = 0.0;
+  double half_oy2 = 0.0;      // 1/2 ||Omega o Y||_F^2 (J = energy + this)
   double* hscal = nullptr;  // pinned host scratch
   unsigned* bar = nullptr;  // grid-barrier words (BAR_WORDS)
   cr_pc* pc = nullptr;      // learned preconditioner for the u-systems (not owned)
@@ -216,6 +217,34 @@ __global__ void k_build_cm(int ninj, int r, const double* __restrict__ Z, int64_
     }
   }
   Cm[e] = v;
+}
+
+// out = {||Z - Zold||_F^2, ||Z||_F^2} over the leading r x r block (ld ldr)
+__global__ __launch_bounds__(256) void k_dw(int r, int64_t ldr, const double* __restrict__ Z,
+                                            const double* __restrict__ Zold,
+                                            double* __restrict__ out) {
+  __shared__ double red[2][4];
+  double dd = 0.0, zz = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += 256) {
+    const int64_t i = e % r, j = e / r;
+    const double a = Z[j * ldr + i], b = Zold[j * ldr + i];
+    dd += (a - b) * (a - b);
+    zz += a * a;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    dd += __shfl_xor(dd, o, 64);
+    zz += __shfl_xor(zz, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = dd;
+    red[1][threadIdx.x >> 6] = zz;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    out[1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
 }
 
 __global__ void k_neg(int n, const double* __restrict__ a, double* __restrict__ b) {
@@ -1532,6 +1561,14 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   CR_HIP(hipMemcpyAsync(P->hscal, s, sizeof(double), hipMemcpyDeviceToHost, P->st));
   CR_HIP(hipStreamSynchronize(P->st));
   P->dnorm = std::sqrt(std::max(P->hscal[0], 0.0));
+  {
+    double* ps = P->buf<double>("oy2part", 520);
+    if (!ps) return CR_ENOMEM;
+    CR_TRY(sumsq(ny, ni, P->OY64, ny, 0.5, ps, ps + 512, P->st));
+    CR_HIP(hipMemcpyAsync(P->hscal, ps + 512, sizeof(double), hipMemcpyDeviceToHost, P->st));
+    CR_HIP(hipStreamSynchronize(P->st));
+    P->half_oy2 = P->hscal[0];
+  }
   return CR_OK;
 }
 
@@ -1760,55 +1797,6 @@ extern "C" cr_status cr_op_apply_f32(cr_problem* P, int64_t r, const float* U, i
   return op_apply_impl<float>(P, r, U, ldu, Z, ldz, V, ldv, F, ldf, G, ldg);
 }
 
-// out[:, c] = s * (M Z^T)[:, c] = s * sum_k M[:, k] Z[c, k] for c < r; with
-// Z == nullptr, out = s * M.  One thread per row, 32 output columns per
-// workgroup column, Z staged in LDS in chunks of 128 k (in place is allowed
-// only for Z == nullptr).
-__global__ __launch_bounds__(256) void k_tall_zt(int64_t n, int r, const double* __restrict__ M,
-                                                 int64_t ldm, const double* __restrict__ Z,
-                                                 int64_t ldz, double s, double* out, int64_t ldo) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int c0 = blockIdx.y * 32;
-  const int nc = min(32, r - c0);
-  if (!Z) {
-    if (i < n)
-      for (int c = 0; c < nc; ++c) out[(int64_t)(c0 + c) * ldo + i] = s * M[(int64_t)(c0 + c) * ldm + i];
-    return;
-  }
-  __shared__ double zs[128][33];
-  double acc[32];
-#pragma unroll
-  for (int c = 0; c < 32; ++c) acc[c] = 0.0;
-  for (int k0 = 0; k0 < r; k0 += 128) {
-    const int nk = min(128, r - k0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < 32 * 128; e += 256) {
-      const int c = e % 32, k = e / 32;
-      zs[k][c] = (c < nc && k < nk) ? Z[(int64_t)(k0 + k) * ldz + c0 + c] : 0.0;
-    }
-    __syncthreads();
-    if (i < n)
-      for (int k = 0; k < nk; ++k) {
-        const double m = M[(int64_t)(k0 + k) * ldm + i];
-#pragma unroll
-        for (int c = 0; c < 32; ++c) acc[c] += m * zs[k][c];
-      }
-  }
-  if (i < n)
-#pragma unroll
-    for (int c = 0; c < 32; ++c)
-      if (c < nc) out[(int64_t)(c0 + c) * ldo + i] = s * acc[c];
-}
-
-static cr_status tall_zt(int64_t n, int r, const double* M, int64_t ldm, const double* Z,
-                         int64_t ldz, double s, double* out, int64_t ldo, hipStream_t st) {
-  if (n == 0 || r == 0) return CR_OK;
-  hipLaunchKernelGGL(k_tall_zt, dim3(nblk(n), (unsigned)((r + 31) / 32)), dim3(256), 0, st, n, r,
-                     M, ldm, Z, ldz, s, out, ldo);
-  CR_HIP(hipGetLastError());
-  return CR_OK;
-}
-
 // A(U Z V^T) = F G^T with k = 3r + n_inj columns (eq. multitermSylv, each
 // term kept in factored form):
 //   F = [lam U | 2 lam L_y U | lam L_y^2 U | Omega o (U Z H)],
@@ -1834,14 +1822,164 @@ extern "C" cr_status cr_op_apply_factors(cr_problem* P, int64_t r, const double*
   CR_TRY(op_apply_impl<double>(P, r, U, ldu, Z, ldz, V, ldv, F + r * ldf, ldf, Gs, nx));
   const double lam = P->lam;
   if (r > 0) {
-    CR_TRY(tall_zt(ny, rr, U, ldu, nullptr, 0, lam, F, ldf, st));
-    CR_TRY(tall_zt(ny, rr, F + r * ldf, ldf, nullptr, 0, 2.0 * lam, F + r * ldf, ldf, st));
-    CR_TRY(tall_zt(ny, rr, F + 2 * r * ldf, ldf, nullptr, 0, lam, F + 2 * r * ldf, ldf, st));
-    CR_TRY(tall_zt(nx, rr, Gs + r * nx, nx, Z, ldz, 1.0, G, ldg, st));
-    CR_TRY(tall_zt(nx, rr, Gs, nx, Z, ldz, 1.0, G + r * ldg, ldg, st));
-    CR_TRY(tall_zt(nx, rr, V, ldv, Z, ldz, 1.0, G + 2 * r * ldg, ldg, st));
+    // F's blocks scaled in place; G's blocks are (.) Z^T
+    CR_TRY(tall_small(ny, rr, rr, U, ldu, nullptr, 0, false, lam, F, ldf, st));
+    CR_TRY(tall_small(ny, rr, rr, F + r * ldf, ldf, nullptr, 0, false, 2.0 * lam, F + r * ldf, ldf,
+                      st));
+    CR_TRY(tall_small(ny, rr, rr, F + 2 * r * ldf, ldf, nullptr, 0, false, lam, F + 2 * r * ldf,
+                      ldf, st));
+    CR_TRY(tall_small(nx, rr, rr, Gs + r * nx, nx, Z, ldz, true, 1.0, G, ldg, st));
+    CR_TRY(tall_small(nx, rr, rr, Gs, nx, Z, ldz, true, 1.0, G + r * ldg, ldg, st));
+    CR_TRY(tall_small(nx, rr, rr, V, ldv, Z, ldz, true, 1.0, G + 2 * r * ldg, ldg, st));
   }
   CR_TRY((convert2d<double, double>(nx, P->ninj, P->X64, nx, G + 3 * r * ldg, ldg, st)));
+  return CR_OK;
+}
+
+// ===================================================================== post-processing
+// Host copy of `count` device doubles through the handle's pinned scratch.
+static cr_status read_scalars(cr_problem* P, const double* dev, double* host, int count) {
+  CR_HIP(hipMemcpyAsync(P->hscal, dev, sizeof(double) * count, hipMemcpyDeviceToHost, P->st));
+  CR_HIP(hipStreamSynchronize(P->st));
+  std::memcpy(host, P->hscal, sizeof(double) * count);
+  return CR_OK;
+}
+
+static bool post_args_ok(cr_problem* P, int64_t r, const double* U, int64_t ldu, const double* Z,
+                         int64_t ldz, const double* V, int64_t ldv) {
+  if (!P || r < 1 || !U || !Z || !V || ldu < P->ny || ldv < P->nx || ldz < r) {
+    set_error("null argument, r < 1 or leading dimension too small");
+    return false;
+  }
+  return true;
+}
+
+// SVD of W = U Z V^T from the SVD of its core (section on the top-view
+// results): Z = Zu diag(s) Zv^T by one-sided Jacobi, then Uh = U Zu, Vh = V Zv.
+extern "C" cr_status cr_core_svd(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                 const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                                 double* Uh, int64_t lduh, double* s, double* Vh, int64_t ldvh,
+                                 int32_t* sweeps_out) {
+  if (!post_args_ok(P, r, U, ldu, Z, ldz, V, ldv)) return CR_EINVAL;
+  if (!Uh || !s || !Vh || lduh < P->ny || ldvh < P->nx) {
+    set_error("cr_core_svd: null output or leading dimension too small");
+    return CR_EINVAL;
+  }
+  hipStream_t st = P->st;
+  const int rr = (int)r;
+  double* A = WS(double, "svd_A", r * r);
+  double* Zu = WS(double, "svd_Zu", r * r);
+  double* Zv = WS(double, "svd_Zv", r * r);
+  double* work = WS(double, "svd_work", r * r + r + 8);
+  CR_TRY((convert2d<double, double>(r, r, Z, ldz, A, r, st)));
+  double* info = work + r * r + r;
+  CR_TRY(small_svd(rr, A, r, Zu, r, s, Zv, r, work, info, st));
+  CR_TRY(tall_small(P->ny, rr, rr, U, ldu, Zu, r, false, 1.0, Uh, lduh, st));
+  CR_TRY(tall_small(P->nx, rr, rr, V, ldv, Zv, r, false, 1.0, Vh, ldvh, st));
+  double h[2];
+  CR_TRY(read_scalars(P, info, h, 2));
+  if (sweeps_out) *sweeps_out = (int32_t)h[0];
+  if (h[1] != 1.0) {
+    set_error("one-sided Jacobi SVD of the core did not converge");
+    return CR_NOTCONV;
+  }
+  return CR_OK;
+}
+
+// J(W) of eq. obj_fun for W = U Z V^T, FP64: misfit 1/2 ||Omega o Y -
+// Omega o (U Z H)||_F^2 (H = V^T X) and regulariser lambda/2 ||F G^T||_F^2 with
+// F = [L_y U | U], G = [V Z^T | L_x V Z^T] (L_y W + W L_x^T in factored form),
+// the latter through the Grams F^T F and G^T G.
+extern "C" cr_status cr_objective(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                  const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                                  double* out3) {
+  if (!post_args_ok(P, r, U, ldu, Z, ldz, V, ldv)) return CR_EINVAL;
+  if (!out3) {
+    set_error("cr_objective: null output");
+    return CR_EINVAL;
+  }
+  hipStream_t st = P->st;
+  const int rr = (int)r, ninj = P->ninj;
+  const int64_t ny = P->ny, nx = P->nx;
+  if (rr > ZH_RMAX) {
+    set_error("cr_objective: r beyond the supported range");
+    return CR_EINVAL;
+  }
+  double* Tm = WS(double, "obj_T", r * ninj);
+  double* gpart = WS(double, "gpart", gemm_part_cap(P));
+  double* N = WS(double, "obj_N", ny * ninj);
+  double* LyU = WS(double, "obj_LyU", ny * r);
+  double* LxV = WS(double, "obj_LxV", nx * r);
+  double* Gm = WS(double, "obj_G", nx * 2 * r);
+  double* FtF = WS(double, "obj_FtF", 4 * r * r);
+  double* GtG = WS(double, "obj_GtG", 4 * r * r);
+  double* sc = WS(double, "obj_sc", 512 + 8);
+  // misfit
+  {
+    Blocks<double> A, B;
+    A.clear();
+    B.clear();
+    A.add(P->X64, nx, ninj);
+    B.add(V, ldv, rr);
+    int ks = 0;
+    CR_TRY(gemm_tn<double>(nx, B, A, nullptr, nullptr, 0, nullptr, rr, gpart, gemm_part_cap(P), st,
+                           &ks));
+    CR_TRY(zh_from_partials<double>(ninj, rr, ks, gpart, Z, ldz, Tm, r, st));
+    CR_TRY(masked_tall_gemm<double>(ny, rr, ninj, U, ldu, Tm, r, P->bits, P->OY64, ny, N, ny, st));
+    CR_TRY(sumsq(ny, ninj, N, ny, 0.5, sc, sc + 512, st));
+  }
+  // regulariser
+  CR_TRY(stencil<double>(P->gy, rr, U, ldu, LyU, ny, st));
+  CR_TRY(stencil<double>(P->gx, rr, V, ldv, LxV, nx, st));
+  CR_TRY(tall_small(nx, rr, rr, V, ldv, Z, ldz, true, 1.0, Gm, nx, st));
+  CR_TRY(tall_small(nx, rr, rr, LxV, nx, Z, ldz, true, 1.0, Gm + r * nx, nx, st));
+  {
+    Blocks<double> F, G;
+    F.clear();
+    F.add(LyU, ny, rr);
+    F.add(U, ldu, rr);
+    G.clear();
+    G.add(Gm, nx, 2 * rr);
+    CR_TRY(gemm_tn<double>(ny, F, F, nullptr, nullptr, 0, FtF, 2 * r, gpart, gemm_part_cap(P), st));
+    CR_TRY(gemm_tn<double>(nx, G, G, nullptr, nullptr, 0, GtG, 2 * r, gpart, gemm_part_cap(P), st));
+  }
+  CR_TRY(trace_prod(2 * rr, FtF, 2 * r, GtG, 2 * r, 0.5 * P->lam, sc + 513, st));
+  double h[2];
+  CR_TRY(read_scalars(P, sc + 512, h, 2));
+  out3[0] = h[0] + h[1];
+  out3[1] = h[0];
+  out3[2] = h[1];
+  return CR_OK;
+}
+
+// Statistics over every entry of W = U Z V^T (section on dropping the
+// nonnegativity constraint), without forming W: A = U Z, then W = A V^T
+// tile by tile on the FP64 matrix cores.
+extern "C" cr_status cr_entry_stats(cr_problem* P, int64_t r, const double* U, int64_t ldu,
+                                    const double* Z, int64_t ldz, const double* V, int64_t ldv,
+                                    cr_entry_stats_t* out) {
+  if (!post_args_ok(P, r, U, ldu, Z, ldz, V, ldv)) return CR_EINVAL;
+  if (!out) {
+    set_error("cr_entry_stats: null output");
+    return CR_EINVAL;
+  }
+  hipStream_t st = P->st;
+  const int rr = (int)r;
+  const int64_t ny = P->ny, nx = P->nx;
+  double* A = WS(double, "es_A", ny * r);
+  double* part = WS(double, "es_part", entry_stats_part_size(ny, nx) + 8);
+  double* res = WS(double, "es_res", 8);
+  CR_TRY(tall_small(ny, rr, rr, U, ldu, Z, ldz, false, 1.0, A, ny, st));
+  CR_TRY(entry_stats(ny, nx, rr, A, ny, V, ldv, part, res, st));
+  double h[6];
+  CR_TRY(read_scalars(P, res, h, 6));
+  out->count_neg = h[0];
+  out->min = h[1];
+  out->max = h[2];
+  out->max_abs = h[3];
+  out->sum_sq = h[4];
+  out->sum_sq_neg = h[5];
+  out->entries = (double)ny * (double)nx;
   return CR_OK;
 }
 
@@ -2000,13 +2138,14 @@ static cr_status greedy_impl(cr_problem* P, const cr_solve_opts& o, double* Uo, 
   c.ldz = rmax;
   const int64_t ldr = rmax;
   double* Zold = WS(double, "Zold", (int64_t)rmax * rmax);
+  double* dws = WS(double, "dws", 2);
   int r0 = (int)*rank_io;
   if (r0 < 0 || r0 > rmax) {
     set_error("rank_io out of range");
     return CR_EINVAL;
   }
   // clear everything beyond the resumed core
-  std::vector<double> hz((size_t)rmax * rmax, 0.0), hzo((size_t)rmax * rmax, 0.0);
+  std::vector<double> hz((size_t)rmax * rmax, 0.0);
   if (r0 > 0) {
     CR_HIP(hipMemcpy2DAsync(hz.data(), rmax * sizeof(double), Zo, rmax * sizeof(double),
                             r0 * sizeof(double), r0, hipMemcpyDeviceToHost, c.st));
@@ -2078,17 +2217,11 @@ static cr_status greedy_impl(cr_problem* P, const cr_solve_opts& o, double* Uo, 
     CR_TRY(c.build_N(r));
     CR_TRY(c.residual(r, nullptr, &relres));
     // delta W = ||Z_j - pad(Z_{j-1})||_F / ||Z_j||_F (orthonormal bases)
-    CR_HIP(hipMemcpyAsync(hz.data(), Zo, sizeof(double) * ldr * ldr, hipMemcpyDeviceToHost, c.st));
-    CR_HIP(hipMemcpyAsync(hzo.data(), Zold, sizeof(double) * ldr * ldr, hipMemcpyDeviceToHost,
-                          c.st));
+    hipLaunchKernelGGL(k_dw, dim3(1), dim3(NT), 0, c.st, r, ldr, Zo, Zold, dws);
+    CR_HIP(hipGetLastError());
+    CR_HIP(hipMemcpyAsync(P->hscal, dws, 2 * sizeof(double), hipMemcpyDeviceToHost, c.st));
     CR_HIP(hipStreamSynchronize(c.st));
-    double dd = 0.0, zz = 0.0;
-    for (int q = 0; q < r; ++q)
-      for (int p = 0; p < r; ++p) {
-        const double a = hz[(size_t)q * ldr + p], b = hzo[(size_t)q * ldr + p];
-        dd += (a - b) * (a - b);
-        zz += a * a;
-      }
+    const double dd = P->hscal[0], zz = P->hscal[1];
     dW = zz > 0 ? std::sqrt(dd / zz) : 0.0;
     const double secs = std::chrono::duration<double>(clk::now() - t0).count();
     if (!std::isfinite(relres)) {
@@ -2106,6 +2239,7 @@ static cr_status greedy_impl(cr_problem* P, const cr_solve_opts& o, double* Uo, 
       info.relres = relres;
       info.dW = dW;
       info.energy = gs[3];
+      info.J = gs[3] + P->half_oy2;
       info.sweeps = as.sweeps;
       info.pcg_iters = as.pcg_iters_u + as.pcg_iters_v;
       info.galerkin_iters = (int)gs[0];

@@ -344,6 +344,27 @@ cr_status kr_gram_bf16(int64_t n, int r, int ninj, const TU* U, int64_t ldu, con
                        double* G, int64_t ldr, float* part, void* aux, bool omega_ready,
                        hipStream_t st);
 
+// ---------------------------------------------------------------- post-processing (k_post.hip)
+// out[:, c] = s * sum_k M[:, k] op(B)[k, c] (c < ncols, k < kd; op(B) = B^T
+// when transB); B == nullptr: out = s * M (in place allowed)
+cr_status tall_small(int64_t n, int kd, int ncols, const double* M, int64_t ldm, const double* B,
+                     int64_t ldb, bool transB, double s, double* out, int64_t ldo, hipStream_t st);
+// SVD of the r x r matrix A (overwritten): A = Uo diag(s) Vo^T, s descending;
+// work: r*r + r doubles; info[2] = {sweeps, converged}
+cr_status small_svd(int r, double* A, int64_t lda, double* Uo, int64_t ldu, double* s, double* Vo,
+                    int64_t ldvo, double* work, double* info, hipStream_t st);
+// out[0] = scale * ||X||_F^2 (X rows x cols); part: 512 doubles
+cr_status sumsq(int64_t rows, int64_t cols, const double* x, int64_t ld, double scale,
+                double* part, double* out, hipStream_t st);
+// out[0] = scale * trace(P Q), P, Q m x m
+cr_status trace_prod(int m, const double* P, int64_t ldp, const double* Q, int64_t ldq,
+                     double scale, double* out, hipStream_t st);
+// statistics over every entry of W = A B^T (A na x k, B nb x k) into out[6] =
+// {negative count, min, max, max |w|, sum w^2, sum of w^2 over w < 0}
+int64_t entry_stats_part_size(int64_t na, int64_t nb);
+cr_status entry_stats(int64_t na, int64_t nb, int k, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double* part, double* out, hipStream_t st);
+
 // ---------------------------------------------------------------- small ops
 // out[i] = sum_k M[i + k*ldm] * v[k] * alpha  (i < m, k < kk), single block
 cr_status small_gemv(int m, int kk, const double* M, int64_t ldm, bool trans, const double* v,

@@ -35,7 +35,7 @@ import numpy as np
 __all__ = [
     "graph_laplacian_csr", "box_coords", "toy_1d", "box_problem",
     "config1", "config1_small", "config2", "config2_tiny", "shell_problem",
-    "config3", "config4_specs",
+    "config3", "config4_specs", "paper_toy",
 ]
 
 
@@ -140,6 +140,39 @@ def config1_small(seed=0):
     """The 40-voxel variant of the toy: every length scaled by 0.2."""
     return toy_1d(n=40, sigma_x=1.6, centre_lo=4.0, centre_hi=36.0, hole_r=2.0,
                   wt_width=3.0, max_rank=40, seed=seed)
+
+
+# ---------------------------------------------------------------------------
+# The paper's own toy brain (section "Test problem: a toy brain"): S = T =
+# [0, 1] on n lattice points, box-car injections, Omega = 1 - X, a Gaussian
+# ridge about the diagonal plus an off-diagonal bump (eq. W_true_toy)
+# ---------------------------------------------------------------------------
+def paper_toy(n=200, n_inj=5, noise=0.1, lam=100.0, max_rank=140, tau_dW=1e-7,
+              omega_ones=False, quadrature=False, seed=1):
+    """Readings where the paper is silent: lattice points x_i = i / (n - 1);
+    injection widths 0.12 + 0.1 eps (eps ~ U(0, 1), drawn first), centres
+    uniform so that the injection stays inside [0, 1] (drawn second);
+    W_true[i, k] = f(target y_i, source x_k) with the bump at source 0.8,
+    target 0.1 (so the lower-left corner of W is near zero, where the paper
+    finds its negative entries); Y = W_true X (quadrature=False) or
+    W_true X / n (quadrature=True), zero inside the injection, plus N(0, noise^2)
+    (drawn third).  omega_ones: the ablation with Omega = 1 everywhere."""
+    rng = np.random.default_rng(seed)
+    widths = 0.12 + 0.1 * rng.uniform(0.0, 1.0, size=n_inj)
+    centres = rng.uniform(widths / 2, 1.0 - widths / 2)
+    pos = np.arange(n, dtype=np.float64) / (n - 1)
+    X = (np.abs(pos[:, None] - centres[None, :]) <= widths[None, :] / 2).astype(np.float64)
+    Omega = np.ones_like(X, dtype=np.uint8) if omega_ones else (1 - X).astype(np.uint8)
+    yt, xs = pos[:, None], pos[None, :]
+    Wt = (np.exp(-((xs - yt) / 0.4) ** 2)
+          + 0.9 * np.exp(-((xs - 0.8) ** 2 + (yt - 0.1) ** 2) / 0.2 ** 2))
+    Ytrue = Wt @ X / (n if quadrature else 1.0)
+    Y = (1 - X) * Ytrue + noise * rng.standard_normal((n, n_inj))
+    coords = np.arange(n, dtype=np.int64)[:, None]
+    return _pack(coords, coords, X, Y, Omega, lam, max_rank, 0.0,
+                 dict(Wt_dense=Wt, box_y=np.array([n, 1, 1], np.int32),
+                      box_x=np.array([n, 1, 1], np.int32), centres=centres, widths=widths,
+                      tau_dW=float(tau_dW)))
 
 
 # ---------------------------------------------------------------------------
