@@ -61,3 +61,22 @@ def test_entry_stats_brute_force():
     assert st["max_abs"] == pytest.approx(ma, rel=1e-14)
     assert st["sum_sq"] == pytest.approx(ss, rel=1e-13)
     assert st["sum_sq_neg"] == pytest.approx(ssn, rel=1e-13)
+
+
+def test_oracle_paper_toy_trends_and_mask_ablation():
+    """The oracle on the paper's toy brain: the distance to W_true falls
+    with the rank and levels off, and dropping the mask (Omega = 1) fits the
+    truth worse (section "Test problem: a toy brain"; values unpinned)."""
+    from oracle import greedy as ogreedy
+    kw = dict(u_method="dense", v_method="dense", galerkin="dense", tau_dW=1e-7)
+    d = synth.paper_toy()
+    Wt = d["Wt_dense"]
+    P = oop.problem_from_arrays(d)
+    err = {}
+    for r in (10, 30, 40):
+        res = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(max_rank=r, **kw))
+        err[r] = np.linalg.norm(res.U @ res.Z @ res.V.T - Wt) / np.linalg.norm(Wt)
+    assert err[40] < err[10] and abs(err[40] - err[30]) <= 0.1 * err[30]
+    P1 = oop.problem_from_arrays(synth.paper_toy(omega_ones=True))
+    res1 = ogreedy.greedy_solve(P1, ogreedy.GreedyOptions(max_rank=40, **kw))
+    assert np.linalg.norm(res1.U @ res1.Z @ res1.V.T - Wt) / np.linalg.norm(Wt) > err[40]
