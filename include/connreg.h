@@ -199,7 +199,15 @@ cr_status cr_galerkin_project(cr_problem* p, int64_t r, const double* U, int64_t
  * G_R = [X | -lambda L_x^2 V Z^T | -2 lambda L_x V Z^T | -lambda V Z^T]
  * via ||R||_F^2 = trace((F_R^T F_R)(G_R^T G_R)).  The Gram form loses about
  * half the digits: its absolute error is near sqrt(eps) ||F_R|| ||G_R||.
- * abs_out / rel_out [host].  Synchronises. */
+ * When that gives a relative residual below 1e-6 (and the factor width
+ * k = n_inj + 3r is at most 1024), the norm is recomputed from CholQR2
+ * factors F_R = Q_F R_F, G_R = Q_G R_G as ||R_F R_G^T||_F, whose error is
+ * near eps ||F_R|| ||G_R||; if the factors' columns are numerically
+ * dependent (a Cholesky pivot fails) the Gram value is kept.  The
+ * environment variable CONNREG_RESID_QR (read at handle creation) selects
+ * 0 = Gram form only, 1 = automatic (default), 2 = CholQR2 always.  The same
+ * evaluation is the greedy solve's relres, whose Grams are updated one basis
+ * column at a time.  abs_out / rel_out [host].  Synchronises. */
 cr_status cr_residual_norm(cr_problem* p, int64_t r, const double* U, int64_t ldu, const double* Z,
                            int64_t ldz, const double* V, int64_t ldv, double* abs_out,
                            double* rel_out);

@@ -63,6 +63,9 @@ struct cr_problem {
   bool use_holes = false;
   double dnorm = 0.0;
   double half_oy2 = 0.0;      // 1/2 ||Omega o Y||_F^2 (J = energy + this)
+  int resid_qr = 1;           // residual norm from CholQR2 factors: 0 never, 1 below
+                              // RESID_QR_SWITCH (Gram form above), 2 always
+                              // (CONNREG_RESID_QR)
   double* hscal = nullptr;  // pinned host scratch
   unsigned* bar = nullptr;  // grid-barrier words (BAR_WORDS)
   cr_pc* pc = nullptr;      // learned preconditioner for the u-systems (not owned)
@@ -131,6 +134,11 @@ const float* cr_problem::OY<float>() const { return OY32; }
     if (!p_) return CR_ENOMEM;                               \
     p_;                                                      \
   })
+
+// the residual norm switches from the Gram form to CholQR2 factors below
+// this relative residual; CholQR2 needs factor widths k = n_inj + 3r <= KMAX
+constexpr double RESID_QR_SWITCH = 1e-6;
+constexpr int RESID_QR_KMAX = 1024;
 
 static int64_t gemm_part_cap(const cr_problem* P) {
   (void)P;
@@ -1248,6 +1256,120 @@ struct Ctx {
   }
 
   // ------------------------------------------------------------ residual norm
+  // Grams of the residual factors F = [N | U | L_y U | L_y^2 U] and
+  // G = [X | L_x^2 V | L_x V | V] (R = F Cm G^T), kept in the capacity layout
+  // (block b >= 1 at ninj + (b - 1) rmax).  In the greedy loop, where every
+  // rank appends one basis column, only the new rows and columns and the
+  // N-rows (N changes with Z) are computed: n_y (n_inj k + 9r) + 3 n_x k
+  // multiply-adds per rank instead of n_y k^2 + n_x k^2.
+  double *GFcap = nullptr, *GXcap = nullptr;
+  int gram_r = -1;        // rank the capacity Grams hold (-1: none)
+  bool gram_inc = false;  // incremental updates allowed (the greedy loop)
+
+  cr_status residual_grams(int r, double* GF, double* GX) {
+    const int k = ninj + 3 * r;
+    const int rc = std::max(rmax, 1);
+    const int64_t K = ninj + 3 * (int64_t)rc;
+    GFcap = WS(double, "resGFcap", K * K);
+    GXcap = WS(double, "resGXcap", K * K);
+    double* C = WS(double, "resC", (int64_t)k * std::max(k, 3));
+    Blocks<T> Fall, Gall;
+    Fall.clear();
+    Fall.add(N, ny, ninj);
+    Fall.add(U, ldu, r);
+    Fall.add(LU, ny, r);
+    Fall.add(L2U, ny, r);
+    Gall.clear();
+    Gall.add(X(), nx, ninj);
+    Gall.add(L2V, nx, r);
+    Gall.add(LV, nx, r);
+    Gall.add(V, ldv, r);
+    const int64_t cap = gemm_part_cap(P);
+    if (!(gram_inc && r >= 1 && gram_r == r - 1)) {
+      CR_TRY(gemm_tn<T>(ny, Fall, Fall, nullptr, nullptr, 0, C, k, gpart, cap, st));
+      CR_TRY(gram_scatter(k, k, C, k, 0, 0, -1, ninj, r, rc, GFcap, K, st));
+      CR_TRY(gemm_tn<T>(nx, Gall, Gall, nullptr, nullptr, 0, C, k, gpart, cap, st));
+      CR_TRY(gram_scatter(k, k, C, k, 0, 0, -1, ninj, r, rc, GXcap, K, st));
+    } else {
+      const int j = r - 1;
+      Blocks<T> Fu, Fn, Nb, Gn;
+      Fu.clear();
+      Fu.add(U, ldu, r);
+      Fu.add(LU, ny, r);
+      Fu.add(L2U, ny, r);
+      Fn.clear();
+      Fn.add(U + (int64_t)j * ldu, ldu, 1);
+      Fn.add(LU + (int64_t)j * ny, ny, 1);
+      Fn.add(L2U + (int64_t)j * ny, ny, 1);
+      CR_TRY(gemm_tn<T>(ny, Fu, Fn, nullptr, nullptr, 0, C, 3 * r, gpart, cap, st));
+      CR_TRY(gram_scatter(3 * r, 3, C, 3 * r, ninj, 0, j, ninj, r, rc, GFcap, K, st));
+      Nb.clear();
+      Nb.add(N, ny, ninj);
+      CR_TRY(gemm_tn<T>(ny, Nb, Fall, nullptr, nullptr, 0, C, ninj, gpart, cap, st));
+      CR_TRY(gram_scatter(ninj, k, C, ninj, 0, 0, -1, ninj, r, rc, GFcap, K, st));
+      Gn.clear();
+      Gn.add(L2V + (int64_t)j * nx, nx, 1);
+      Gn.add(LV + (int64_t)j * nx, nx, 1);
+      Gn.add(V + (int64_t)j * ldv, ldv, 1);
+      CR_TRY(gemm_tn<T>(nx, Gall, Gn, nullptr, nullptr, 0, C, k, gpart, cap, st));
+      CR_TRY(gram_scatter(k, 3, C, k, 0, 0, j, ninj, r, rc, GXcap, K, st));
+    }
+    gram_r = r;
+    CR_TRY(gram_gather(k, ninj, r, rc, GFcap, K, GF, st));
+    CR_TRY(gram_gather(k, ninj, r, rc, GXcap, K, GX, st));
+    return CR_OK;
+  }
+
+  // Upper factor R of a tall factor Fb (columns in blocks) from its Gram Gr
+  // (k x k, preserved) by CholQR2 with column scaling: Gr = S^-1 A1 S^-1,
+  // A1 = L1 L1^T, Q1 = Fb S L1^-T, Q1^T Q1 = L2 L2^T, R = L2^T L1^T S^-1.
+  // ok = false when a Cholesky pivot fails (columns too close to dependent).
+  cr_status cholqr2_r(int64_t n, const Blocks<T>& Fb, const double* Gr, int k, const char* tag,
+                      double* R, bool& ok) {
+    ok = false;
+    const int64_t kk = (int64_t)k * k;
+    const std::string t(tag);
+    double* A1 = WS(double, "qrA1" + t, kk);
+    double* A2 = WS(double, "qrA2" + t, kk);
+    double* W1 = WS(double, "qrW1" + t, kk);
+    double* W2 = WS(double, "qrW2" + t, kk);
+    double* sv = WS(double, "qrs" + t, 2 * k + 8);
+    double* info = sv + 2 * k;
+    double* ones = sv + k;
+    double* Fc = WS(double, "qrFc", n * k);
+    double* Q = WS(double, "qrQ", n * k);
+    CR_TRY((convert2d<double, double>(k, k, Gr, k, A1, k, st)));
+    CR_TRY(diag_scale(k, A1, k, sv, st));
+    CR_TRY(chol_lower(k, A1, k, info, st));
+    double h;
+    CR_TRY(read_scalars(info, 1, &h));
+    if (h != 0.0) return CR_OK;
+    // Fc = the factor in FP64, then Q = Fc (L1^-1 diag(s))^T
+    int off = 0;
+    for (int b = 0; b < Fb.nb; ++b) {
+      const int nc = Fb.col0[b + 1] - Fb.col0[b];
+      CR_TRY((convert2d<double, T>(n, nc, Fb.p[b], Fb.ld[b], Fc + (int64_t)off * n, n, st)));
+      off += nc;
+    }
+    CR_TRY(trinv_lower(k, A1, k, W1, k, st));
+    CR_TRY(tri_scale(k, 0, W1, k, sv, W2, k, st));
+    CR_TRY(tall_small(n, k, k, Fc, n, W2, k, true, 1.0, Q, n, st));
+    Blocks<double> Qb;
+    Qb.clear();
+    Qb.add(Q, n, k);
+    CR_TRY(gemm_tn<double>(n, Qb, Qb, nullptr, nullptr, 0, A2, k, gpart, gemm_part_cap(P), st));
+    CR_TRY(chol_lower(k, A2, k, info, st));
+    CR_TRY(read_scalars(info, 1, &h));
+    if (h != 0.0) return CR_OK;
+    hipLaunchKernelGGL(k_fill, dim3(nblk(k)), dim3(256), 0, st, (int64_t)k, 1.0, ones);
+    CR_HIP(hipGetLastError());
+    CR_TRY(tri_scale(k, 1, A2, k, ones, W1, k, st));  // L2^T
+    CR_TRY(tri_scale(k, 1, A1, k, sv, W2, k, st));    // L1^T S^-1
+    CR_TRY(small_gemm(k, k, k, W1, k, false, W2, k, false, 1.0, R, k, st));
+    ok = true;
+    return CR_OK;
+  }
+
   cr_status residual(int r, double* abs_out, double* rel_out) {
     const int k = ninj + 3 * r;
     const int64_t k2 = (int64_t)k * k;
@@ -1255,38 +1377,61 @@ struct Ctx {
     double* GX = WS(double, "resGX", k2);
     double* Cm = WS(double, "resCm", k2);
     double* M1 = WS(double, "resM1", k2);
-    Blocks<T> F;
-    F.clear();
-    F.add(N, ny, ninj);
-    F.add(U, ldu, r);
-    F.add(LU, ny, r);
-    F.add(L2U, ny, r);
-    CR_TRY(gemm_tn<T>(ny, F, F, nullptr, nullptr, 0, GF, k, gpart, gemm_part_cap(P), st));
-    Blocks<T> Gx;
-    Gx.clear();
-    Gx.add(X(), nx, ninj);
-    Gx.add(L2V, nx, r);
-    Gx.add(LV, nx, r);
-    Gx.add(V, ldv, r);
-    CR_TRY(gemm_tn<T>(nx, Gx, Gx, nullptr, nullptr, 0, GX, k, gpart, gemm_part_cap(P), st));
+    double* M2 = WS(double, "resM2", k2);
+    CR_TRY(residual_grams(r, GF, GX));
     hipLaunchKernelGGL(k_build_cm, dim3(nblk(k2)), dim3(256), 0, st, ninj, r, Z, ldz, lam, Cm);
     CR_HIP(hipGetLastError());
-    // M1 = GX Cm ; Cm <- Cm^T M1 is stored in GX (no longer needed)
+    // ||R||^2 = trace(GF Cm^T GX Cm) = sum_ij GF_ij (Cm^T GX Cm)_ij
     CR_TRY(small_gemm(k, k, k, GX, k, false, Cm, k, false, 1.0, M1, k, st));
-    CR_TRY(small_gemm(k, k, k, Cm, k, true, M1, k, false, 1.0, GX, k, st));
-    // ||R||^2 = sum_ij GF_ij GX_ij
+    CR_TRY(small_gemm(k, k, k, Cm, k, true, M1, k, false, 1.0, M2, k, st));
     Blocks<double> A;
     A.clear();
     A.add(GF, k2, 1);
     double* part64 = (double*)part;
-    CR_TRY(gemv_t<double>(k2, A, GX, tmp + 6, part64, st));
+    CR_TRY(gemv_t<double>(k2, A, M2, tmp + 6, part64, st));
     double h;
     CR_TRY(read_scalars(tmp + 6, 1, &h));
-    const double nr = std::sqrt(std::max(h, 0.0));
+    double nr = std::sqrt(std::max(h, 0.0));
+    // Below a relative residual of about 1e-6 the Gram form's cancellation
+    // (absolute error near sqrt(eps) ||F|| ||G||) dominates: recompute from
+    // the CholQR2 factors, ||R||_F = ||R_F Cm^T R_G^T||_F (error near
+    // eps ||F|| ||G||)
+    const double rel = P->dnorm > 0 ? nr / P->dnorm : nr;
+    last_resid_qr = false;
+    if (P->resid_qr == 2 || (P->resid_qr == 1 && rel < RESID_QR_SWITCH)) {
+      if (k <= RESID_QR_KMAX) {
+        Blocks<T> Fall, Gall;
+        Fall.clear();
+        Fall.add(N, ny, ninj);
+        Fall.add(U, ldu, r);
+        Fall.add(LU, ny, r);
+        Fall.add(L2U, ny, r);
+        Gall.clear();
+        Gall.add(X(), nx, ninj);
+        Gall.add(L2V, nx, r);
+        Gall.add(LV, nx, r);
+        Gall.add(V, ldv, r);
+        double* RF = WS(double, "qrRF", k2);
+        double* RG = WS(double, "qrRG", k2);
+        bool okf = false, okg = false;
+        CR_TRY(cholqr2_r(ny, Fall, GF, k, "F", RF, okf));
+        if (okf) CR_TRY(cholqr2_r(nx, Gall, GX, k, "G", RG, okg));
+        if (okf && okg) {
+          // R = F Cm^T G^T (G_R = G Cm), so ||R||_F = ||R_F Cm^T R_G^T||_F
+          CR_TRY(small_gemm(k, k, k, Cm, k, true, RG, k, true, 1.0, M1, k, st));
+          CR_TRY(small_gemm(k, k, k, RF, k, false, M1, k, false, 1.0, M2, k, st));
+          CR_TRY(sumsq(k, k, M2, k, 1.0, part64, tmp + 7, st));
+          CR_TRY(read_scalars(tmp + 7, 1, &h));
+          nr = std::sqrt(std::max(h, 0.0));
+          last_resid_qr = true;
+        }
+      }
+    }
     if (abs_out) *abs_out = nr;
     if (rel_out) *rel_out = P->dnorm > 0 ? nr / P->dnorm : nr;
     return CR_OK;
   }
+  bool last_resid_qr = false;
 };
 
 // ===================================================================== create / destroy
@@ -1461,6 +1606,7 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   if (const char* e = std::getenv("CONNREG_PCG_XREG")) P->no_xreg = std::atoi(e) == 0;
   if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
   if (const char* e = std::getenv("CONNREG_PCG_WARM")) P->pcg_warm = std::atoi(e) != 0;
+  if (const char* e = std::getenv("CONNREG_RESID_QR")) P->resid_qr = std::max(0, std::min(2, std::atoi(e)));
   P->ny = d->Ly.n;
   P->nx = d->Lx.n;
   P->ninj = (int)d->n_inj;
@@ -2122,6 +2268,7 @@ static cr_status greedy_impl(cr_problem* P, const cr_solve_opts& o, double* Uo, 
   const int rmax = o.max_rank;
   const int64_t ny = P->ny, nx = P->nx;
   Ctx<T> c(P);
+  c.gram_inc = true;  // one basis column per rank: residual Grams updated incrementally
   CR_TRY(c.alloc_rank(rmax));
   CR_TRY(c.alloc_vectors(o.pcg_vpt));
   // bases: the caller's buffers directly in FP64, internal copies otherwise

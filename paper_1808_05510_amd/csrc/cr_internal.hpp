@@ -365,6 +365,20 @@ int64_t entry_stats_part_size(int64_t na, int64_t nb);
 cr_status entry_stats(int64_t na, int64_t nb, int k, const double* A, int64_t lda,
                       const double* B, int64_t ldb, double* part, double* out, hipStream_t st);
 
+// residual Grams in the capacity layout (block b >= 1 at ninj + (b-1) rmax)
+cr_status gram_scatter(int m, int n, const double* C, int64_t ldc, int row0, int col0, int newcol,
+                       int ninj, int r, int rmax, double* Gc, int64_t ldg, hipStream_t st);
+cr_status gram_gather(int k, int ninj, int r, int rmax, const double* Gc, int64_t ldg, double* out,
+                      hipStream_t st);
+// CholQR2 pieces: symmetric diagonal scaling to unit diagonal (s = 1/sqrt(diag));
+// in-place lower Cholesky (info[0] = 0 or failing pivot + 1); lower inverse;
+// tri_scale mode 0: out = X diag(s), mode 1: out = L^T diag(1/s)
+cr_status diag_scale(int k, double* A, int64_t lda, double* s, hipStream_t st);
+cr_status chol_lower(int k, double* A, int64_t lda, double* info, hipStream_t st);
+cr_status trinv_lower(int k, const double* L, int64_t ldl, double* X, int64_t ldx, hipStream_t st);
+cr_status tri_scale(int k, int mode, const double* X, int64_t ldx, const double* s, double* out,
+                    int64_t ldo, hipStream_t st);
+
 // ---------------------------------------------------------------- small ops
 // out[i] = sum_k M[i + k*ldm] * v[k] * alpha  (i < m, k < kk), single block
 cr_status small_gemv(int m, int kk, const double* M, int64_t ldm, bool trans, const double* v,

@@ -472,3 +472,193 @@ cr_status entry_stats(int64_t na, int64_t nb, int k, const double* A, int64_t ld
 }
 
 }  // namespace cr
+
+namespace cr {
+
+// ============================================================== residual Grams in a capacity layout
+// The Grams of the residual factors F = [N | U | L_y U | L_y^2 U] and
+// G = [X | L_x^2 V | L_x V | V] keep block b (b = 0: n_inj columns, b = 1..3:
+// r columns each) at a fixed offset ninj + (b - 1) rmax, so a new basis
+// column only adds rows and columns instead of shifting the others.
+__device__ __forceinline__ int cap_index(int c, int ninj, int r, int rmax) {
+  if (c < ninj) return c;
+  const int b = (c - ninj) / r, o = (c - ninj) % r;
+  return ninj + b * rmax + o;
+}
+
+// C (m x n, ldc): row i is compact index row0 + i; column jj is compact
+// index col0 + jj (newcol < 0), or the new column `newcol` of block jj + 1
+// (newcol >= 0, n = 3).  Writes both (row, col) and (col, row) of Gc.
+__global__ __launch_bounds__(NT) void k_gram_scatter(int m, int n, const double* __restrict__ C,
+                                                     int64_t ldc, int row0, int col0, int newcol,
+                                                     int ninj, int r, int rmax,
+                                                     double* __restrict__ Gc, int64_t ldg) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)m * n) return;
+  const int i = (int)(e % m), jj = (int)(e / m);
+  const int ci = cap_index(row0 + i, ninj, r, rmax);
+  const int cj = newcol >= 0 ? ninj + jj * rmax + newcol : cap_index(col0 + jj, ninj, r, rmax);
+  const double v = C[(int64_t)jj * ldc + i];
+  Gc[(int64_t)cj * ldg + ci] = v;
+  Gc[(int64_t)ci * ldg + cj] = v;
+}
+
+// out (k x k compact, ld k) = Gc at the capacity positions
+__global__ __launch_bounds__(NT) void k_gram_gather(int k, int ninj, int r, int rmax,
+                                                    const double* __restrict__ Gc, int64_t ldg,
+                                                    double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)k * k) return;
+  const int i = (int)(e % k), j = (int)(e / k);
+  out[e] = Gc[(int64_t)cap_index(j, ninj, r, rmax) * ldg + cap_index(i, ninj, r, rmax)];
+}
+
+cr_status gram_scatter(int m, int n, const double* C, int64_t ldc, int row0, int col0, int newcol,
+                       int ninj, int r, int rmax, double* Gc, int64_t ldg, hipStream_t st) {
+  const int64_t mn = (int64_t)m * n;
+  if (mn == 0) return CR_OK;
+  hipLaunchKernelGGL(k_gram_scatter, dim3((unsigned)((mn + NT - 1) / NT)), dim3(NT), 0, st, m, n,
+                     C, ldc, row0, col0, newcol, ninj, r, rmax, Gc, ldg);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+cr_status gram_gather(int k, int ninj, int r, int rmax, const double* Gc, int64_t ldg, double* out,
+                      hipStream_t st) {
+  const int64_t kk = (int64_t)k * k;
+  hipLaunchKernelGGL(k_gram_gather, dim3((unsigned)((kk + NT - 1) / NT)), dim3(NT), 0, st, k, ninj,
+                     r, rmax, Gc, ldg, out);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+// ============================================================== CholQR2 pieces
+// s[i] = 1 / sqrt(A_ii) (0 for a zero column)
+__global__ __launch_bounds__(NT) void k_diag_rsqrt(int k, const double* __restrict__ A, int64_t lda,
+                                                   double* __restrict__ s) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= k) return;
+  const double d = A[(int64_t)i * lda + i];
+  s[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+}
+
+// A <- diag(s) A diag(s); the diagonal entry of a zero column becomes 1 so
+// that the Cholesky factor exists (s computed beforehand: no entry of A is
+// read after another thread may have rescaled it)
+__global__ __launch_bounds__(NT) void k_diag_apply(int k, double* __restrict__ A, int64_t lda,
+                                                   const double* __restrict__ s) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)k * k) return;
+  const int i = (int)(e % k), j = (int)(e / k);
+  double* a = A + (int64_t)j * lda + i;
+  *a = (i == j && s[i] == 0.0) ? 1.0 : *a * s[i] * s[j];
+}
+
+// In-place Cholesky A = L L^T (lower triangle of A, k <= a few thousand),
+// right-looking, one workgroup; info[0] = 0 on success, j + 1 when pivot j
+// is not positive.
+constexpr int CH_NT = 1024;
+__global__ __launch_bounds__(CH_NT) void k_chol(int k, double* __restrict__ A, int64_t lda,
+                                                double* __restrict__ info) {
+  __shared__ double dj;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      const double p = A[(int64_t)j * lda + j];
+      bad = !(p > 0.0) || !isfinite(p);
+      dj = bad ? 1.0 : sqrt(p);
+      A[(int64_t)j * lda + j] = dj;
+    }
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) info[0] = (double)(j + 1);
+      return;
+    }
+    const double inv = 1.0 / dj;
+    for (int i = j + 1 + tid; i < k; i += CH_NT) A[(int64_t)j * lda + i] *= inv;
+    __syncthreads();
+    // trailing lower triangle: A[i, l] -= A[i, j] A[l, j], j < l <= i
+    const int m = k - j - 1;
+    const int64_t tri = (int64_t)m * (m + 1) / 2;
+    for (int64_t e = tid; e < tri; e += CH_NT) {
+      int row = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+      while ((int64_t)row * (row + 1) / 2 > e) --row;
+      while ((int64_t)(row + 1) * (row + 2) / 2 <= e) ++row;
+      const int col = (int)(e - (int64_t)row * (row + 1) / 2);
+      const int i = j + 1 + row, l = j + 1 + col;
+      A[(int64_t)l * lda + i] -= A[(int64_t)j * lda + i] * A[(int64_t)j * lda + l];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) info[0] = 0.0;
+}
+
+// X = L^{-1} (lower triangular, k x k): thread j forms column j by forward
+// substitution.  Entries above the diagonal of X are set to 0.
+__global__ __launch_bounds__(NT) void k_trinv_lower(int k, const double* __restrict__ L,
+                                                    int64_t ldl, double* __restrict__ X,
+                                                    int64_t ldx) {
+  const int j = blockIdx.x * NT + threadIdx.x;
+  if (j >= k) return;
+  double* x = X + (int64_t)j * ldx;
+  for (int i = 0; i < j; ++i) x[i] = 0.0;
+  x[j] = 1.0 / L[(int64_t)j * ldl + j];
+  for (int i = j + 1; i < k; ++i) {
+    double s = 0.0;
+    for (int m = j; m < i; ++m) s += L[(int64_t)m * ldl + i] * x[m];
+    x[i] = -s / L[(int64_t)i * ldl + i];
+  }
+}
+
+// B[c, m] = X[c, m] * s[m] for an upper copy: out = diag? (here: scale
+// column m of X by s[m]); and the upper factor R = L^T with column m scaled
+// by 1 / s[m] (R1 S^-1).  mode 0: out = X diag(s); mode 1: out = L^T diag(1/s)
+__global__ __launch_bounds__(NT) void k_tri_scale(int k, int mode, const double* __restrict__ X,
+                                                  int64_t ldx, const double* __restrict__ s,
+                                                  double* __restrict__ out, int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)k * k) return;
+  const int i = (int)(e % k), m = (int)(e / k);
+  double v;
+  if (mode == 0) {
+    v = X[(int64_t)m * ldx + i] * s[m];
+  } else {
+    // (L^T)[i, m] = L[m, i] for m >= i (upper), zero below
+    v = m >= i ? X[(int64_t)i * ldx + m] : 0.0;
+    v = s[m] > 0.0 ? v / s[m] : 0.0;
+  }
+  out[(int64_t)m * ldo + i] = v;
+}
+
+cr_status chol_lower(int k, double* A, int64_t lda, double* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(CH_NT), 0, st, k, A, lda, info);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+cr_status trinv_lower(int k, const double* L, int64_t ldl, double* X, int64_t ldx, hipStream_t st) {
+  hipLaunchKernelGGL(k_trinv_lower, dim3((unsigned)((k + NT - 1) / NT)), dim3(NT), 0, st, k, L, ldl,
+                     X, ldx);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+cr_status diag_scale(int k, double* A, int64_t lda, double* s, hipStream_t st) {
+  const int64_t kk = (int64_t)k * k;
+  hipLaunchKernelGGL(k_diag_rsqrt, dim3((unsigned)((k + NT - 1) / NT)), dim3(NT), 0, st, k, A, lda,
+                     s);
+  CR_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_diag_apply, dim3((unsigned)((kk + NT - 1) / NT)), dim3(NT), 0, st, k, A, lda,
+                     s);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+cr_status tri_scale(int k, int mode, const double* X, int64_t ldx, const double* s, double* out,
+                    int64_t ldo, hipStream_t st) {
+  const int64_t kk = (int64_t)k * k;
+  hipLaunchKernelGGL(k_tri_scale, dim3((unsigned)((kk + NT - 1) / NT)), dim3(NT), 0, st, k, mode, X,
+                     ldx, s, out, ldo);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+}  // namespace cr

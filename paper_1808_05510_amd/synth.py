@@ -35,7 +35,7 @@ import numpy as np
 __all__ = [
     "graph_laplacian_csr", "box_coords", "toy_1d", "box_problem",
     "config1", "config1_small", "config2", "config2_tiny", "shell_problem",
-    "config3", "config4_specs", "paper_toy",
+    "config3", "config4_specs", "paper_toy", "cortex_2d", "tau_schedule",
 ]
 
 
@@ -323,6 +323,90 @@ def shell_problem(grid=(132, 80, 114), semi=(60.0, 36.0, 26.0), target_count=131
 def config3(seed=0):
     """Cortex-shaped shells: n_y ~ 262,144, n_x ~ 131,072, n_inj 128."""
     return shell_problem(seed=seed)
+
+
+# ---------------------------------------------------------------------------
+# 2-D cortical maps: stand-ins for the paper's top-view and flatmap data
+# (two mirrored hemispheres on a pixel lattice, 5-point graph Laplacians,
+# 126 injections, Omega = 1{X <= 0.4} as for the real data)
+# ---------------------------------------------------------------------------
+def _ellipse_count(a, b):
+    yy, xx = np.mgrid[-int(b) - 1:int(b) + 2, -int(a) - 1:int(a) + 2]
+    return int(np.count_nonzero((xx / a) ** 2 + (yy / b) ** 2 <= 1.0))
+
+
+def hemisphere_masks_2d(per_hemi, aspect=1.35, gap=2):
+    """Two mirrored elliptical hemispheres (semi-axes a = aspect b) whose
+    pixel counts are within 0.1% of per_hemi (b found by bisection)."""
+    lo, hi = 2.0, 4000.0
+    for _ in range(60):
+        b = 0.5 * (lo + hi)
+        if _ellipse_count(aspect * b, b) < per_hemi:
+            lo = b
+        else:
+            hi = b
+    b = hi
+    a = aspect * b
+    nyg = 2 * int(b) + 3
+    nxg = 2 * (2 * int(a) + 3) + gap
+    yy, xx = np.mgrid[0:nyg, 0:nxg].astype(np.float64)
+    cy0 = (nyg - 1) / 2.0
+    cl = int(a) + 1.0
+    cr = nxg - 1 - cl
+    left = ((xx - cl) / a) ** 2 + ((yy - cy0) / b) ** 2 <= 1.0
+    right = ((xx - cr) / a) ** 2 + ((yy - cy0) / b) ** 2 <= 1.0
+    return right, left
+
+
+def cortex_2d(kind="topview", n_inj=126, sigma=(3.0, 6.0), wt_rank=8, wt_w=(8.0, 30.0),
+              mult_noise=0.05, lam_bar=None, max_rank=500, seed=0):
+    """kind "topview": n_y ~ 44,478, n_x ~ 22,239 (the paper's top view has
+    n_y = 44,478, n_x = 22,377); "flatmap": n_y ~ 126,847, n_x ~ 63,424
+    (paper: 126,847 / 63,435).  Target = both hemispheres, source = the
+    right one (same pixels).  Injections: centres on random source pixels,
+    X = Gaussian of width U[sigma], peak 1 (values in [0, 1], about 30 to
+    500 pixels above 0.1); Omega = 0 where the injection density at the
+    target pixel exceeds 0.4 (the paper's rule for its data).  W_true as
+    for the cortex shells (rank-8 Gaussian profiles), multiplicative noise.
+    lambda = lambda_bar n_inj / n_x with the paper's lambda_bar (1e6 top
+    view, 3e7 flatmap)."""
+    per = {"topview": 22239, "flatmap": 63424}[kind]
+    if lam_bar is None:
+        lam_bar = {"topview": 1e6, "flatmap": 3e7}[kind]
+    right, left = hemisphere_masks_2d(per)
+    cy = _mask_coords(right | left)
+    cx = _mask_coords(right)
+    rng = np.random.default_rng(seed)
+    pick = rng.integers(0, cx.shape[0], size=n_inj)
+    centres = cx[pick].astype(np.float64) + rng.uniform(-0.5, 0.5, size=(n_inj, 2))
+    widths = rng.uniform(sigma[0], sigma[1], size=n_inj)
+    cxf, cyf = cx.astype(np.float64), cy.astype(np.float64)
+    X = np.empty((cx.shape[0], n_inj))
+    Omega = np.empty((cy.shape[0], n_inj), dtype=np.uint8)
+    for a in range(n_inj):
+        X[:, a] = _gauss(((cxf - centres[a]) ** 2).sum(1), widths[a])
+        Omega[:, a] = _gauss(((cyf - centres[a]) ** 2).sum(1), widths[a]) <= 0.4
+    grid = np.asarray(right.shape, float)
+    cg = rng.uniform(0.0, 1.0, size=(wt_rank, 2)) * (grid - 1)
+    ch = rng.uniform(0.0, 1.0, size=(wt_rank, 2)) * (grid - 1)
+    wg = rng.uniform(*wt_w, size=wt_rank)
+    wh = rng.uniform(*wt_w, size=wt_rank)
+    amp = rng.uniform(0.5, 1.0, size=wt_rank)
+    G = _profiles(cy, cg, wg)
+    H = _profiles(cx, ch, wh)
+    Ytrue = (G * amp[None, :]) @ (H.T @ X)
+    Y = (Omega * Ytrue) * (1.0 + mult_noise * rng.standard_normal(Ytrue.shape))
+    lam = lam_bar * n_inj / cx.shape[0]
+    return _pack(cy, cx, X, Y, Omega, lam, max_rank, 0.0,
+                 dict(Wt_a=amp, Wt_g=G, Wt_h=H, box_y=np.zeros(3, np.int32),
+                      box_x=np.zeros(3, np.int32), centres=centres, lam_bar=float(lam_bar)))
+
+
+def tau_schedule(r, r_lo=125, r_hi=1000, tau_lo=1e-3, tau_hi=1e-6):
+    """The paper's stopping tolerances for its real-data runs: geometric in r
+    from tau_lo at r_lo to tau_hi at r_hi."""
+    t = math.log(r / r_lo) / math.log(r_hi / r_lo)
+    return float(tau_lo * (tau_hi / tau_lo) ** t)
 
 
 @dataclass
