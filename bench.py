@@ -101,7 +101,7 @@ def compact_cpu(cpu):
     return out
 
 
-def summarize(mixed, learned, shells, batch, op):
+def summarize(mixed, learned, shells, batch, op, highrank=None):
     """Scalar figures of every leg for the one-line result (seconds, relres,
     W error against the FP64 GPU solve, bandwidths)."""
     s = {}
@@ -122,6 +122,12 @@ def summarize(mixed, learned, shells, batch, op):
                        for k, v in shells.items() if isinstance(v, dict) and "seconds" in v}
         if "w_err_mixed_vs_fp64" in shells:
             s["shells"]["w_err_mixed_vs_fp64"] = sig(shells["w_err_mixed_vs_fp64"])
+    if highrank:
+        s["highrank_2d"] = {k: dict(s=sig(v["seconds"]), rank=v["rank"], relres=sig(v["relres"]),
+                                    at=v["seconds_at_rank"])
+                            for k, v in highrank.items() if isinstance(v, dict) and "seconds" in v}
+        if "w_err_mixed_vs_fp64" in highrank:
+            s["highrank_2d"]["w_err_mixed_vs_fp64"] = sig(highrank["w_err_mixed_vs_fp64"])
     if batch:
         s["batch"] = dict(seq_s=sig(batch["sequential_s"]), batched_s=sig(batch["batched_s"]),
                           speedup=sig(batch["speedup"], 3))
@@ -354,6 +360,43 @@ def bench_shells(steps=1):
     return out
 
 
+def bench_highrank(max_rank=250, kind="topview", precs=("fp64", "mixed"), verbose=0):
+    """The paper's operating point: high rank on a 2-D cortical map (top-view
+    size, n_inj 126), Galerkin tolerance tau(r)/2 from the paper's schedule
+    for the target rank, no delta W stop (so the target rank is reached).
+    Seconds to each of the paper's reported ranks (125, 200, 250, 400, 500)
+    that the run passes."""
+    d = synth.cortex_2d(kind, seed=0)
+    gtol = 0.5 * synth.tau_schedule(max_rank)
+    out = dict(kind=kind, n_y=int(d["Ly_rowptr"].size - 1), n_x=int(d["Lx_rowptr"].size - 1),
+               n_inj=int(d["X"].shape[1]), lam=float(d["lam"]), max_rank=max_rank,
+               galerkin_rtol=gtol)
+    for prec in precs:
+        p = connreg.Problem(d, prec, "cuda:0")
+        rtol = MIXED_RTOL if prec == "mixed" else FP64_RTOL
+        p.greedy_solve(max_rank=2, tau_dW=0.0, galerkin_rtol=gtol, seed=0, pcg_rtol=rtol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = p.greedy_solve(max_rank=max_rank, tau_dW=0.0, galerkin_rtol=gtol, seed=0,
+                             pcg_rtol=rtol, verbose=verbose)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        hist = res["history"]
+        at = {str(h["rank"]): round(h["seconds"], 3) for h in hist
+              if h["rank"] in (125, 200, 250, 400, 500)}
+        out[prec] = dict(seconds=secs, rank=res["rank"], relres=res["stats"]["relres"],
+                         pcg_iters=res["stats"]["pcg_iters"],
+                         galerkin_iters=res["stats"]["galerkin_iters"], seconds_at_rank=at,
+                         J=hist[-1]["J"] if hist else None,
+                         curve=[[h["rank"], h["relres"], h["seconds"], h["J"]] for h in hist])
+        out.setdefault("_res", {})[prec] = res
+        p.close()
+    if "fp64" in precs and "mixed" in precs:
+        out["w_err_mixed_vs_fp64"] = w_rel_diff(out["_res"]["mixed"], out["_res"]["fp64"])
+    out.pop("_res", None)
+    return out
+
+
 def blas_threads():
     from threadpoolctl import threadpool_info
     n = [i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"]
@@ -430,6 +473,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-shells", action="store_true")
+    ap.add_argument("--no-highrank", action="store_true")
+    ap.add_argument("--highrank-rank", type=int, default=250,
+                    help="target rank of the 2-D high-rank leg (the paper goes to 1000)")
+    ap.add_argument("--highrank-only", action="store_true")
     ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="file for curves and per-problem arrays ('' = none)")
     a = ap.parse_args()
@@ -456,6 +503,15 @@ def main():
         for kind, e in lr["inner_u_solves"].items():
             log(f"[bench] inner u-solves {kind}: {e['mean_iters']:.1f} iterations, "
                 f"{e['mean_ms']:.2f} ms")
+        return
+    if a.highrank_only:
+        hr = bench_highrank(a.highrank_rank, verbose=1)
+        write_detail(a.detail, {"highrank_2d": hr})
+        for k in ("fp64", "mixed"):
+            log(f"[bench] highrank {k}: {hr[k]['seconds']:.1f} s to rank {hr[k]['rank']} "
+                f"(at ranks {hr[k]['seconds_at_rank']}), relres {hr[k]['relres']:.3e}, "
+                f"galerkin iterations {hr[k]['galerkin_iters']}, pcg {hr[k]['pcg_iters']}")
+        log(f"[bench] highrank mixed W error vs fp64 {hr['w_err_mixed_vs_fp64']:.2e}")
         return
     if a.batch_only:
         for pre in ("jacobi", "base"):
@@ -550,6 +606,14 @@ def main():
         log(f"[bench] shells: fp64 {shells['fp64']['seconds']:.2f} s (rank {shells['fp64']['rank']}, "
             f"relres {shells['fp64']['relres']:.2e}); mixed {shells['mixed']['seconds']:.2f} s")
 
+    highrank = None
+    if not a.no_highrank:
+        log(f"[bench] high-rank 2-D top-view map to rank {a.highrank_rank}")
+        highrank = bench_highrank(a.highrank_rank)
+        for k in ("fp64", "mixed"):
+            log(f"[bench] highrank {k}: {highrank[k]['seconds']:.1f} s to rank {highrank[k]['rank']}"
+                f" (at ranks {highrank[k]['seconds_at_rank']}), relres {highrank[k]['relres']:.3e}")
+
     batch = None
     if not a.no_batch:
         log("[bench] 16-problem batch (sequential vs one batched call)")
@@ -573,7 +637,7 @@ def main():
                      pcg_iters=res["stats"]["pcg_iters"],
                      galerkin_iters=res["stats"]["galerkin_iters"], relres_curve=curve),
         "mixed": mixed, "mixed_learned_pc": learned, "shells": shells, "op_apply": op,
-        "batch": batch, "roofline": roof, "cpu_baseline": cpu,
+        "batch": batch, "roofline": roof, "cpu_baseline": cpu, "highrank_2d": highrank,
     }
     write_detail(a.detail, detail)
     line = {
@@ -598,7 +662,7 @@ def main():
         "pcg_iters": res["stats"]["pcg_iters"],
         "roofline": roof,
         "cpu_baseline": compact_cpu(cpu),
-        "summary": summarize(mixed, learned, shells, batch, op),
+        "summary": summarize(mixed, learned, shells, batch, op, highrank),
         "detail_file": a.detail,
     }
     print(json.dumps(line, separators=(",", ":")), flush=True)
