@@ -88,6 +88,7 @@ struct cr_problem {
   bool no_xreg = false;     // CONNREG_PCG_XREG=0: v-system PCG streams X (no register-resident rows)
   bool pcg_warm = true;     // FP64 ALS half-steps warm-started (CONNREG_PCG_WARM=0: from zero)
   int bar_mode = 1;
+  unsigned bar_spin = 1u << 22;  // grid-barrier poll bound (CONNREG_BAR_SPIN, for tests)
   std::map<std::string, DevBuf> ws;
   std::vector<void*> owned;
 
@@ -587,6 +588,10 @@ struct Ctx {
     return CR_OK;
   }
 
+  // Host copy of device scalars; fails when a persistent kernel's grid
+  // barrier timed out (the live flag, for reads right after the launch; the
+  // kernels also record PERSIST_TIMEOUT in their status scalars for reads
+  // deferred past later launches, checked where those are read).
   cr_status read_scalars(const double* dev, int count, double* host) {
     unsigned* flag = (unsigned*)(P->hscal + 60);
     CR_HIP(hipMemcpyAsync(P->hscal, dev, sizeof(double) * count, hipMemcpyDeviceToHost, st));
@@ -719,6 +724,7 @@ struct Ctx {
     a.bar.bar = P->bar;
     a.bar.mode = P->bar_mode;
     a.bar.coop = P->coop;
+    a.bar.spin_max = P->bar_spin;
     return pcg_solve<T>(a, usys ? pcg_nwg_u : pcg_nwg_v, st);
   }
 
@@ -1091,6 +1097,10 @@ struct Ctx {
     if (du || dv) {
       double hs[8];
       CR_TRY(read_scalars(sc, 8, hs));
+      if ((du && hs[3] == PERSIST_TIMEOUT) || (dv && hs[7] == PERSIST_TIMEOUT)) {
+        set_error("grid barrier timed out in a persistent PCG kernel");
+        return CR_EHIP;
+      }
       if (du) *ou = SolveOut{hs[0], hs[1], (int)hs[2], (int)hs[3]};
       if (dv) *ov = SolveOut{hs[4], hs[5], (int)hs[6], (int)hs[7]};
     }
@@ -1251,6 +1261,7 @@ struct Ctx {
     a.bar.bar = P->bar;
     a.bar.mode = P->bar_mode;
     a.bar.coop = P->coop;
+    a.bar.spin_max = P->bar_spin;
     CR_TRY(galerkin_cg(a, nwg, st));
     return read_scalars(sc + 8, 4, scal4);
   }
@@ -1607,6 +1618,8 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
   if (const char* e = std::getenv("CONNREG_PCG_WARM")) P->pcg_warm = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_RESID_QR")) P->resid_qr = std::max(0, std::min(2, std::atoi(e)));
+  if (const char* e = std::getenv("CONNREG_BAR_SPIN"))
+    P->bar_spin = (unsigned)std::max(1L, std::min(1L << 22, std::atol(e)));
   P->ny = d->Ly.n;
   P->nx = d->Lx.n;
   P->ninj = (int)d->n_inj;
@@ -2217,6 +2230,10 @@ static cr_status galerkin_impl(cr_problem* P, int64_t r, const double* U, int64_
   CR_TRY((convert2d<double, double>(r, r, c.Z, r, Z_io, ldz, c.st)));
   CR_HIP(hipStreamSynchronize(c.st));
   if (iters_out) *iters_out = (int32_t)s[0];
+  if (s[2] == PERSIST_TIMEOUT) {
+    set_error("grid barrier timed out in the projected CG kernel");
+    return CR_EHIP;
+  }
   if (s[2] == 2.0) {
     set_error("projected operator not positive definite on a CG direction");
     return CR_ENONFINITE;
@@ -2355,6 +2372,10 @@ static cr_status greedy_impl(cr_problem* P, const cr_solve_opts& o, double* Uo, 
     double gs[4];
     const int gmax = o.galerkin_maxit > 0 ? o.galerkin_maxit : 50 * (j + 1) + 200;
     CR_TRY(c.galerkin(j + 1, ldr, g_rtol, gmax, gs));
+    if (gs[2] == PERSIST_TIMEOUT) {
+      set_error("grid barrier timed out in the projected CG kernel");
+      return CR_EHIP;
+    }
     if (gs[2] == 2.0) {
       set_error("projected operator not positive definite on a CG direction");
       return CR_ENONFINITE;

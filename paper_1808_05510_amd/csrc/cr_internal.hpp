@@ -195,7 +195,12 @@ struct BarrierArg {
   int mode = 1;             // 0: cooperative-groups grid sync, 1: atomic barrier
   int coop = 1;             // 1: cooperative launch; 0: ordinary launch (mode 1 only, for
                             // concurrent persistent kernels that together fit on the device)
+  unsigned spin_max = 1u << 22;  // polls before a waiting workgroup gives up (timeout flag)
 };
+// Status a persistent kernel writes when its grid barrier timed out: the
+// kernel records it in its own scalars, so a read deferred past a later
+// launch (which clears the barrier words) still sees it.
+constexpr double PERSIST_TIMEOUT = 3.0;
 
 template <typename T>
 struct PcgArgs {

@@ -121,7 +121,7 @@ __device__ __forceinline__ void grid_barrier(const BarrierArg& b, cgrp::grid_gro
       unsigned spins = 0;
       while (__hip_atomic_load(b.bar + BAR_GEN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1u << 22)) {
+        if (++spins > b.spin_max) {
           __hip_atomic_store(b.bar + BAR_TIMEOUT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
@@ -555,7 +555,10 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
     a.scal[0] = xn;
     a.scal[1] = bnorm2 > 0.0 ? sqrt(rr / bnorm2) : 0.0;
     a.scal[2] = (double)it;
-    a.scal[3] = (double)status;
+    const bool timed_out =
+        a.bar.mode == 1 &&
+        __hip_atomic_load(a.bar.bar + BAR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    a.scal[3] = timed_out ? PERSIST_TIMEOUT : (double)status;
   }
 }
 
@@ -843,7 +846,10 @@ __global__ __launch_bounds__(NT) void k_galerkin(GalerkinArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.scal[0] = (double)it;
     a.scal[1] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-    a.scal[2] = (double)status;
+    const bool timed_out =
+        a.bar.mode == 1 &&
+        __hip_atomic_load(a.bar.bar + BAR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    a.scal[2] = timed_out ? PERSIST_TIMEOUT : (double)status;
     a.scal[3] = -0.5 * zb - 0.5 * zr;  // 1/2 <Z, A_p Z> - <Z, B> with A_p Z = B - R
   }
 }

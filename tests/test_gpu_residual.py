@@ -118,3 +118,17 @@ def test_greedy_incremental_grams_give_each_ranks_relres():
     for hg, ho in zip(res["history"], ores.history):
         assert abs(hg["relres"] - ho["relres"]) <= 1e-7 * ho["relres"], (hg["rank"], hg["relres"],
                                                                           ho["relres"])
+
+
+def test_barrier_timeout_surfaces_through_deferred_reads(monkeypatch):
+    """A grid barrier that gives up (forced from the host: a poll bound of
+    one, so waiting workgroups time out at once; every kernel still runs to
+    its end) must turn into an error even where the PCG scalars are read
+    after the next launch has cleared the barrier words (the FP64 u-solve's
+    deferred read)."""
+    monkeypatch.setenv("CONNREG_BAR_SPIN", "1")
+    d = synth.config2(lam=1e3, seed=0)  # 63 u-system and 106 v-system workgroups
+    g = connreg.Problem(d, "fp64", DEV)
+    with pytest.raises(connreg.ConnRegError, match="timed out"):
+        g.greedy_solve(max_rank=2, seed=0)
+    g.close()
