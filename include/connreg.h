@@ -394,6 +394,25 @@ cr_status cr_problem_set_precond(cr_problem* p, int32_t kind);
  * dims [host]. */
 cr_status cr_problem_set_box(cr_problem* p, int32_t which, const int32_t* dims);
 
+/* Two-level preconditioner for the v-systems of eq. ALS_linsys_v (the ALS
+ * half-step the paper solves with Sherman-Morrison-Woodbury around a sparse
+ * direct solve; here Jacobi-PCG, whose iteration count is set by the nearly
+ * singular lam (L_x + c I)^2 part).  The source voxels are grouped into
+ * aggregates, the cubes of `block` voxels per axis of their integer
+ * coordinates coords [host] (n_x x dim, row-major, the numbering of L_x;
+ * dim 1..3); M^-1 = D^-1 + P (P^T B_hat P)^-1 P^T with D the Jacobi
+ * diagonal and P the normalised aggregate indicator matrix.  The coarse
+ * matrix is assembled and inverted on the GPU for every v-system (m
+ * aggregates: a few m^3 flops), and each PCG iteration restricts the
+ * residual per aggregate and adds the coarse correction (one more grid
+ * barrier per iteration).  The answer does not change (same stopping test).
+ * which must be 1 (source); block <= 0 switches it off.  Errors: CR_EINVAL
+ * (an aggregate above 256 voxels, more than 2048 aggregates, bad dim).
+ * Launches whose two-level grid does not fit co-resident use plain
+ * Jacobi-PCG. */
+cr_status cr_problem_set_coarse(cr_problem* p, int32_t which, const int32_t* coords,
+                                int32_t dim, int32_t block);
+
 /* ---------------------------------------------------------------------------
  * Batched solves and autotuning.
  * ------------------------------------------------------------------------- */

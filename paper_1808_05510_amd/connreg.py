@@ -29,7 +29,8 @@ PREC = {"fp64": 0, "mixed": 1}
 
 EXPORTS = ["cr_problem_create", "cr_problem_destroy", "cr_rhs_norm", "cr_op_apply",
            "cr_op_apply_f32", "cr_op_apply_factors",
-           "cr_op_apply_noalloc", "cr_core_svd", "cr_objective", "cr_entry_stats", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
+           "cr_op_apply_noalloc", "cr_core_svd", "cr_objective", "cr_entry_stats",
+           "cr_problem_set_coarse", "cr_solve_opts_default", "cr_als_step", "cr_galerkin_project",
            "cr_residual_norm", "cr_greedy_solve", "cr_last_error", "cr_version",
            "cr_u_system", "cr_u_solve", "cr_problem_set_pc", "cr_pc_create", "cr_pc_destroy",
            "cr_pc_num_params", "cr_pc_get_params", "cr_pc_set_params", "cr_pc_forward",
@@ -141,6 +142,7 @@ def load(path: str = LIB_PATH):
     L.cr_problem_set_pc.argtypes = [P, P]
     L.cr_problem_set_precond.argtypes = [P, c_int32]
     L.cr_problem_set_box.argtypes = [P, c_int32, POINTER(c_int32)]
+    L.cr_problem_set_coarse.argtypes = [P, c_int32, P, c_int32, c_int32]
     L.cr_pc_create.argtypes = [c_int32, c_int32, c_int32, c_int32, c_uint64, P, POINTER(P)]
     L.cr_pc_destroy.argtypes = [P]
     L.cr_pc_destroy.restype = None
@@ -433,6 +435,16 @@ class Problem:
         """Declare the target or source grid a full box (first axis fastest)."""
         w = {"target": 0, "source": 1}[which]
         _check(load().cr_problem_set_box(self.h, w, (c_int32 * 3)(*[int(v) for v in dims])))
+
+    def set_coarse(self, coords, block):
+        """Two-level preconditioner for the v-systems: aggregates = cubes of
+        `block` voxels per axis of the source voxel coordinates (n_x x dim);
+        block <= 0 switches it off."""
+        c = np.ascontiguousarray(np.asarray(coords), dtype=np.int32)
+        if c.ndim == 1:
+            c = c[:, None]
+        _check(load().cr_problem_set_coarse(self.h, 1, c.ctypes.data, int(c.shape[1]),
+                                            int(block)))
 
     def set_precond(self, kind):
         """u-system preconditioner of the greedy solve: "jacobi", "base" or "learned"."""

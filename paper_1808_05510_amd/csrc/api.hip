@@ -41,6 +41,22 @@ static bool poison_workspace() {
   return v;
 }
 
+// Two-level preconditioner of the v-systems (cr_problem_set_coarse): the
+// aggregate packing for 256- and 512-thread workgroups and the coarse
+// operator's geometry (C1 = P^T L_x P, C2 = P^T L_x^2 P) and data (Y = P^T X).
+struct CoarsePack {
+  int bs = 0, nwg = 0;
+  int32_t *slot_vox = nullptr, *slot_agg = nullptr, *wg_agg = nullptr;
+  int32_t *agg_lo = nullptr, *agg_hi = nullptr;
+  double* slot_w = nullptr;
+};
+struct CoarseLevel {
+  bool valid = false;
+  int m = 0, block = 0;
+  CoarsePack pack[2];  // 256- and 512-thread workgroups
+  double *C1 = nullptr, *C2 = nullptr, *Y = nullptr;
+};
+
 struct cr_problem {
   int dev = -1;               // device the handle was created on
   hipStream_t st = nullptr;
@@ -72,6 +88,7 @@ struct cr_problem {
   int fcg_mode = 0;         // u-systems: 0 Jacobi-PCG, 1 FCG + base step, 2 FCG + base step + network
   BoxBasis boxy;            // spectral basis of the target grid when it is a full box
   BoxBasis boxx;            // spectral basis of the source grid when it is a full box
+  CoarseLevel cv;           // two-level preconditioner of the v-systems
   bool kr_omega_ready = false;
   bool smw_xh_ready = false;    // workspace "smw_Xh" holds Q^T X of the source box  // workspace "kraux" holds the BF16 copy of Omega
   int64_t pc_fallbacks = 0;
@@ -423,6 +440,7 @@ struct Ctx {
   double *sc = nullptr, *part = nullptr, *pcgpart = nullptr, *sbuf = nullptr, *gpart = nullptr;
   double* tmp = nullptr;
   int pcg_vpt_u = 1, pcg_vpt_v = 1, pcg_nwg_u = 1, pcg_nwg_v = 1, pcg_bs = NT;
+  int64_t pcgpart_size = 0;
   int pcg_xtail_v = 0;  // v-system: register rows plus a streamed tail of X
   int pcg_bs_v = NT, pcg_nxr_v = 0;  // v-system: X rows in registers when n_inj <= PCG_NXR
   // stats of the last ALS
@@ -564,7 +582,12 @@ struct Ctx {
       return CR_EINVAL;
     }
     const int nwg = std::max(pcg_nwg_u, pcg_nwg_v);
-    pcgpart = WS(double, "pcgpart", (int64_t)(5 + ninj) * nwg);
+    // partial sums for the widest grid (the two-level packing may use more
+    // workgroups than the plain v-system grid)
+    int nwg_all = nwg;
+    if (P->cv.valid) nwg_all = std::max({nwg_all, P->cv.pack[0].nwg, P->cv.pack[1].nwg});
+    pcgpart_size = (int64_t)(6 + ninj) * nwg_all;
+    pcgpart = WS(double, "pcgpart", pcgpart_size);
     return CR_OK;
   }
 
@@ -688,6 +711,29 @@ struct Ctx {
   // ------------------------------------------------------------ ALS
   // x0 / xbuf / bref: warm start (xbuf receives the unnormalised solution,
   // default the work vector), see pcg_warm
+  // Coarse operator of the current v-system, A_c = P^T B_hat P =
+  // lam (C2 + 2c C1 + e I) + Y diag(g) Y^T, and its inverse by Cholesky (one
+  // workgroup), a row-parallel triangular inverse and Ainv = L^-T L^-1
+  // (matrix cores); Ainv stays zero if the factorisation fails (Jacobi).
+  double *co_Ainv = nullptr, *co_rc = nullptr;
+  cr_status coarse_factor() {
+    const CoarseLevel& cl = P->cv;
+    const int m = cl.m;
+    const int64_t mm = (int64_t)m * m;
+    double* A = WS(double, "co_A", mm);
+    double* Li = WS(double, "co_Li", mm);
+    co_Ainv = WS(double, "co_Ainv", mm);
+    co_rc = WS(double, "co_rc", m);
+    double* info = WS(double, "co_info", 2);
+    CR_TRY(coarse_assemble(m, lam, cv, cl.C1, cl.C2, cl.Y, ninj, gw, A, st));
+    CR_TRY(chol_lower(m, A, m, info, st));
+    CR_TRY(trinv_rows(m, A, m, Li, m, info, st));
+    Blocks<double> B;
+    B.clear();
+    B.add(Li, m, m);
+    return gemm_tn<double>(m, B, B, nullptr, nullptr, 0, co_Ainv, m, gpart, gemm_part_cap(P), st);
+  }
+
   cr_status pcg(bool usys, const T* b, T* xout, double rtol, int maxit, double* scal,
                 const T* x0 = nullptr, T* xbuf = nullptr, const double* bref = nullptr) {
     PcgArgs<T> a{};
@@ -725,7 +771,27 @@ struct Ctx {
     a.bar.mode = P->bar_mode;
     a.bar.coop = P->coop;
     a.bar.spin_max = P->bar_spin;
-    return pcg_solve<T>(a, usys ? pcg_nwg_u : pcg_nwg_v, st);
+    int nwg = usys ? pcg_nwg_u : pcg_nwg_v;
+    if (!usys && P->cv.valid && co_Ainv && a.vpt == 1 && (a.bs == NT || a.bs == 512)) {
+      const CoarsePack& pk = P->cv.pack[a.bs == NT ? 0 : 1];
+      PcgArgs<T> c = a;
+      c.co.slot_vox = pk.slot_vox;
+      c.co.slot_agg = pk.slot_agg;
+      c.co.slot_w = pk.slot_w;
+      c.co.wg_agg = pk.wg_agg;
+      c.co.agg_lo = pk.agg_lo;
+      c.co.agg_hi = pk.agg_hi;
+      c.co.m = P->cv.m;
+      c.co.Ainv = co_Ainv;
+      c.co.rc = co_rc;
+      int maxwg = pcg_max_wg<T>(c);
+      if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
+      // the two-level grid must be co-resident; else plain Jacobi-PCG
+      if (maxwg >= pk.nwg && pk.nwg * 6 + (int64_t)ninj * pk.nwg <= pcgpart_size) {
+        return pcg_solve<T>(c, pk.nwg, st);
+      }
+    }
+    return pcg_solve<T>(a, nwg, st);
   }
 
   // FP64 Jacobi-PCG of an ALS half-step, warm-started from the previous
@@ -1093,6 +1159,7 @@ struct Ctx {
     hipLaunchKernelGGL(k_set2, dim3(1), dim3(1), 0, st, cv, tmp + 2, 2.0, tmp + 3, 1.0);
     CR_HIP(hipGetLastError());
     CR_TRY(pcg_diag<T>(P->gx, lam, cv, nullptr, X(), nx, ninj, gw, minv_v, st));
+    if (P->cv.valid) CR_TRY(coarse_factor());
     CR_TRY(solve_sys(false, rhs_v, v, rtol, maxit, sc + 4, ov, dv));
     if (du || dv) {
       double hs[8];
@@ -2549,6 +2616,171 @@ extern "C" cr_status cr_problem_set_box(cr_problem* P, int32_t which, const int3
   }
   (which == 0 ? P->boxy : P->boxx) = bx;
   if (which != 0) P->smw_xh_ready = false;
+  return CR_OK;
+}
+
+// ===================================================================== two-level set-up
+// Aggregates = the source voxels grouped by cubes of `block` voxels per axis
+// of their coordinates; packed whole into workgroups (in cube order) for
+// 256- and 512-thread launches; coarse geometry C1 = P^T L P and C2 =
+// (L P)^T (L P) from the neighbour table, and Y = P^T X, all in FP64 on the
+// host at set-up (P the normalised aggregate indicator matrix).
+static constexpr int CO_MMAX = 2048;
+
+static cr_status coarse_pack(cr_problem* P, int bs, const std::vector<int32_t>& order,
+                             const std::vector<int32_t>& agg_first,
+                             const std::vector<double>& agg_w, CoarsePack& pk) {
+  const int m = (int)agg_first.size() - 1;
+  std::vector<int32_t> wg_agg{0}, agg_lo(m), agg_hi(m);
+  int fill = 0, nloc = 0;
+  for (int a = 0; a < m; ++a) {
+    const int sz = agg_first[a + 1] - agg_first[a];
+    if (fill + sz > bs || nloc == CO_MAXLOC) {
+      wg_agg.push_back(a);
+      fill = 0;
+      nloc = 0;
+    }
+    agg_lo[a] = fill;
+    agg_hi[a] = fill + sz;
+    fill += sz;
+    ++nloc;
+  }
+  wg_agg.push_back(m);
+  const int nwg = (int)wg_agg.size() - 1;
+  std::vector<int32_t> svox((size_t)nwg * bs, -1), sagg((size_t)nwg * bs, -1);
+  std::vector<double> sw((size_t)nwg * bs, 0.0);
+  for (int w = 0; w < nwg; ++w)
+    for (int a = wg_agg[w]; a < wg_agg[w + 1]; ++a)
+      for (int q = 0; q < agg_hi[a] - agg_lo[a]; ++q) {
+        const size_t slot = (size_t)w * bs + agg_lo[a] + q;
+        svox[slot] = order[agg_first[a] + q];
+        sagg[slot] = a;
+        sw[slot] = agg_w[a];
+      }
+  pk.bs = bs;
+  pk.nwg = nwg;
+  CR_TRY(dev_alloc(P, &pk.slot_vox, (int64_t)svox.size()));
+  CR_TRY(dev_alloc(P, &pk.slot_agg, (int64_t)sagg.size()));
+  CR_TRY(dev_alloc(P, &pk.slot_w, (int64_t)sw.size()));
+  CR_TRY(dev_alloc(P, &pk.wg_agg, (int64_t)wg_agg.size()));
+  CR_TRY(dev_alloc(P, &pk.agg_lo, (int64_t)m));
+  CR_TRY(dev_alloc(P, &pk.agg_hi, (int64_t)m));
+  CR_HIP(stage_to_device(pk.slot_vox, svox.data(), sizeof(int32_t) * svox.size(), P->st));
+  CR_HIP(stage_to_device(pk.slot_agg, sagg.data(), sizeof(int32_t) * sagg.size(), P->st));
+  CR_HIP(stage_to_device(pk.slot_w, sw.data(), sizeof(double) * sw.size(), P->st));
+  CR_HIP(stage_to_device(pk.wg_agg, wg_agg.data(), sizeof(int32_t) * wg_agg.size(), P->st));
+  CR_HIP(stage_to_device(pk.agg_lo, agg_lo.data(), sizeof(int32_t) * m, P->st));
+  CR_HIP(stage_to_device(pk.agg_hi, agg_hi.data(), sizeof(int32_t) * m, P->st));
+  return CR_OK;
+}
+
+extern "C" cr_status cr_problem_set_coarse(cr_problem* P, int32_t which, const int32_t* coords,
+                                           int32_t dim, int32_t block) {
+  if (!P) {
+    set_error("null handle");
+    return CR_EINVAL;
+  }
+  if (which != 1) {
+    set_error("cr_problem_set_coarse: only the source grid (which = 1, the v-systems)");
+    return CR_EINVAL;
+  }
+  if (block <= 0) {
+    P->cv.valid = false;
+    return CR_OK;
+  }
+  if (!coords || dim < 1 || dim > 3) {
+    set_error("cr_problem_set_coarse: coordinates required, dim in 1..3");
+    return CR_EINVAL;
+  }
+  const int64_t n = P->nx;
+  // aggregate key of every voxel: its cube of block^dim voxels
+  int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < dim; ++d) {
+      lo[d] = std::min(lo[d], coords[i * dim + d]);
+      hi[d] = std::max(hi[d], coords[i * dim + d]);
+    }
+  int64_t ext[3] = {1, 1, 1};
+  for (int d = 0; d < dim; ++d) ext[d] = (int64_t)(hi[d] - lo[d]) / block + 1;
+  std::vector<int64_t> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t k = 0;
+    for (int d = dim - 1; d >= 0; --d) k = k * ext[d] + (coords[i * dim + d] - lo[d]) / block;
+    key[i] = k;
+  }
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  std::vector<int32_t> agg_of(n), agg_first;
+  for (int64_t q = 0; q < n; ++q) {
+    if (q == 0 || key[order[q]] != key[order[q - 1]]) agg_first.push_back((int32_t)q);
+    agg_of[order[q]] = (int32_t)agg_first.size() - 1;
+  }
+  agg_first.push_back((int32_t)n);
+  const int m = (int)agg_first.size() - 1;
+  int maxsz = 0;
+  for (int a = 0; a < m; ++a) maxsz = std::max(maxsz, agg_first[a + 1] - agg_first[a]);
+  if (maxsz > NT) {
+    set_error("cr_problem_set_coarse: an aggregate has more than 256 voxels (smaller block)");
+    return CR_EINVAL;
+  }
+  if (m > CO_MMAX) {
+    set_error("cr_problem_set_coarse: " + std::to_string(m) + " aggregates, at most " +
+              std::to_string(CO_MMAX) + " (larger block)");
+    return CR_EINVAL;
+  }
+  std::vector<double> aw(m);
+  for (int a = 0; a < m; ++a) aw[a] = 1.0 / std::sqrt((double)(agg_first[a + 1] - agg_first[a]));
+  // neighbour table of the source Laplacian (absent neighbours point to the voxel)
+  const int K = P->gx.K;
+  std::vector<int32_t> nbr((size_t)K * n);
+  CR_HIP(stage_to_host(nbr.data(), P->gx.nbr, sizeof(int32_t) * nbr.size(), 1, 0, P->st));
+  // row i of L P: K w_i P_i,. - sum_k P_nbr_k(i),.  (sparse over aggregates)
+  std::vector<double> C1((size_t)m * m, 0.0), C2((size_t)m * m, 0.0);
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t i = 0; i < n; ++i) {
+    row.clear();
+    auto add = [&](int32_t a, double v) {
+      for (auto& e : row)
+        if (e.first == a) {
+          e.second += v;
+          return;
+        }
+      row.emplace_back(a, v);
+    };
+    add(agg_of[i], (double)K * aw[agg_of[i]]);
+    for (int k = 0; k < K; ++k) {
+      const int32_t j = nbr[(size_t)k * n + i];
+      add(agg_of[j], -aw[agg_of[j]]);
+    }
+    const int32_t ai = agg_of[i];
+    for (auto& e : row) {
+      if (e.second == 0.0) continue;
+      C1[(size_t)e.first * m + ai] += aw[ai] * e.second;  // (P^T L P)[a(i), b]
+      for (auto& f : row) C2[(size_t)f.first * m + e.first] += e.second * f.second;
+    }
+  }
+  // Y = P^T X (FP64)
+  const int ni = P->ninj;
+  std::vector<double> X((size_t)n * ni), Y((size_t)m * ni, 0.0);
+  CR_HIP(stage_to_host(X.data(), P->X64, sizeof(double) * X.size(), 1, 0, P->st));
+  for (int al = 0; al < ni; ++al)
+    for (int64_t i = 0; i < n; ++i)
+      Y[(size_t)al * m + agg_of[i]] += aw[agg_of[i]] * X[(size_t)al * n + i];
+  CoarseLevel cl;
+  cl.m = m;
+  cl.block = block;
+  CR_TRY(coarse_pack(P, NT, order, agg_first, aw, cl.pack[0]));
+  CR_TRY(coarse_pack(P, 512, order, agg_first, aw, cl.pack[1]));
+  CR_TRY(dev_alloc(P, &cl.C1, (int64_t)m * m));
+  CR_TRY(dev_alloc(P, &cl.C2, (int64_t)m * m));
+  CR_TRY(dev_alloc(P, &cl.Y, (int64_t)m * ni));
+  CR_HIP(stage_to_device(cl.C1, C1.data(), sizeof(double) * C1.size(), P->st));
+  CR_HIP(stage_to_device(cl.C2, C2.data(), sizeof(double) * C2.size(), P->st));
+  CR_HIP(stage_to_device(cl.Y, Y.data(), sizeof(double) * Y.size(), P->st));
+  cl.valid = true;
+  P->cv = cl;
   return CR_OK;
 }
 

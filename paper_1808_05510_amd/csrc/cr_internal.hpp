@@ -202,8 +202,31 @@ struct BarrierArg {
 // launch (which clears the barrier words) still sees it.
 constexpr double PERSIST_TIMEOUT = 3.0;
 
+// Two-level preconditioner of the v-system PCG: aggregates of source voxels
+// (a partition into spatial blocks), packed whole into workgroups; thread
+// slot s of the launch holds voxel slot_vox[s] (-1: idle) of aggregate
+// slot_agg[s], weight slot_w[s] = 1 / sqrt(|aggregate|).  Workgroup b owns
+// aggregates [wg_agg[b], wg_agg[b+1]), aggregate a the slots
+// [agg_lo[a], agg_hi[a]) of its workgroup.  M^-1 r = D^-1 r + P Ainv P^T r
+// with P the normalised indicator matrix and Ainv = (P^T A P)^-1 (m x m,
+// rebuilt for every solve; all zero when its Cholesky factorisation fails,
+// which leaves plain Jacobi).  rc: m doubles, the restricted residual.
+struct CoarseArg {
+  const int32_t* slot_vox = nullptr;
+  const int32_t* slot_agg = nullptr;
+  const double* slot_w = nullptr;
+  const int32_t* wg_agg = nullptr;
+  const int32_t* agg_lo = nullptr;
+  const int32_t* agg_hi = nullptr;
+  int m = 0;
+  const double* Ainv = nullptr;
+  double* rc = nullptr;
+};
+constexpr int CO_MAXLOC = 64;  // aggregates per workgroup
+
 template <typename T>
 struct PcgArgs {
+  CoarseArg co;         // two-level (CO kernels only)
   Geom g;
   double lam;
   const double* coef;   // device: coef[0] = c1, coef[1] = c0
@@ -383,6 +406,15 @@ cr_status chol_lower(int k, double* A, int64_t lda, double* info, hipStream_t st
 cr_status trinv_lower(int k, const double* L, int64_t ldl, double* X, int64_t ldx, hipStream_t st);
 cr_status tri_scale(int k, int mode, const double* X, int64_t ldx, const double* s, double* out,
                     int64_t ldo, hipStream_t st);
+
+// two-level coarse operator: A = lam (C2 + coef[0] C1 + coef[1] I) + Y diag(gw) Y^T
+// (Y may be null), and the lower-triangular inverse of a Cholesky factor
+// (X zero when info[0] != 0)
+cr_status coarse_assemble(int m, double lam, const double* coef, const double* C1,
+                          const double* C2, const double* Y, int ninj, const double* gw, double* A,
+                          hipStream_t st);
+cr_status trinv_rows(int k, const double* L, int64_t ldl, double* X, int64_t ldx,
+                     const double* info, hipStream_t st);
 
 // ---------------------------------------------------------------- small ops
 // out[i] = sum_k M[i + k*ldm] * v[k] * alpha  (i < m, k < kk), single block

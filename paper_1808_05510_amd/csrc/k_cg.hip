@@ -180,7 +180,7 @@ __device__ __forceinline__ double lap(const T* __restrict__ w, const int32_t* __
 }
 
 // partial X^T z over this workgroup's voxels, z staged in LDS
-template <typename T, int BS>
+template <typename T, int BS, bool CO = false>
 __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, int64_t n, int nwg,
                            double* lrpart, int al0 = 0) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -190,8 +190,9 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
     double acc = 0.0;
     for (int k = 0; k < per; ++k) {
       const int loc = lane + WAVE * k;
-      const int64_t i = lo + loc;
-      if (i < n) acc += (double)xc[i] * zs[loc];
+      // two-level launches: the slot's voxel (-1 for an idle slot)
+      const int64_t i = CO ? (int64_t)a.co.slot_vox[lo + loc] : lo + loc;
+      if (i >= 0 && i < n) acc += (double)xc[i] * zs[loc];
     }
     acc = wsum(acc);
     if (lane == 0) lrpart[(int64_t)al * nwg + blockIdx.x] = acc;
@@ -212,19 +213,67 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // for FP32 data (rows held in FP32, 128 registers).  XTAIL: more injections than NXR; the
 // first NXR rows are in registers and the rest are streamed (z staged in LDS
 // for their partials), which halves the X traffic at 128 injections.
-template <typename T, int K, bool LR, int VPT, int BS, int NXR, bool XTAIL = false>
+// CO (two-level, one voxel per thread): thread slots hold the voxels of whole
+// aggregates (CoarseArg); z = D^-1 r + P Ainv P^T r needs the restricted
+// residual of every workgroup, so each z update takes one more grid barrier
+// (four per iteration).
+template <typename T, int K, bool LR, int VPT, int BS, int NXR, bool XTAIL = false,
+          bool CO = false>
 __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   static_assert(!XTAIL || NXR > 0, "a streamed tail follows register rows");
   static_assert(NXR == 0 || (LR && VPT == 1), "register-resident X needs LR and VPT 1");
+  static_assert(!CO || VPT == 1, "two-level launches hold one voxel per thread");
   cgrp::grid_group grid = cgrp::this_grid();
   __shared__ double red[2 * BS / WAVE];
   __shared__ double redc[2 * BS / WAVE];  // phase C's own reduction slots (no leading barrier)
   __shared__ double zs[BS * VPT];
   __shared__ double slr[LR ? PCG_MAX_NINJ : 1];
   __shared__ double lred[NXR > 0 ? BS / WAVE : 1][NXR > 0 ? NXR : 1];
+  __shared__ double crs[CO ? BS : 1];         // w r of the workgroup's slots
+  __shared__ double cys[CO ? CO_MAXLOC : 1];  // Ainv rc of the workgroup's aggregates
   const int64_t n = a.g.n;
   const int nwg = gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * BS * VPT;
+  // voxel of this thread's slot m (two-level: from the slot map)
+  const int64_t co_vox = CO ? (int64_t)a.co.slot_vox[lo + threadIdx.x] : 0;
+  const double co_w = CO ? a.co.slot_w[lo + threadIdx.x] : 0.0;
+  const int co_a0 = CO ? a.co.wg_agg[blockIdx.x] : 0;
+  const int co_nla = CO ? a.co.wg_agg[blockIdx.x + 1] - co_a0 : 0;
+  const int co_la = CO ? (co_vox >= 0 ? a.co.slot_agg[lo + threadIdx.x] - co_a0 : -1) : -1;
+  auto vox = [&](int m) -> int64_t { return CO ? co_vox : lo + threadIdx.x + BS * m; };
+  // restriction: rc[a] = sum over the aggregate's slots of w r (the
+  // workgroup's own aggregates); starts and ends with a workgroup barrier
+  auto co_restrict = [&](double rv) {
+    if constexpr (CO) {
+      __syncthreads();
+      crs[threadIdx.x] = co_w * rv;
+      __syncthreads();
+      for (int la = threadIdx.x; la < co_nla; la += BS) {
+        const int ag = co_a0 + la;
+        double s = 0.0;
+        for (int q = a.co.agg_lo[ag]; q < a.co.agg_hi[ag]; ++q) s += crs[q];
+        a.co.rc[ag] = s;
+      }
+    }
+  };
+  // after a grid barrier: y = Ainv rc for the workgroup's aggregates (one
+  // wave per aggregate row), returns w y of this thread's aggregate
+  auto co_apply = [&]() -> double {
+    if constexpr (CO) {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      const int m = a.co.m;
+      for (int la = wv; la < co_nla; la += BS / WAVE) {
+        const double* row = a.co.Ainv + (int64_t)(co_a0 + la) * m;
+        double s = 0.0;
+        for (int b = lane; b < m; b += WAVE) s += row[b] * a.co.rc[b];
+        s = wsum(s);
+        if (lane == 0) cys[la] = s;
+      }
+      __syncthreads();
+      return co_la >= 0 ? co_w * cys[co_la] : 0.0;
+    }
+    return 0.0;
+  };
   double* part = a.part;
   double* lrpart = a.part + PCG_SLOTS * nwg;
   const double lam = a.lam;
@@ -247,10 +296,10 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       return (double)(xr[al] * (XR)zv);
   };
   if (NXR > 0) {
-    const int64_t i0 = lo + threadIdx.x;
+    const int64_t i0 = vox(0);
 #pragma unroll
     for (int al = 0; al < NXR; ++al)
-      xr[al] = (i0 < n && al < ninj) ? (XR)Xm[(int64_t)al * ldx + i0] : (XR)0;
+      xr[al] = (i0 >= 0 && i0 < n && al < ninj) ? (XR)Xm[(int64_t)al * ldx + i0] : (XR)0;
     for (int al = threadIdx.x; al < NXR; al += BS) slr[al] = 0.0;
   }
   // per-workgroup partials of X^T z into lrpart (z of this thread's voxels)
@@ -279,9 +328,9 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         for (int w = 0; w < BS / WAVE; ++w) t += lred[w][al];
         lrpart[(int64_t)al * nwg + blockIdx.x] = t;
       }
-      if constexpr (XTAIL) lr_partial<T, BS>(a, zs, lo, n, nwg, lrpart, NXR);
+      if constexpr (XTAIL) lr_partial<T, BS, CO>(a, zs, lo, n, nwg, lrpart, NXR);
     } else {
-      lr_partial<T, BS>(a, zs, lo, n, nwg, lrpart);
+      lr_partial<T, BS, CO>(a, zs, lo, n, nwg, lrpart);
     }
   };
 
@@ -291,8 +340,8 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   double rz = 0.0, bb = 0.0;
 #pragma unroll
   for (int m = 0; m < VPT; ++m) {
-    const int64_t i = lo + threadIdx.x + BS * m;
-    ok[m] = i < n;
+    const int64_t i = vox(m);
+    ok[m] = i >= 0 && i < n;
     double bi = 0.0;
     mi[m] = 0.0;
     dd[m] = 0.0;
@@ -307,7 +356,13 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
     }
     x[m] = (a.x0 && ok[m]) ? (double)a.x0[i] : 0.0;
     r[m] = (double)(T)bi;
-    z[m] = (double)(T)(mi[m] * r[m]);
+    double zc = 0.0;
+    if constexpr (CO) {
+      co_restrict(r[m]);
+      grid_barrier(a.bar, grid);
+      zc = co_apply();
+    }
+    z[m] = (double)(T)(mi[m] * r[m] + zc);
     p[m] = 0.0;
     t[m] = 0.0;
     if (ok[m]) zg[i] = (T)z[m];
@@ -342,7 +397,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         for (int k = 0; k < K; ++k) s -= (double)zg[nb[m][k]];
         p[m] = z[m];
         t[m] = (double)(T)s;
-        tg[lo + threadIdx.x + BS * m] = (T)t[m];
+        tg[vox(m)] = (T)t[m];
       }
     }
     if (LR) {
@@ -377,7 +432,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       for (int m = 0; m < VPT; ++m) {
         q[m] = 0.0;
         if (ok[m]) {
-          const int64_t i = lo + threadIdx.x + BS * m;
+          const int64_t i = vox(m);
           double lt = (double)K * t[m];
           if constexpr (VPT <= 2) {
 #pragma unroll
@@ -416,6 +471,23 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       }
       const double alpha = rz_cur / pq_tot;
       double rzn = 0.0, rrn = 0.0;
+      if constexpr (CO) {
+        // two-level: r first, its restriction to every workgroup, then z
+        if (ok[0]) {
+          x[0] = (double)(T)(x[0] + alpha * p[0]);
+          r[0] = (double)(T)(r[0] - alpha * q[0]);
+        }
+        co_restrict(r[0]);
+        grid_barrier(a.bar, grid);
+        const double zc = co_apply();
+        if (ok[0]) {
+          z[0] = (double)(T)(mi[0] * r[0] + zc);
+          zg[vox(0)] = (T)z[0];
+          rzn += r[0] * z[0];
+          rrn += r[0] * r[0];
+        }
+        if (LR && (NXR == 0 || XTAIL)) zs[threadIdx.x] = z[0];
+      } else {
 #pragma unroll
       for (int m = 0; m < VPT; ++m) {
         if (ok[m]) {
@@ -427,6 +499,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
           rrn += r[m] * r[m];
         }
         if (LR && (NXR == 0 || XTAIL)) zs[threadIdx.x + BS * m] = z[m];
+      }
       }
       if constexpr (LR && (NXR == 0 || XTAIL)) {
         __syncthreads();
@@ -513,7 +586,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
           }
           p[m] = (double)(T)(z[m] + beta * p[m]);
           t[m] = (double)(T)(lz + beta * t[m]);
-          tg[lo + threadIdx.x + BS * m] = (T)t[m];
+          tg[vox(m)] = (T)t[m];
         }
       }
       if (LR) {
@@ -545,7 +618,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   const double inv = xn > 0.0 ? 1.0 / xn : 0.0;
 #pragma unroll
   for (int m = 0; m < VPT; ++m) {
-    const int64_t i = lo + threadIdx.x + BS * m;
+    const int64_t i = vox(m);
     if (ok[m]) {
       a.x[i] = (T)x[m];
       a.xout[i] = (T)(x[m] * inv);
@@ -573,8 +646,33 @@ static void* pcg_fn_vb(int vpt) {
   }
 }
 
+// two-level launches (v-systems: low-rank term, one voxel per thread)
+template <typename T, int K>
+static void* pcg_fn_co(int bs, int nxr, int xtail) {
+  if (nxr == 0)
+    return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, 0, false, true>
+                     : bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, 0, false, true> : nullptr;
+  if (xtail)
+    return (nxr == PCG_NXR && bs == 512) ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR, true, true>
+                                          : nullptr;
+  if (nxr == PCG_NXR2) {
+    if constexpr (std::is_same<T, float>::value)
+      return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR2, false, true>
+                       : bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR2, false, true>
+                                  : nullptr;
+    return nullptr;
+  }
+  if (nxr != PCG_NXR) return nullptr;
+  return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR, false, true>
+                   : bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR, false, true> : nullptr;
+}
+
 template <typename T, int K, bool LR>
-static void* pcg_fn_v(int vpt, int bs, int nxr, int xtail) {
+static void* pcg_fn_v(int vpt, int bs, int nxr, int xtail, bool co) {
+  if (co) {
+    if (!LR || vpt != 1) return nullptr;
+    return pcg_fn_co<T, K>(bs, nxr, xtail);
+  }
   if (nxr > 0) {  // register-resident X: one voxel per thread, 256- or 512-thread groups
     if (!LR || vpt != 1) return nullptr;
     if (xtail) {  // 64 register rows and a streamed tail, 512-thread groups
@@ -596,12 +694,12 @@ static void* pcg_fn_v(int vpt, int bs, int nxr, int xtail) {
 }
 
 template <typename T>
-static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr, int xtail) {
+static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr, int xtail, bool co) {
   switch (K) {
 #define CASE(KK)                                                                     \
   case KK:                                                                           \
-    return lr ? pcg_fn_v<T, KK, true>(vpt, bs, nxr, xtail)                           \
-              : pcg_fn_v<T, KK, false>(vpt, bs, nxr, xtail);
+    return lr ? pcg_fn_v<T, KK, true>(vpt, bs, nxr, xtail, co)                       \
+              : pcg_fn_v<T, KK, false>(vpt, bs, nxr, xtail, co);
     CASE(2) CASE(4) CASE(6) CASE(8)
 #undef CASE
     default:
@@ -611,7 +709,8 @@ static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr, int xtail) {
 
 template <typename T>
 int pcg_max_wg(const PcgArgs<T>& a) {
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail,
+                           a.co.slot_vox != nullptr);
   if (!fn) return 0;
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -631,11 +730,12 @@ cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
     set_error("pcg: n_inj above the low-rank limit");
     return CR_EINVAL;
   }
-  if ((int64_t)nwg * a.bs * a.vpt < a.g.n) {
+  if (!a.co.slot_vox && (int64_t)nwg * a.bs * a.vpt < a.g.n) {
     set_error("pcg: grid does not cover the voxels");
     return CR_EINVAL;
   }
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail);
+  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail,
+                           a.co.slot_vox != nullptr);
   if (!fn) {
     set_error("pcg: unsupported stencil width or voxels per thread");
     return CR_EINVAL;

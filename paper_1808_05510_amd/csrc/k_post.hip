@@ -662,3 +662,65 @@ cr_status tri_scale(int k, int mode, const double* X, int64_t ldx, const double*
 }
 
 }  // namespace cr
+
+namespace cr {
+
+// ============================================================== two-level coarse operator
+// A = lam (C2 + c1 C1 + c0 I) + Y diag(gw) Y^T  (m x m, all column-major, Y m x ninj)
+__global__ __launch_bounds__(NT) void k_coarse_assemble(int m, double lam,
+                                                        const double* __restrict__ coef,
+                                                        const double* __restrict__ C1,
+                                                        const double* __restrict__ C2,
+                                                        const double* __restrict__ Y, int ninj,
+                                                        const double* __restrict__ gw,
+                                                        double* __restrict__ A) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  double v = lam * (C2[e] + coef[0] * C1[e] + (i == j ? coef[1] : 0.0));
+  if (Y)
+    for (int al = 0; al < ninj; ++al) v += Y[(int64_t)al * m + i] * gw[al] * Y[(int64_t)al * m + j];
+  A[e] = v;
+}
+
+// X = L^-1 for the lower triangle L of A (k x k), one workgroup, row by row:
+// X[i, i] = 1 / L_ii, X[i, j] = -(1 / L_ii) sum_{j <= q < i} L[i, q] X[q, j].
+// Skipped (X left zero) when info[0] reports a failed factorisation.
+__global__ __launch_bounds__(CH_NT) void k_trinv_rows(int k, const double* __restrict__ L,
+                                                      int64_t ldl, double* __restrict__ X,
+                                                      int64_t ldx,
+                                                      const double* __restrict__ info) {
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < (int64_t)k * k; e += CH_NT) X[(e / k) * ldx + e % k] = 0.0;
+  __syncthreads();
+  if (info[0] != 0.0) return;
+  for (int i = 0; i < k; ++i) {
+    const double inv = 1.0 / L[(int64_t)i * ldl + i];
+    for (int j = tid; j < i; j += CH_NT) {
+      double s = 0.0;
+      for (int q = j; q < i; ++q) s += L[(int64_t)q * ldl + i] * X[(int64_t)j * ldx + q];
+      X[(int64_t)j * ldx + i] = -inv * s;
+    }
+    if (tid == 0) X[(int64_t)i * ldx + i] = inv;
+    __syncthreads();
+  }
+}
+
+cr_status coarse_assemble(int m, double lam, const double* coef, const double* C1,
+                          const double* C2, const double* Y, int ninj, const double* gw, double* A,
+                          hipStream_t st) {
+  const int64_t mm = (int64_t)m * m;
+  hipLaunchKernelGGL(k_coarse_assemble, dim3((unsigned)((mm + NT - 1) / NT)), dim3(NT), 0, st, m,
+                     lam, coef, C1, C2, Y, ninj, gw, A);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+cr_status trinv_rows(int k, const double* L, int64_t ldl, double* X, int64_t ldx,
+                     const double* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_trinv_rows, dim3(1), dim3(CH_NT), 0, st, k, L, ldl, X, ldx, info);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+}  // namespace cr

@@ -14,8 +14,9 @@ passes, one counter each:
 dispatch) over the library kernels of the second call, scales each counter by
 copy bytes / counter reading of the copy, and writes STEM.md (table and the
 commands) and STEM.json (figures plus a hash of the code, comments and layout excluded, of
-the file that holds the kernels, so that a reader can tell whether they
-changed since the counters were taken).
+the file that holds the kernels and of the host function that launches them,
+so that a reader can tell whether they changed since the counters were
+taken).
 """
 from __future__ import annotations
 
@@ -31,8 +32,10 @@ COPY_BYTES = 256 * 1024 * 1024
 RANK = 100
 
 
-# the kernels that move op_apply's bytes (stencils, X^T V, masked product)
+# the kernels that move op_apply's bytes (stencils, X^T V, masked product),
+# and the host function that orders them (fork/join, launch order, grids)
 KERNEL_SOURCES = ("k_blas.hip",)
+ORCHESTRATION = ("api.hip", "static cr_status op_apply_run(", "static cr_status op_apply_impl(")
 
 
 def _code_only(src: str) -> str:
@@ -49,6 +52,12 @@ def sources_hash() -> str:
         with open(os.path.join(CSRC, name)) as f:
             h.update(name.encode())
             h.update(_code_only(f.read()).encode())
+    name, start, end = ORCHESTRATION
+    with open(os.path.join(CSRC, name)) as f:
+        src = f.read()
+    i, j = src.find(start), src.find(end)
+    h.update(name.encode())
+    h.update(_code_only(src[i:j] if 0 <= i < j else src).encode())
     return h.hexdigest()[:16]
 
 
