@@ -185,6 +185,11 @@ cr_status cr_als_step(cr_problem* p, int64_t r, const double* U, int64_t ldu, co
  * solves the projected equation for Z by matrix-valued CG in FP64 from the
  * warm start Z_io [dev] r x r (ldz) until
  *   ||U^T D V - A_p(Z)||_F <= rtol ||U^T D V||_F   or maxit iterations.
+ * Mixed-precision problems run the CG on a BF16 copy of the Gram tensor
+ * U^T diag(Omega_a) U inside iterative refinement: every correction step
+ * starts from the residual of the FP64 operator, and the stop above is
+ * tested on that residual, so the tolerance means the same in both
+ * precisions (iters_out then counts the CG steps of all corrections).
  * Z_io out = solution.  iters_out [host] may be NULL.  Synchronises.
  * Soft status CR_NOTCONV when maxit was hit. */
 cr_status cr_galerkin_project(cr_problem* p, int64_t r, const double* U, int64_t ldu,

@@ -106,6 +106,9 @@ struct cr_problem {
   bool pcg_warm = true;     // FP64 ALS half-steps warm-started (CONNREG_PCG_WARM=0: from zero)
   int bar_mode = 1;
   unsigned bar_spin = 1u << 22;  // grid-barrier poll bound (CONNREG_BAR_SPIN, for tests)
+  int gal_low = -1;  // projected CG on BF16 Grams with FP64 correction steps: -1 for mixed
+                     // problems, 0 never, 1 always (CONNREG_GAL_LOW)
+  int gal_tile = 0;  // projected CG output tiles: 0 by size, 16 or 32 (CONNREG_GAL_TILE)
   std::map<std::string, DevBuf> ws;
   std::vector<void*> owned;
 
@@ -157,6 +160,9 @@ const float* cr_problem::OY<float>() const { return OY32; }
 // this relative residual; CholQR2 needs factor widths k = n_inj + 3r <= KMAX
 constexpr double RESID_QR_SWITCH = 1e-6;
 constexpr int RESID_QR_KMAX = 1024;
+// with neither factor (both have more columns than rows, or dependent ones)
+// the residual's entries are formed when n_y n_x k is at most this
+constexpr double RESID_DENSE_MAX = 2e11;
 
 static int64_t gemm_part_cap(const cr_problem* P) {
   (void)P;
@@ -1293,6 +1299,17 @@ struct Ctx {
   }
 
   // ------------------------------------------------------------ Galerkin
+  // Projected CG (eq. Proj_Sylv) from the current Z.  FP64 form: one launch.
+  // Low form (BF16 copy of the Gram tensor): iterative refinement, each launch
+  // forms the residual with the FP64 operator and runs CG on the BF16 operator
+  // until that residual has dropped by GAL_LOW_INNER (or to rtol ||B||); the
+  // loop ends when a launch starts from a residual already at rtol ||B||.
+  // scal4: total iterations, relative residual (FP64 operator in the low
+  // form), status, energy.
+  static constexpr double GAL_LOW_INNER = 1e-3;
+  static constexpr int GAL_LOW_MAXOUTER = 40;
+  int last_gal_outer = 0;
+
   cr_status galerkin(int r, int64_t ldr, double rtol, int maxit, double* scal4) {
     const int64_t r2 = ldr * ldr;
     GalerkinArgs a{};
@@ -1313,15 +1330,22 @@ struct Ctx {
     a.Q = WS(double, "gQ", r2);
     a.Y2 = WS(double, "gY2", r2);
     a.Bm = WS(double, "gB", r2);
+    a.T = WS(double, "gT", ldr * ninj);
     a.SG = WS(double, "gSG", ldr * ninj);
     const int maxwg = galerkin_max_wg(r);
     if (maxwg <= 0) {
       set_error("cooperative launch not available for the Galerkin kernel");
       return CR_EHIP;
     }
-    int nwg = std::max(1, std::min(maxwg, std::max(ninj, r)));
+    // one workgroup per 16 x 16 output tile or per Gram block of 128 rows,
+    // at most two per CU
+    int ncu = 0;
+    CR_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->dev));
+    const int64_t nt16 = (r + 15) / 16, nrb = (r + 127) / 128;
+    const int64_t want = std::max<int64_t>(nt16 * nt16, (int64_t)ninj * nrb);
+    int nwg = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)maxwg, 2 * (int64_t)ncu, want}));
     if (P->cu_share > 0) nwg = std::max(1, std::min(nwg, share_cap(maxwg, P->cu_share)));
-    a.part = WS(double, "galpart", 6 * nwg);
+    a.part = WS(double, "galpart", 9 * nwg);
     a.scal = sc + 8;
     a.rtol = rtol;
     a.maxit = maxit;
@@ -1329,8 +1353,43 @@ struct Ctx {
     a.bar.mode = P->bar_mode;
     a.bar.coop = P->coop;
     a.bar.spin_max = P->bar_spin;
-    CR_TRY(galerkin_cg(a, nwg, st));
-    return read_scalars(sc + 8, 4, scal4);
+    const bool low = P->gal_low == 1 || (P->gal_low == -1 && !std::is_same<T, double>::value);
+    last_gal_outer = 1;
+    if (!low) {
+      CR_TRY(galerkin_cg(a, nwg, P->gal_tile / 16, st));
+      return read_scalars(sc + 8, 4, scal4);
+    }
+    const int ldh = (r + 3) / 4 * 4;
+    a.ldh = ldh;
+    a.Gb = WS(__bf16, "gGb", (int64_t)ninj * r * ldh);
+    CR_TRY(gram_to_bf16(r, (int)ldr, ldh, ninj, G, const_cast<__bf16*>(a.Gb), st));
+    a.inner_rel = GAL_LOW_INNER;
+    double tot = 0.0, s5[5] = {0, 0, 0, 0, 0};
+    int outer = 0;
+    for (; outer < GAL_LOW_MAXOUTER; ++outer) {
+      a.maxit = std::max(1, maxit - (int)tot);
+      CR_TRY(galerkin_cg(a, nwg, P->gal_tile / 16, st));
+      CR_TRY(read_scalars(sc + 8, 5, s5));
+      tot += s5[0];
+      if (s5[2] == PERSIST_TIMEOUT || s5[2] == 2.0) break;
+      // the launch started at the tolerance: Z is unchanged and s5[4] is its
+      // FP64 relative residual
+      if (s5[4] <= rtol || s5[0] == 0.0) {
+        s5[1] = s5[4];
+        s5[2] = s5[4] <= rtol ? 0.0 : 1.0;
+        break;
+      }
+      if (tot >= maxit) {
+        s5[2] = 1.0;
+        break;
+      }
+    }
+    last_gal_outer = outer + 1;
+    scal4[0] = tot;
+    scal4[1] = s5[1];
+    scal4[2] = s5[2];
+    scal4[3] = s5[3];
+    return CR_OK;
   }
 
   // ------------------------------------------------------------ residual norm
@@ -1401,9 +1460,11 @@ struct Ctx {
   // Upper factor R of a tall factor Fb (columns in blocks) from its Gram Gr
   // (k x k, preserved) by CholQR2 with column scaling: Gr = S^-1 A1 S^-1,
   // A1 = L1 L1^T, Q1 = Fb S L1^-T, Q1^T Q1 = L2 L2^T, R = L2^T L1^T S^-1.
-  // ok = false when a Cholesky pivot fails (columns too close to dependent).
+  // ok = false when a Cholesky pivot fails (columns too close to dependent,
+  // or more columns than rows).  *Fc_out: the factor in FP64 (n x k, kept
+  // under the tag), also on failure.
   cr_status cholqr2_r(int64_t n, const Blocks<T>& Fb, const double* Gr, int k, const char* tag,
-                      double* R, bool& ok) {
+                      double* R, bool& ok, double** Fc_out) {
     ok = false;
     const int64_t kk = (int64_t)k * k;
     const std::string t(tag);
@@ -1414,21 +1475,23 @@ struct Ctx {
     double* sv = WS(double, "qrs" + t, 2 * k + 8);
     double* info = sv + 2 * k;
     double* ones = sv + k;
-    double* Fc = WS(double, "qrFc", n * k);
+    double* Fc = WS(double, "qrFc" + t, n * k);
     double* Q = WS(double, "qrQ", n * k);
-    CR_TRY((convert2d<double, double>(k, k, Gr, k, A1, k, st)));
-    CR_TRY(diag_scale(k, A1, k, sv, st));
-    CR_TRY(chol_lower(k, A1, k, info, st));
-    double h;
-    CR_TRY(read_scalars(info, 1, &h));
-    if (h != 0.0) return CR_OK;
-    // Fc = the factor in FP64, then Q = Fc (L1^-1 diag(s))^T
     int off = 0;
     for (int b = 0; b < Fb.nb; ++b) {
       const int nc = Fb.col0[b + 1] - Fb.col0[b];
       CR_TRY((convert2d<double, T>(n, nc, Fb.p[b], Fb.ld[b], Fc + (int64_t)off * n, n, st)));
       off += nc;
     }
+    *Fc_out = Fc;
+    if (k > n) return CR_OK;
+    CR_TRY((convert2d<double, double>(k, k, Gr, k, A1, k, st)));
+    CR_TRY(diag_scale(k, A1, k, sv, st));
+    CR_TRY(chol_lower(k, A1, k, info, st));
+    double h;
+    CR_TRY(read_scalars(info, 1, &h));
+    if (h != 0.0) return CR_OK;
+    // Q = Fc (L1^-1 diag(s))^T
     CR_TRY(trinv_lower(k, A1, k, W1, k, st));
     CR_TRY(tri_scale(k, 0, W1, k, sv, W2, k, st));
     CR_TRY(tall_small(n, k, k, Fc, n, W2, k, true, 1.0, Q, n, st));
@@ -1492,14 +1555,41 @@ struct Ctx {
         double* RF = WS(double, "qrRF", k2);
         double* RG = WS(double, "qrRG", k2);
         bool okf = false, okg = false;
-        CR_TRY(cholqr2_r(ny, Fall, GF, k, "F", RF, okf));
-        if (okf) CR_TRY(cholqr2_r(nx, Gall, GX, k, "G", RG, okg));
+        double *Fc = nullptr, *Gc = nullptr;
+        CR_TRY(cholqr2_r(ny, Fall, GF, k, "F", RF, okf, &Fc));
+        CR_TRY(cholqr2_r(nx, Gall, GX, k, "G", RG, okg, &Gc));
+        // R = F Cm^T G^T (G_R = G Cm).  Both factors: ||R||_F =
+        // ||R_F Cm^T R_G^T||_F.  One: ||F (Cm^T R_G^T)||_F or
+        // ||G (Cm R_F^T)||_F, an n x k product.  Neither (more columns than
+        // rows on both sides, e.g. at full rank): the entries of R itself,
+        // when n_y n_x k is moderate; else the Gram value stands.
+        bool done = false;
+        const double* hsrc = tmp + 7;
         if (okf && okg) {
-          // R = F Cm^T G^T (G_R = G Cm), so ||R||_F = ||R_F Cm^T R_G^T||_F
           CR_TRY(small_gemm(k, k, k, Cm, k, true, RG, k, true, 1.0, M1, k, st));
           CR_TRY(small_gemm(k, k, k, RF, k, false, M1, k, false, 1.0, M2, k, st));
           CR_TRY(sumsq(k, k, M2, k, 1.0, part64, tmp + 7, st));
-          CR_TRY(read_scalars(tmp + 7, 1, &h));
+          done = true;
+        } else if (okf || okg) {
+          const int64_t n = okg ? ny : nx;
+          double* W = WS(double, "qrQ", n * k);
+          if (okg)
+            CR_TRY(small_gemm(k, k, k, Cm, k, true, RG, k, true, 1.0, M1, k, st));
+          else
+            CR_TRY(small_gemm(k, k, k, Cm, k, false, RF, k, true, 1.0, M1, k, st));
+          CR_TRY(tall_small(n, k, k, okg ? Fc : Gc, n, M1, k, false, 1.0, W, n, st));
+          CR_TRY(sumsq(n, k, W, n, 1.0, part64, tmp + 7, st));
+          done = true;
+        } else if ((double)ny * (double)nx * (double)k <= RESID_DENSE_MAX) {
+          double* W = WS(double, "qrQ", ny * k);
+          double* ep = WS(double, "qrEP", entry_stats_part_size(ny, nx) + 8);
+          CR_TRY(tall_small(ny, k, k, Fc, ny, Cm, k, true, 1.0, W, ny, st));  // F Cm^T
+          CR_TRY(entry_stats(ny, nx, k, W, ny, Gc, nx, ep + 8, ep, st));
+          hsrc = ep + 4;  // sum of the squared entries
+          done = true;
+        }
+        if (done) {
+          CR_TRY(read_scalars(hsrc, 1, &h));
           nr = std::sqrt(std::max(h, 0.0));
           last_resid_qr = true;
         }
@@ -1685,6 +1775,8 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
   if (const char* e = std::getenv("CONNREG_PCG_WARM")) P->pcg_warm = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_RESID_QR")) P->resid_qr = std::max(0, std::min(2, std::atoi(e)));
+  if (const char* e = std::getenv("CONNREG_GAL_LOW")) P->gal_low = std::max(-1, std::min(1, std::atoi(e)));
+  if (const char* e = std::getenv("CONNREG_GAL_TILE")) P->gal_tile = std::atoi(e);
   if (const char* e = std::getenv("CONNREG_BAR_SPIN"))
     P->bar_spin = (unsigned)std::max(1L, std::min(1L << 22, std::atol(e)));
   P->ny = d->Ly.n;

@@ -284,19 +284,29 @@ struct GalerkinArgs {
   int r, ldr, ninj;
   double lam;
   const double* G;    // ninj blocks of ldr*ldr (col-major r x r each)
+  const __bf16* Gb;   // optional BF16 copy (block al at al*r*ldh, rows padded to ldh, ldh % 4 == 0):
+                      // when set, the CG iterations use it; the initial residual always uses G
+  int ldh;
   const double* H;    // H = V^T X stored transposed: H(k,a) = H[a + k*ninj]
   const double* S;    // S = U^T (Omega o Y) stored the same way
   const double* By1; const double* By2; const double* Bx1; const double* Bx2;  // ld ldr
   double* Z;          // in/out, ld ldr
   double* R; double* P; double* Q; double* Y2; double* Bm;  // work, r x r (ld ldr)
+  double* T;          // work, r x ninj (ld ldr): P H
   double* SG;         // work, r x ninj (ld ldr)
-  double* part;       // >= 6*nwg
-  double* scal;       // out: [0] iters, [1] relres, [2] status, [3] energy
+  double* part;       // >= 9*nwg
+  double* scal;       // out: [0] iters, [1] relres, [2] status, [3] energy,
+                      //      [4] relres of the initial residual (FP64 operator)
   double rtol;
+  double inner_rel;   // also stop once ||R|| <= inner_rel ||R_0|| (0: off)
   int maxit;
   BarrierArg bar;
 };
-cr_status galerkin_cg(const GalerkinArgs& a, int nwg, hipStream_t st);
+// nb: output tiles of 16 nb x 16 nb (1 or 2; 0 chooses by r and nwg)
+cr_status galerkin_cg(const GalerkinArgs& a, int nwg, int nb, hipStream_t st);
+// Gb (ninj blocks of r x ldh BF16) = the r x r leading blocks of G, rounded
+cr_status gram_to_bf16(int r, int ld, int ldh, int ninj, const double* G, __bf16* Gb,
+                       hipStream_t st);
 int galerkin_max_wg(int r);
 
 // ---------------------------------------------------------------- learned preconditioner

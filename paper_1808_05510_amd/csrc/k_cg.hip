@@ -3,7 +3,7 @@
 //               ALS_linsys_v), one launch per solve, three grid barriers per
 //               iteration;
 //  * k_galerkin matrix-valued CG on the projected equation (eq. Proj_Sylv)
-//               in FP64, four grid barriers per iteration.
+//               in FP64 (FP64 MFMA tiles), four grid barriers per iteration.
 // Control flow is uniform over the grid: every workgroup reduces the same
 // partial sums in the same order, so all take identical branch decisions and
 // every grid barrier is reached by all workgroups; loops are bounded by maxit.
@@ -113,7 +113,8 @@ __device__ __forceinline__ void grid_barrier(const BarrierArg& b, cgrp::grid_gro
     const unsigned gen = __hip_atomic_load(b.bar + BAR_GEN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned prev =
         __hip_atomic_fetch_add(b.bar + BAR_COUNT, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == nwg - 1) {
+    const bool last = prev == nwg - 1;
+    if (last) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(b.bar + BAR_COUNT, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(b.bar + BAR_GEN, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -783,198 +784,440 @@ cr_status pcg_diag(const Geom& g, double lam, const double* coef, const T* dvec,
 }
 
 // ================================================================ Galerkin CG
-// Partial-sum slots: 0 <P,Q>, 1 initial ||R||^2, 2 ||R||^2, 3 ||B||^2,
-// 4 <Z,B>, 5 <Z,R> (6 * nwg doubles).
-// A_p(P) = lam (P Bx2 + 2 By1 P Bx1 + By2 P) + sum_a G_a (P h_a) h_a^T, with
-// h_a = H[:,a] (H(k,a) stored as Ht[a + k*ninj]).  Column c of every r x r
-// matrix is owned by workgroup c mod nwg for element-wise updates.
-__device__ __forceinline__ double Hk(const GalerkinArgs& a, int k, int al) {
-  return a.H[(int64_t)k * a.ninj + al];
-}
-__device__ __forceinline__ double Sk(const GalerkinArgs& a, int k, int al) {
-  return a.S[(int64_t)k * a.ninj + al];
+// A_p(P) = lam (P Bx2 + 2 By1 P Bx1 + By2 P) + sum_a G_a (P h_a) h_a^T with
+// h_a = H[:, a] (H(k, a) stored at H[a + k ninj]), all r x r column-major
+// with leading dimension ldr.  One operator application is three phases
+// separated by grid barriers:
+//   A: T = P H (r x ninj) and Y2 = By1 P (and, before the loop, B = S H^T);
+//   B: SG[:, a] = G_a T[:, a] for every injection (the Gram tensor, streamed
+//      once; optionally from a BF16 copy);
+//   C: Q = lam (P Bx2 + By2 P + 2 Y2 Bx1) + SG H^T, with the partial dot
+//      products CG needs.
+// The products of A and C are FP64 MFMA tiles (16 x 16 x 4): one output tile
+// per task, the four waves of a workgroup taking interleaved k-steps and
+// summing through LDS.  Phase C also sums <P,Q>, <R,Q>, <Q,Q> and <R,R> of
+// the current vectors, so ||R - alpha Q||^2 = <R,R> - 2 alpha <R,Q> +
+// alpha^2 <Q,Q> gives beta without a separate reduction, and the update
+// Z += alpha P, R -= alpha Q, P = R + beta P is one elementwise phase: four
+// grid barriers per iteration.  (<R,R> is summed afresh each step: carried
+// over from the previous expansion, its rounding error would stay at
+// eps ||R_0||^2 and swamp the later steps.)  Partial-sum slots (9 nwg
+// doubles): 0 <P,Q>, 1 <R,Q>, 2 <Q,Q>, 3 <R,R>, 4 initial ||R||^2,
+// 5 ||B||^2, 6 <Z,B>, 7 <Z,R>, 8 final ||R||^2.
+namespace galk {
+
+constexpr int NW = NT / WAVE;  // waves per workgroup
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+// v_mfma_f64_16x16x4f64: lane l supplies A(row l % 16, k l / 16) and
+// B(k l / 16, col l % 16); result element e of lane l is
+// D(row l / 16 + 4 e, col l % 16).
+__device__ __forceinline__ dbl4 mfma64(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// phase 1: SG[:,a] = G_a (P h_a) for the workgroup's injections; Y2 = By1 P
-// for its columns.
-__device__ void gal_phase1(const GalerkinArgs& a, const double* Pm, double* tsh) {
+// Wave wv's share (k-steps wv, wv + 4, ...) of C(tile) += s A B over k < K.
+// AROW: A(i, k) = A[i lda + k], else A[k lda + i]; BROW: B(k, j) = B[k ldb + j],
+// else B[j ldb + k].  Tile rows i0 .. i0 + 16 NB - 1 (< m), columns j0 ..
+// (< n); lane l supplies A(row l % 16, k l / 16) and B(k l / 16, col l % 16).
+template <int NB, bool AROW, bool BROW>
+__device__ __forceinline__ void tile_acc(dbl4 (&acc)[NB][NB], const double* __restrict__ A,
+                                         int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                         int K, double s, int i0, int j0, int m, int n) {
+  constexpr int UNR = 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  const int nst = (K + 3) >> 2;
+  bool aok[NB], bok[NB];
+  int ia[NB], jb[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    ia[t] = i0 + 16 * t + fr;
+    jb[t] = j0 + 16 * t + fr;
+    aok[t] = ia[t] < m;
+    bok[t] = jb[t] < n;
+  }
+  for (int st0 = wv; st0 < nst; st0 += NW * UNR) {
+    double av[UNR][NB], bv[UNR][NB];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int k = 4 * (st0 + NW * u) + fk;
+      const bool kok = k < K;
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const int64_t ea = AROW ? (int64_t)ia[t] * lda + k : (int64_t)k * lda + ia[t];
+        const int64_t eb = BROW ? (int64_t)k * ldb + jb[t] : (int64_t)jb[t] * ldb + k;
+        av[u][t] = (kok && aok[t]) ? A[ea] * s : 0.0;
+        bv[u][t] = (kok && bok[t]) ? B[eb] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = mfma64(av[u][a], bv[u][b], acc[a][b]);
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void acc_zero(dbl4 (&acc)[NB][NB]) {
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Sums the four waves' tiles through LDS and calls f(row, col, value) once per
+// tile entry inside the m x n bounds (entries spread over the workgroup).
+template <int NB, typename F>
+__device__ __forceinline__ void tile_reduce(const dbl4 (&acc)[NB][NB], double* lds, int i0,
+                                            int j0, int m, int n, F&& f) {
+  constexpr int Q = NB * NB * 4;  // doubles per lane
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) lds[((wv * Q) + (a * NB + b) * 4 + e) * WAVE + lane] = acc[a][b][e];
+  __syncthreads();
+#pragma unroll
+  for (int q0 = 0; q0 < Q * WAVE; q0 += NT) {
+    const int idx = q0 + threadIdx.x;
+    const int ln = idx & 63, q = idx >> 6;
+    const int blk = q >> 2, e = q & 3;
+    const int a = blk / NB, b = blk % NB;
+    const int row = i0 + 16 * a + (ln >> 4) + 4 * e;
+    const int col = j0 + 16 * b + (ln & 15);
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += lds[(w * Q + q) * WAVE + ln];
+    if (row < m && col < n) f(row, col, v);
+  }
+  __syncthreads();
+}
+
+// Phase A.  INIT additionally forms B = S H^T into Bm.
+template <int NB, bool INIT>
+__device__ void phase_a(const GalerkinArgs& a, const double* Xm, double* lds) {
+  constexpr int TS = 16 * NB;
+  const int r = a.r, ld = a.ldr, ni = a.ninj;
+  const int nt = (r + TS - 1) / TS, nti = (ni + TS - 1) / TS;
+  const int ny2 = nt * nt, nT = nt * nti;
+  const int ntask = ny2 + nT + (INIT ? ny2 : 0);
+  for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
+    dbl4 acc[NB][NB];
+    acc_zero(acc);
+    if (t < ny2) {  // Y2 = By1 X
+      const int i0 = (t % nt) * TS, j0 = (t / nt) * TS;
+      tile_acc<NB, false, false>(acc, a.By1, ld, Xm, ld, r, 1.0, i0, j0, r, r);
+      tile_reduce(acc, lds, i0, j0, r, r,
+                  [&](int i, int j, double v) { a.Y2[(int64_t)j * ld + i] = v; });
+    } else if (t < ny2 + nT) {  // T = X H
+      const int u = t - ny2;
+      const int i0 = (u % nt) * TS, j0 = (u / nt) * TS;
+      tile_acc<NB, false, true>(acc, Xm, ld, a.H, ni, r, 1.0, i0, j0, r, ni);
+      tile_reduce(acc, lds, i0, j0, r, ni,
+                  [&](int i, int j, double v) { a.T[(int64_t)j * ld + i] = v; });
+    } else {  // B = S H^T: S(i, c) = S[i ninj + c], H^T(c, j) = H[j ninj + c]
+      const int u = t - ny2 - nT;
+      const int i0 = (u % nt) * TS, j0 = (u / nt) * TS;
+      tile_acc<NB, true, false>(acc, a.S, ni, a.H, ni, ni, 1.0, i0, j0, r, r);
+      tile_reduce(acc, lds, i0, j0, r, r,
+                  [&](int i, int j, double v) { a.Bm[(int64_t)j * ld + i] = v; });
+    }
+  }
+}
+
+// Phase B: SG[:, al] = G_al T[:, al].  FP64 Grams: task (injection, block of
+// 128 rows), lane l owns rows l and l + 64, wave wv the k-steps wv, wv + 4, ...
+// (so each load instruction reads 512 contiguous bytes of one Gram column).
+// BF16 Grams (Gb, rows padded to ldh, block al at al r ldh): blocks of 256
+// rows, lane l owns rows 4l .. 4l + 3 (one 8-byte load).
+template <bool LOW>
+__device__ void phase_b(const GalerkinArgs& a, double* lds) {
   const int r = a.r, ld = a.ldr;
-  for (int al = blockIdx.x; al < a.ninj; al += gridDim.x) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int ROWS = LOW ? 256 : 128;
+  constexpr int PER = ROWS / WAVE;
+  const int nrb = (r + ROWS - 1) / ROWS;
+  const int ntask = a.ninj * nrb;
+  for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
+    const int al = t / nrb, rb = t % nrb;
+    const int row0 = rb * ROWS;
+    const double* tv = a.T + (int64_t)al * ld;
+    double acc[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) acc[p] = 0.0;
+    if constexpr (LOW) {
+      const int ldh = a.ldh;
+      const int rowq = row0 + 4 * lane;  // < ldh when row0 + 4 lane < r (ldh >= r, ldh % 4 == 0)
+      const bool ok = rowq < r;
+      const __bf16* g = a.Gb + (int64_t)al * r * ldh + rowq;
+      constexpr int UNR = 8;
+      for (int k0 = wv; k0 < r; k0 += NW * UNR) {
+        uint2 w[UNR];
+        double tk[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int k = k0 + NW * u;
+          const bool kk = k < r;
+          w[u] = (kk && ok) ? *reinterpret_cast<const uint2*>(g + (int64_t)k * ldh) : uint2{0u, 0u};
+          tk[u] = kk ? tv[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          // a BF16 value is the high half of the FP32 with the same bits
+          acc[0] += (double)__uint_as_float(w[u].x << 16) * tk[u];
+          acc[1] += (double)__uint_as_float(w[u].x & 0xffff0000u) * tk[u];
+          acc[2] += (double)__uint_as_float(w[u].y << 16) * tk[u];
+          acc[3] += (double)__uint_as_float(w[u].y & 0xffff0000u) * tk[u];
+        }
+      }
+    } else {
+      const double* g = a.G + (int64_t)al * ld * ld;
+      bool ok[PER];
+#pragma unroll
+      for (int p = 0; p < PER; ++p) ok[p] = row0 + lane + WAVE * p < r;
+      constexpr int UNR = 8;
+      for (int k0 = wv; k0 < r; k0 += NW * UNR) {
+        double gv[UNR][PER], tk[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int k = k0 + NW * u;
+          const bool kk = k < r;
+          tk[u] = kk ? tv[k] : 0.0;
+#pragma unroll
+          for (int p = 0; p < PER; ++p)
+            gv[u][p] = (kk && ok[p]) ? g[(int64_t)k * ld + row0 + lane + WAVE * p] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+          for (int p = 0; p < PER; ++p) acc[p] += gv[u][p] * tk[u];
+      }
+    }
+    // sum the four waves (row index = the lane's rows)
+#pragma unroll
+    for (int p = 0; p < PER; ++p) lds[(wv * PER + p) * WAVE + lane] = acc[p];
     __syncthreads();
-    for (int i = threadIdx.x; i < r; i += NT) {
-      double s = 0.0;
-      for (int k = 0; k < r; ++k) s += Pm[(int64_t)k * ld + i] * Hk(a, k, al);
-      tsh[i] = s;
+    for (int q = threadIdx.x; q < ROWS; q += NT) {
+      // q enumerates (p, lane) as stored: row of entry (p, ln)
+      const int p = q / WAVE, ln = q % WAVE;
+      const int row = LOW ? row0 + 4 * ln + p : row0 + ln + WAVE * p;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v += lds[(w * PER + p) * WAVE + ln];
+      if (row < r) a.SG[(int64_t)al * ld + row] = v;
     }
     __syncthreads();
-    const double* Ga = a.G + (int64_t)al * ld * ld;
-    for (int i = threadIdx.x; i < r; i += NT) {
-      double s = 0.0;
-      for (int k = 0; k < r; ++k) s += Ga[(int64_t)k * ld + i] * tsh[k];
-      a.SG[(int64_t)al * ld + i] = s;
-    }
   }
-  for (int c = blockIdx.x; c < r; c += gridDim.x) {
-    for (int i = threadIdx.x; i < r; i += NT) {
-      double s = 0.0;
-      for (int k = 0; k < r; ++k) s += a.By1[(int64_t)k * ld + i] * Pm[(int64_t)c * ld + k];
-      a.Y2[(int64_t)c * ld + i] = s;
+}
+
+// Phase C: Q tiles.  INIT: R = B - Q, P = R, partial ||R||^2 and ||B||^2
+// (slots 4, 5); else Q stored with partial <P,Q>, <R,Q>, <Q,Q>, <R,R>
+// (slots 0-3).
+template <int NB, bool INIT>
+__device__ void phase_c(const GalerkinArgs& a, const double* Xm, double* lds, double* red) {
+  constexpr int TS = 16 * NB;
+  const int r = a.r, ld = a.ldr, ni = a.ninj;
+  const int nt = (r + TS - 1) / TS;
+  const double lam = a.lam;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int t = blockIdx.x; t < nt * nt; t += gridDim.x) {
+    const int i0 = (t % nt) * TS, j0 = (t / nt) * TS;
+    dbl4 acc[NB][NB];
+    acc_zero(acc);
+    tile_acc<NB, false, false>(acc, Xm, ld, a.Bx2, ld, r, lam, i0, j0, r, r);
+    tile_acc<NB, false, false>(acc, a.By2, ld, Xm, ld, r, lam, i0, j0, r, r);
+    tile_acc<NB, false, false>(acc, a.Y2, ld, a.Bx1, ld, r, 2.0 * lam, i0, j0, r, r);
+    // SG H^T: SG(i, c) = SG[c ld + i], H^T(c, j) = H[j ninj + c]
+    tile_acc<NB, false, false>(acc, a.SG, ld, a.H, ni, ni, 1.0, i0, j0, r, r);
+    tile_reduce(acc, lds, i0, j0, r, r, [&](int i, int j, double q) {
+      const int64_t e = (int64_t)j * ld + i;
+      if (INIT) {
+        const double b = a.Bm[e];
+        const double rv = b - q;
+        a.R[e] = rv;
+        a.P[e] = rv;
+        s0 += rv * rv;
+        s1 += b * b;
+      } else {
+        const double rv = a.R[e];
+        a.Q[e] = q;
+        s0 += a.P[e] * q;
+        s1 += rv * q;
+        s2 += q * q;
+        s3 += rv * rv;
+      }
+    });
+  }
+  const int nwg = gridDim.x;
+  if (INIT) {
+    block_sum2(s0, s1, red);
+    if (threadIdx.x == 0) {
+      a.part[4 * nwg + blockIdx.x] = s0;
+      a.part[5 * nwg + blockIdx.x] = s1;
+    }
+  } else {
+    block_sum2(s0, s1, red);
+    block_sum2(s2, s3, red + 2 * NW);
+    if (threadIdx.x == 0) {
+      a.part[0 * nwg + blockIdx.x] = s0;
+      a.part[1 * nwg + blockIdx.x] = s1;
+      a.part[2 * nwg + blockIdx.x] = s2;
+      a.part[3 * nwg + blockIdx.x] = s3;
     }
   }
 }
 
-// phase 2: Q[:,c] for the workgroup's columns; returns partial <Pm, Q>.
-__device__ double gal_phase2(const GalerkinArgs& a, const double* Pm) {
-  const int r = a.r, ld = a.ldr;
-  double dot = 0.0;
-  for (int c = blockIdx.x; c < r; c += gridDim.x) {
-    for (int i = threadIdx.x; i < r; i += NT) {
-      double s = 0.0;
-      for (int al = 0; al < a.ninj; ++al) s += a.SG[(int64_t)al * ld + i] * Hk(a, c, al);
-      double t = 0.0;
-      for (int k = 0; k < r; ++k)
-        t += Pm[(int64_t)k * ld + i] * a.Bx2[(int64_t)c * ld + k] +
-             a.By2[(int64_t)k * ld + i] * Pm[(int64_t)c * ld + k] +
-             2.0 * a.Y2[(int64_t)k * ld + i] * a.Bx1[(int64_t)c * ld + k];
-      const double q = s + a.lam * t;
-      a.Q[(int64_t)c * ld + i] = q;
-      dot += Pm[(int64_t)c * ld + i] * q;
-    }
-  }
-  return dot;
+// Q = A_p(X) in three phases (INIT: from X = Z, also B and R = B - Q).
+template <int NB, bool INIT>
+__device__ __forceinline__ void apply(const GalerkinArgs& a, const double* Xm, bool low,
+                                      double* lds, double* red, cgrp::grid_group& grid) {
+  phase_a<NB, INIT>(a, Xm, lds);
+  grid_barrier(a.bar, grid);
+  if (low)
+    phase_b<true>(a, lds);
+  else
+    phase_b<false>(a, lds);
+  grid_barrier(a.bar, grid);
+  phase_c<NB, INIT>(a, Xm, lds, red);
+  grid_barrier(a.bar, grid);
 }
 
+}  // namespace galk
+
+template <int NB>
 __global__ __launch_bounds__(NT) void k_galerkin(GalerkinArgs a) {
+  using namespace galk;
   cgrp::grid_group grid = cgrp::this_grid();
-  __shared__ double red[NT / WAVE];
-  extern __shared__ double tsh[];
+  __shared__ double lds[NW * NB * NB * 4 * WAVE > NW * 4 * WAVE ? NW * NB * NB * 4 * WAVE
+                                                               : NW * 4 * WAVE];
+  __shared__ double red[4 * NW];
   const int r = a.r, ld = a.ldr, nwg = gridDim.x;
+  const int64_t nel = (int64_t)r * r;
+  const int64_t gtid = (int64_t)blockIdx.x * NT + threadIdx.x, gstride = (int64_t)nwg * NT;
   double* part = a.part;
 
-  // ---- B = S H^T ; Q = A_p(Z)
-  gal_phase1(a, a.Z, tsh);
-  for (int c = blockIdx.x; c < r; c += nwg)
-    for (int i = threadIdx.x; i < r; i += NT) {
-      double s = 0.0;
-      for (int al = 0; al < a.ninj; ++al) s += Sk(a, i, al) * Hk(a, c, al);
-      a.Bm[(int64_t)c * ld + i] = s;
-    }
-  grid_barrier(a.bar, grid);
-  gal_phase2(a, a.Z);
-  // R = B - Q, P = R (own columns); partial ||R||^2, ||B||^2
-  double rr = 0.0, bb = 0.0;
-  for (int c = blockIdx.x; c < r; c += nwg)
-    for (int i = threadIdx.x; i < r; i += NT) {
-      const int64_t e = (int64_t)c * ld + i;
-      const double b = a.Bm[e];
-      const double rv = b - a.Q[e];
-      a.R[e] = rv;
-      a.P[e] = rv;
-      rr += rv * rv;
-      bb += b * b;
-    }
-  rr = block_sum(rr, red);
-  bb = block_sum(bb, red);
-  if (threadIdx.x == 0) {
-    part[1 * nwg + blockIdx.x] = rr;
-    part[3 * nwg + blockIdx.x] = bb;
-  }
-  grid_barrier(a.bar, grid);
-  rr = grid_total(part, 1, nwg, red);
-  bb = grid_total(part, 3, nwg, red);
-  const double tol2 = a.rtol * a.rtol * bb;
+  // ---- B = S H^T, R = B - A_p(Z) with the FP64 Grams, P = R
+  apply<NB, true>(a, a.Z, false, lds, red, grid);
+  double rr, bb;
+  grid_total2<NT, false>(part, 4, 5, nwg, red, rr, bb);
+  const double rr0 = rr;
+  const double tol2 = fmax(a.rtol * a.rtol * bb, a.inner_rel * a.inner_rel * rr0);
+  const bool low = a.Gb != nullptr;
   int it = 0, status = 0;
   for (; it < a.maxit && rr > tol2; ++it) {
-    gal_phase1(a, a.P, tsh);
-    grid_barrier(a.bar, grid);
-    double pq = gal_phase2(a, a.P);
-    pq = block_sum(pq, red);
-    if (threadIdx.x == 0) part[0 * nwg + blockIdx.x] = pq;
-    grid_barrier(a.bar, grid);
-    const double pq_tot = grid_total(part, 0, nwg, red);
-    if (!(pq_tot > 0.0)) {
+    apply<NB, false>(a, a.P, low, lds, red, grid);
+    double pq, rq, qq;
+    grid_total2<NT, false>(part, 0, 1, nwg, red, pq, rq);
+    grid_total2(part, 2, 3, nwg, red, qq, rr);
+    if (!(pq > 0.0)) {
       status = 2;
       break;
     }
-    const double alpha = rr / pq_tot;
-    double rrn = 0.0;
-    for (int c = blockIdx.x; c < r; c += nwg)
-      for (int i = threadIdx.x; i < r; i += NT) {
-        const int64_t e = (int64_t)c * ld + i;
-        a.Z[e] += alpha * a.P[e];
-        const double rv = a.R[e] - alpha * a.Q[e];
-        a.R[e] = rv;
-        rrn += rv * rv;
-      }
-    rrn = block_sum(rrn, red);
-    if (threadIdx.x == 0) part[2 * nwg + blockIdx.x] = rrn;
-    grid_barrier(a.bar, grid);
-    const double rr_new = grid_total(part, 2, nwg, red);
+    const double alpha = rr / pq;
+    const double rr_new = fmax(rr - 2.0 * alpha * rq + alpha * alpha * qq, 0.0);
     const double beta = rr_new / rr;
-    rr = rr_new;
-    if (rr <= tol2) {
-      ++it;
-      break;
+    for (int64_t q = gtid; q < nel; q += gstride) {
+      const int64_t e = (q / r) * ld + q % r;
+      const double p = a.P[e];
+      a.Z[e] += alpha * p;
+      const double rv = a.R[e] - alpha * a.Q[e];
+      a.R[e] = rv;
+      a.P[e] = rv + beta * p;
     }
-    for (int c = blockIdx.x; c < r; c += nwg)
-      for (int i = threadIdx.x; i < r; i += NT) {
-        const int64_t e = (int64_t)c * ld + i;
-        a.P[e] = a.R[e] + beta * a.P[e];
-      }
+    rr = rr_new;
     grid_barrier(a.bar, grid);
   }
   if (status == 0 && rr > tol2) status = 1;
-  // energy pieces: <Z, B>, <Z, R>
-  double zb = 0.0, zr = 0.0;
-  for (int c = blockIdx.x; c < r; c += nwg)
-    for (int i = threadIdx.x; i < r; i += NT) {
-      const int64_t e = (int64_t)c * ld + i;
-      zb += a.Z[e] * a.Bm[e];
-      zr += a.Z[e] * a.R[e];
-    }
-  zb = block_sum(zb, red);
-  zr = block_sum(zr, red);
-  // slots 4, 5 are written only here (slower workgroups may still be reading
-  // slots 0..3 of the exit test)
+  // energy pieces <Z,B>, <Z,R> and the final ||R||^2 (slots 6-8)
+  double zb = 0.0, zr = 0.0, rf = 0.0;
+  for (int64_t q = gtid; q < nel; q += gstride) {
+    const int64_t e = (q / r) * ld + q % r;
+    const double z = a.Z[e], rv = a.R[e];
+    zb += z * a.Bm[e];
+    zr += z * rv;
+    rf += rv * rv;
+  }
+  block_sum2(zb, zr, red);
+  rf = block_sum(rf, red + 2 * NW);
   if (threadIdx.x == 0) {
-    part[4 * nwg + blockIdx.x] = zb;
-    part[5 * nwg + blockIdx.x] = zr;
+    part[6 * nwg + blockIdx.x] = zb;
+    part[7 * nwg + blockIdx.x] = zr;
+    part[8 * nwg + blockIdx.x] = rf;
   }
   grid_barrier(a.bar, grid);
-  zb = grid_total(part, 4, nwg, red);
-  zr = grid_total(part, 5, nwg, red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.scal[0] = (double)it;
-    a.scal[1] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-    const bool timed_out =
-        a.bar.mode == 1 &&
-        __hip_atomic_load(a.bar.bar + BAR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-    a.scal[2] = timed_out ? PERSIST_TIMEOUT : (double)status;
-    a.scal[3] = -0.5 * zb - 0.5 * zr;  // 1/2 <Z, A_p Z> - <Z, B> with A_p Z = B - R
+  if (blockIdx.x == 0) {
+    grid_total2<NT, false>(part, 6, 7, nwg, red, zb, zr);
+    rf = grid_total(part, 8, nwg, red);
+    if (threadIdx.x == 0) {
+      a.scal[0] = (double)it;
+      a.scal[1] = bb > 0.0 ? sqrt(rf / bb) : 0.0;
+      const bool timed_out =
+          a.bar.mode == 1 &&
+          __hip_atomic_load(a.bar.bar + BAR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+      a.scal[2] = timed_out ? PERSIST_TIMEOUT : (double)status;
+      a.scal[3] = -0.5 * zb - 0.5 * zr;  // 1/2 <Z, A_p Z> - <Z, B> with A_p Z = B - R
+      a.scal[4] = bb > 0.0 ? sqrt(rr0 / bb) : 0.0;
+    }
   }
+}
+
+// Output tiles of 32 x 32 once there are enough of them to give every
+// workgroup one; 16 x 16 below.
+static int gal_nb(int r, int nwg) {
+  const int nt32 = (r + 31) / 32;
+  return nt32 * nt32 >= nwg ? 2 : 1;
 }
 
 int galerkin_max_wg(int r) {
-  int dev = 0, ncu = 0, per = 0;
+  int dev = 0, ncu = 0, p1 = 0, p2 = 0;
+  (void)r;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (void*)k_galerkin, NT,
-                                                   sizeof(double) * std::max(r, 1)) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p1, (void*)k_galerkin<1>, NT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p2, (void*)k_galerkin<2>, NT, 0) != hipSuccess)
     return 0;
-  return per * ncu;
+  return std::min(p1, p2) * ncu;
 }
 
-cr_status galerkin_cg(const GalerkinArgs& a, int nwg, hipStream_t st) {
+__global__ __launch_bounds__(NT) void k_gram_bf16(int r, int ld, int ldh, int ninj,
+                                                  const double* __restrict__ G,
+                                                  __bf16* __restrict__ Gb) {
+  const int64_t n = (int64_t)ninj * r * ldh;
+  for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < n; q += (int64_t)gridDim.x * NT) {
+    const int row = (int)(q % ldh);
+    const int64_t ak = q / ldh;  // al r + k
+    const int k = (int)(ak % r), al = (int)(ak / r);
+    const double v = row < r ? G[((int64_t)al * ld + k) * ld + row] : 0.0;
+    Gb[q] = (__bf16)(float)v;
+  }
+}
+
+cr_status gram_to_bf16(int r, int ld, int ldh, int ninj, const double* G, __bf16* Gb,
+                       hipStream_t st) {
+  const int64_t n = (int64_t)ninj * r * ldh;
+  if (n == 0) return CR_OK;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 8192);
+  hipLaunchKernelGGL(k_gram_bf16, dim3(nb), dim3(NT), 0, st, r, ld, ldh, ninj, G, Gb);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
+cr_status galerkin_cg(const GalerkinArgs& a, int nwg, int nb, hipStream_t st) {
   if (a.r <= 0) return CR_OK;
   GalerkinArgs arg = a;
   if (arg.bar.mode == 1) CR_HIP(hipMemsetAsync(arg.bar.bar, 0, BAR_WORDS * sizeof(unsigned), st));
   void* params[] = {&arg};
+  if (nb != 1 && nb != 2) nb = gal_nb(a.r, nwg);
+  const void* fn = nb == 2 ? (const void*)k_galerkin<2> : (const void*)k_galerkin<1>;
   if (!arg.bar.coop && arg.bar.mode == 1)
-    CR_HIP(hipLaunchKernel((void*)k_galerkin, dim3(nwg), dim3(NT), params, sizeof(double) * a.r, st));
+    CR_HIP(hipLaunchKernel(fn, dim3(nwg), dim3(NT), params, 0, st));
   else
-    CR_HIP(hipLaunchCooperativeKernel((void*)k_galerkin, dim3(nwg), dim3(NT), params,
-                                    sizeof(double) * a.r, st));
+    CR_HIP(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(NT), params, 0, st));
   return CR_OK;
 }
 

@@ -31,7 +31,17 @@ def mid_box():
                              sigma=1.5, hole_r=1.5, wt_rank=4, wt_w=(2.0, 4.0), lam=30.0, seed=4)
 
 
-@pytest.mark.parametrize("maker,r", [(synth.config1, 5), (mid_box, 12), (mid_box, 40)])
+def small_target_box():
+    """mid_box with the two grids swapped in size: 504 target, 990 source voxels."""
+    return synth.box_problem(box_y=(8, 7, 9), box_x=(11, 10, 9), offset=(0, 0, 0), n_inj=37,
+                             sigma=1.5, hole_r=1.5, wt_rank=4, wt_w=(2.0, 4.0), lam=30.0, seed=4)
+
+
+# r = 160 (k = 37 + 3 r = 517 columns): on mid_box the source-side factor has
+# more columns than its 504 rows, so only the target side has a CholQR2
+# factor; on small_target_box the other way round
+@pytest.mark.parametrize("maker,r", [(synth.config1, 5), (mid_box, 12), (mid_box, 40),
+                                     (mid_box, 160), (small_target_box, 160)])
 def test_residual_norm_cholqr2_matches_oracle(monkeypatch, maker, r):
     monkeypatch.setenv("CONNREG_RESID_QR", "2")
     d = maker()
@@ -53,7 +63,9 @@ def test_greedy_tiny_relres_at_full_rank(prec):
     """The 40-voxel toy to its full rank 40, where W = W*.  In FP64 the
     relative residual falls to rounding level and the solve stops on
     tau_res = 1e-10; in mixed precision the FP32 storage of the bases sets a
-    floor near 1e-6, which the library's relres must report faithfully."""
+    floor near 1e-6, which the library's relres must report faithfully.
+    Near full rank both residual factors have more columns than rows, so the
+    library forms the residual's entries."""
     d = synth.config1_small(seed=0)
     P = oop.problem_from_arrays(d)
     g = connreg.Problem(d, prec, DEV)
