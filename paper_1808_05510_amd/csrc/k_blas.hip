@@ -1182,35 +1182,74 @@ cr_status small_gemv(int m, int kk, const double* M, int64_t ldm, bool trans, co
   return CR_OK;
 }
 
+// C = alpha op(A) op(B) on FP64 MFMA: a workgroup per 64 x 64 tile of C,
+// wave w the 32 x 32 quadrant (w % 2, w / 2) as 2 x 2 blocks of 16 x 16 x 4;
+// fragments straight from memory (the operands are small enough for L2),
+// four k-steps of loads in flight ahead of their MFMAs.  A(i, t) =
+// A[i sa_i + t sa_t], B(t, j) = B[t sb_t + j sb_j].
 __global__ __launch_bounds__(NT) void k_small_gemm(int m, int n, int k, const double* __restrict__ A,
-                                                   int64_t lda, int ta, const double* __restrict__ B,
-                                                   int64_t ldb, int tb, double alpha,
+                                                   int64_t sa_i, int64_t sa_t,
+                                                   const double* __restrict__ B, int64_t sb_t,
+                                                   int64_t sb_j, double alpha,
                                                    double* __restrict__ C, int64_t ldc) {
-  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (e >= (int64_t)m * n) return;
-  const int i = (int)(e % m), j = (int)(e / m);
-  const int64_t sa_i = ta ? lda : 1, sa_t = ta ? 1 : lda;
-  const int64_t sb_t = tb ? ldb : 1, sb_j = tb ? 1 : ldb;
-  const double* a = A + i * sa_i;
-  const double* b = B + j * sb_j;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int t = 0;
-  for (; t + 4 <= k; t += 4) {
-    s0 += a[t * sa_t] * b[t * sb_t];
-    s1 += a[(t + 1) * sa_t] * b[(t + 1) * sb_t];
-    s2 += a[(t + 2) * sa_t] * b[(t + 2) * sb_t];
-    s3 += a[(t + 3) * sa_t] * b[(t + 3) * sb_t];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 64 + 32 * (wv & 1);
+  const int64_t c0 = (int64_t)blockIdx.y * 64 + 32 * (wv >> 1);
+  int64_t ia[2], jb[2];
+  bool aok[2], bok[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    ia[t] = r0 + 16 * t + fr;
+    jb[t] = c0 + 16 * t + fr;
+    aok[t] = ia[t] < m;
+    bok[t] = jb[t] < n;
   }
-  for (; t < k; ++t) s0 += a[t * sa_t] * b[t * sb_t];
-  C[(int64_t)j * ldc + i] = alpha * ((s0 + s1) + (s2 + s3));
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  constexpr int UNR = 4;
+  for (int kk = 0; kk < k; kk += 4 * UNR) {
+    double av[UNR][2], bv[UNR][2];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int64_t t = kk + 4 * u + fk;
+      const bool tok = t < k;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[u][q] = (tok && aok[q]) ? A[ia[q] * sa_i + t * sa_t] : 0.0;
+        bv[u][q] = (tok && bok[q]) ? B[t * sb_t + jb[q] * sb_j] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[u][a], bv[u][b], acc[a][b]);
+  }
+  // element e of lane l in block (a, b): row r0 + 16 a + fk + 4 e, column c0 + 16 b + fr
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = r0 + 16 * a + fk + 4 * e, col = c0 + 16 * b + fr;
+        if (row < m && col < n) C[col * ldc + row] = alpha * acc[a][b][e];
+      }
 }
 
 cr_status small_gemm(int m, int n, int k, const double* A, int64_t lda, bool ta, const double* B,
                      int64_t ldb, bool tb, double alpha, double* C, int64_t ldc, hipStream_t st) {
   if (m <= 0 || n <= 0) return CR_OK;
-  const int64_t mn = (int64_t)m * n;
-  hipLaunchKernelGGL(k_small_gemm, dim3((unsigned)((mn + NT - 1) / NT)), dim3(NT), 0, st, m, n, k,
-                     A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, alpha, C, ldc);
+  const int64_t sa_i = ta ? lda : 1, sa_t = ta ? 1 : lda;
+  const int64_t sb_t = tb ? ldb : 1, sb_j = tb ? 1 : ldb;
+  const dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
+  hipLaunchKernelGGL(k_small_gemm, grid, dim3(NT), 0, st, m, n, k, A, sa_i, sa_t, B, sb_t, sb_j,
+                     alpha, C, ldc);
   CR_HIP(hipGetLastError());
   return CR_OK;
 }
