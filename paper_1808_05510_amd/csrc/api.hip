@@ -170,13 +170,16 @@ static int64_t gemm_part_cap(const cr_problem* P) {
 }
 
 // ===================================================================== small kernels
-// coef for the factored residual products (see apply_R / apply_RT)
-__global__ void k_rcoef(int ninj, int r, const double* __restrict__ y0,
-                        const double* __restrict__ Z, int64_t ldz, int trans, double lam,
-                        double* __restrict__ coef) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// coef for the factored residual products (see apply_R / apply_RT): one wave
+// per coefficient, its lanes splitting the r-long dot product with Z
+__global__ __launch_bounds__(256) void k_rcoef(int ninj, int r, const double* __restrict__ y0,
+                                               const double* __restrict__ Z, int64_t ldz,
+                                               int trans, double lam,
+                                               double* __restrict__ coef) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t < ninj) {
-    coef[t] = y0[t];
+    if (lane == 0) coef[t] = y0[t];
     return;
   }
   const int e = t - ninj;
@@ -191,10 +194,12 @@ __global__ void k_rcoef(int ninj, int r, const double* __restrict__ y0,
   const double* q = y0 + ninj + (int64_t)src * r;
   double s = 0.0;
   if (trans)
-    for (int k = 0; k < r; ++k) s += Z[(int64_t)i * ldz + k] * q[k];
+    for (int k = lane; k < r; k += 64) s += Z[(int64_t)i * ldz + k] * q[k];
   else
-    for (int k = 0; k < r; ++k) s += Z[(int64_t)k * ldz + i] * q[k];
-  coef[t] = sc * s;
+    for (int k = lane; k < r; k += 64) s += Z[(int64_t)k * ldz + i] * q[k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) coef[t] = sc * s;
 }
 
 __global__ void k_set2(double* dst, const double* s0, double f0, const double* s1, double f1) {
@@ -252,12 +257,16 @@ __global__ void k_build_cm(int ninj, int r, const double* __restrict__ Z, int64_
 }
 
 // out = {||Z - Zold||_F^2, ||Z||_F^2} over the leading r x r block (ld ldr)
+// ||Z - Zold||_F^2 and ||Z||_F^2 over the r x r core: per-workgroup partials
+// (part[2 b], part[2 b + 1]), then k_dw_final sums them in a fixed order
+constexpr int DW_MAXWG = 256;
 __global__ __launch_bounds__(256) void k_dw(int r, int64_t ldr, const double* __restrict__ Z,
                                             const double* __restrict__ Zold,
-                                            double* __restrict__ out) {
+                                            double* __restrict__ part) {
   __shared__ double red[2][4];
   double dd = 0.0, zz = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += 256) {
+  const int64_t n = (int64_t)r * r;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
     const int64_t i = e % r, j = e / r;
     const double a = Z[j * ldr + i], b = Zold[j * ldr + i];
     dd += (a - b) * (a - b);
@@ -274,8 +283,26 @@ __global__ __launch_bounds__(256) void k_dw(int r, int64_t ldr, const double* __
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    out[0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    out[1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    part[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    part[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_dw_final(int nb, const double* __restrict__ part,
+                                                 double* __restrict__ out) {
+  double dd = 0.0, zz = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 64) {
+    dd += part[2 * b];
+    zz += part[2 * b + 1];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    dd += __shfl_xor(dd, o, 64);
+    zz += __shfl_xor(zz, o, 64);
+  }
+  if (threadIdx.x == 0) {
+    out[0] = dd;
+    out[1] = zz;
   }
 }
 
@@ -673,7 +700,7 @@ struct Ctx {
     A.add(L2V, nx, r);
     CR_TRY(gemv_t<T>(nx, A, v, y0, part, st));
     const int k = ninj + 3 * r;
-    hipLaunchKernelGGL(k_rcoef, dim3(nblk(k, 128)), dim3(128), 0, st, ninj, r, y0, Z, ldz, 0,
+    hipLaunchKernelGGL(k_rcoef, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, st, ninj, r, y0, Z, ldz, 0,
                        lam, coef);
     CR_HIP(hipGetLastError());
     Blocks<T> B;
@@ -695,7 +722,7 @@ struct Ctx {
     A.add(L2U, ny, r);
     CR_TRY(gemv_t<T>(ny, A, u, y0, part, st));
     const int k = ninj + 3 * r;
-    hipLaunchKernelGGL(k_rcoef, dim3(nblk(k, 128)), dim3(128), 0, st, ninj, r, y0, Z, ldz, 1,
+    hipLaunchKernelGGL(k_rcoef, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, st, ninj, r, y0, Z, ldz, 1,
                        lam, coef);
     CR_HIP(hipGetLastError());
     Blocks<T> B;
@@ -2461,7 +2488,7 @@ static cr_status greedy_impl(cr_problem* P, const cr_solve_opts& o, double* Uo, 
   c.ldz = rmax;
   const int64_t ldr = rmax;
   double* Zold = WS(double, "Zold", (int64_t)rmax * rmax);
-  double* dws = WS(double, "dws", 2);
+  double* dws = WS(double, "dws", 2 + 2 * DW_MAXWG);
   int r0 = (int)*rank_io;
   if (r0 < 0 || r0 > rmax) {
     set_error("rank_io out of range");
@@ -2544,8 +2571,13 @@ static cr_status greedy_impl(cr_problem* P, const cr_solve_opts& o, double* Uo, 
     CR_TRY(c.build_N(r));
     CR_TRY(c.residual(r, nullptr, &relres));
     // delta W = ||Z_j - pad(Z_{j-1})||_F / ||Z_j||_F (orthonormal bases)
-    hipLaunchKernelGGL(k_dw, dim3(1), dim3(NT), 0, c.st, r, ldr, Zo, Zold, dws);
-    CR_HIP(hipGetLastError());
+    {
+      const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(DW_MAXWG, ((int64_t)r * r + 2047) / 2048));
+      hipLaunchKernelGGL(k_dw, dim3(nb), dim3(NT), 0, c.st, r, ldr, Zo, Zold, dws + 2);
+      CR_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_dw_final, dim3(1), dim3(64), 0, c.st, nb, dws + 2, dws);
+      CR_HIP(hipGetLastError());
+    }
     CR_HIP(hipMemcpyAsync(P->hscal, dws, 2 * sizeof(double), hipMemcpyDeviceToHost, c.st));
     CR_HIP(hipStreamSynchronize(c.st));
     const double dd = P->hscal[0], zz = P->hscal[1];
