@@ -103,6 +103,7 @@ struct cr_problem {
   int pcg_xbs = 0;           // v-system group size with register-resident X (0: 256;
                              // CONNREG_PCG_XBS=256 or 512)
   bool no_xreg = false;     // CONNREG_PCG_XREG=0: v-system PCG streams X (no register-resident rows)
+  bool pcg_xlds = true;     // rows of X beyond the register rows held in LDS (CONNREG_PCG_XLDS=0: streamed)
   bool pcg_warm = true;     // FP64 ALS half-steps warm-started (CONNREG_PCG_WARM=0: from zero)
   int bar_mode = 1;
   unsigned bar_spin = 1u << 22;  // grid-barrier poll bound (CONNREG_BAR_SPIN, for tests)
@@ -588,7 +589,30 @@ struct Ctx {
         }
       }
       // more injections than register rows: 64 rows in registers and the
-      // rest streamed, in 512-thread groups (253 VGPRs, two waves per SIMD)
+      // rest in LDS, loaded once per solve (256-thread groups, one per CU:
+      // the LDS holds at most PCG_XLDS_MAX rows), when the grid fits
+      if (pcg_nxr_v == 0 && ninj > PCG_NXR && ninj - PCG_NXR <= PCG_XLDS_MAX && want <= 1 &&
+          !P->no_xreg && P->pcg_xlds) {
+        PcgArgs<T> probe{};
+        probe.g = P->gx;
+        probe.Xm = X();
+        probe.ninj = ninj;
+        probe.vpt = 1;
+        probe.bs = NT;
+        probe.nxr = PCG_NXR;
+        probe.xtail = 2;
+        int maxwg = pcg_max_wg<T>(probe);
+        if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
+        const int64_t w = std::max<int64_t>(1, (nx + NT - 1) / NT);
+        if (maxwg > 0 && w <= maxwg) {
+          pcg_vpt_v = 1;
+          pcg_nwg_v = (int)w;
+          pcg_bs_v = NT;
+          pcg_nxr_v = PCG_NXR;
+          pcg_xtail_v = 2;
+        }
+      }
+      // else the rest streamed, in 512-thread groups (253 VGPRs, two waves per SIMD)
       if (pcg_nxr_v == 0 && ninj > PCG_NXR && want <= 1 && !P->no_xreg) {
         PcgArgs<T> probe{};
         probe.g = P->gx;
@@ -806,8 +830,12 @@ struct Ctx {
     a.bar.spin_max = P->bar_spin;
     int nwg = usys ? pcg_nwg_u : pcg_nwg_v;
     if (!usys && P->cv.valid && co_Ainv && a.vpt == 1 && (a.bs == NT || a.bs == 512)) {
-      const CoarsePack& pk = P->cv.pack[a.bs == NT ? 0 : 1];
       PcgArgs<T> c = a;
+      if (c.xtail == 2) {  // the two-level form streams the tail (512-thread groups)
+        c.xtail = 1;
+        c.bs = 512;
+      }
+      const CoarsePack& pk = P->cv.pack[c.bs == NT ? 0 : 1];
       c.co.slot_vox = pk.slot_vox;
       c.co.slot_agg = pk.slot_agg;
       c.co.slot_w = pk.slot_w;
@@ -1800,6 +1828,7 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   if (const char* e = std::getenv("CONNREG_PCG_BS")) P->pcg_bs = std::atoi(e) == NT ? NT : 1024;
   if (const char* e = std::getenv("CONNREG_PCG_XREG")) P->no_xreg = std::atoi(e) == 0;
   if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
+  if (const char* e = std::getenv("CONNREG_PCG_XLDS")) P->pcg_xlds = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_PCG_WARM")) P->pcg_warm = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_RESID_QR")) P->resid_qr = std::max(0, std::min(2, std::atoi(e)));
   if (const char* e = std::getenv("CONNREG_GAL_LOW")) P->gal_low = std::max(-1, std::min(1, std::atoi(e)));

@@ -214,14 +214,17 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // for FP32 data (rows held in FP32, 128 registers).  XTAIL: more injections than NXR; the
 // first NXR rows are in registers and the rest are streamed (z staged in LDS
 // for their partials), which halves the X traffic at 128 injections.
+// XLDS (with XTAIL): the tail rows are loaded once into LDS (dynamic shared
+// memory, (n_inj - NXR) * BS doubles) and read from there every iteration.
 // CO (two-level, one voxel per thread): thread slots hold the voxels of whole
 // aggregates (CoarseArg); z = D^-1 r + P Ainv P^T r needs the restricted
 // residual of every workgroup, so each z update takes one more grid barrier
 // (four per iteration).
 template <typename T, int K, bool LR, int VPT, int BS, int NXR, bool XTAIL = false,
-          bool CO = false>
+          bool CO = false, bool XLDS = false>
 __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   static_assert(!XTAIL || NXR > 0, "a streamed tail follows register rows");
+  static_assert(!XLDS || (XTAIL && !CO), "the LDS-resident tail replaces the streamed one");
   static_assert(NXR == 0 || (LR && VPT == 1), "register-resident X needs LR and VPT 1");
   static_assert(!CO || VPT == 1, "two-level launches hold one voxel per thread");
   cgrp::grid_group grid = cgrp::this_grid();
@@ -232,6 +235,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   __shared__ double lred[NXR > 0 ? BS / WAVE : 1][NXR > 0 ? NXR : 1];
   __shared__ double crs[CO ? BS : 1];         // w r of the workgroup's slots
   __shared__ double cys[CO ? CO_MAXLOC : 1];  // Ainv rc of the workgroup's aggregates
+  extern __shared__ double xtl[];             // XLDS: tail rows, xtl[(al - NXR) * BS + thread]
   const int64_t n = a.g.n;
   const int nwg = gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * BS * VPT;
@@ -302,6 +306,11 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
     for (int al = 0; al < NXR; ++al)
       xr[al] = (i0 >= 0 && i0 < n && al < ninj) ? (XR)Xm[(int64_t)al * ldx + i0] : (XR)0;
     for (int al = threadIdx.x; al < NXR; al += BS) slr[al] = 0.0;
+    if constexpr (XLDS) {
+      for (int al = NXR; al < ninj; ++al)
+        xtl[(al - NXR) * BS + threadIdx.x] =
+            (i0 >= 0 && i0 < n) ? (double)Xm[(int64_t)al * ldx + i0] : 0.0;
+    }
   }
   // per-workgroup partials of X^T z into lrpart (z of this thread's voxels)
   auto lr_part = [&](const double* zv) {
@@ -329,7 +338,19 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         for (int w = 0; w < BS / WAVE; ++w) t += lred[w][al];
         lrpart[(int64_t)al * nwg + blockIdx.x] = t;
       }
-      if constexpr (XTAIL) lr_partial<T, BS, CO>(a, zs, lo, n, nwg, lrpart, NXR);
+      if constexpr (XLDS) {
+        // tail partials from the LDS rows: one wave per injection
+        for (int al = NXR + wv; al < ninj; al += BS / WAVE) {
+          const double* xt = xtl + (al - NXR) * BS;
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < BS / WAVE; ++k) acc += xt[lane + WAVE * k] * zs[lane + WAVE * k];
+          acc = wsum(acc);
+          if (lane == 0) lrpart[(int64_t)al * nwg + blockIdx.x] = acc;
+        }
+      } else if constexpr (XTAIL) {
+        lr_partial<T, BS, CO>(a, zs, lo, n, nwg, lrpart, NXR);
+      }
     } else {
       lr_partial<T, BS, CO>(a, zs, lo, n, nwg, lrpart);
     }
@@ -448,9 +469,13 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
             if (NXR > 0) {
 #pragma unroll
               for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) s += xz(al, slr[al]);
-              if constexpr (XTAIL)
+              if constexpr (XLDS) {
+                for (int al = NXR; al < ninj; ++al)
+                  s += xtl[(al - NXR) * BS + threadIdx.x] * slr[al];
+              } else if constexpr (XTAIL) {
                 for (int al = NXR; al < ninj; ++al)
                   s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
+              }
             } else {
               for (int al = 0; al < ninj; ++al) s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
             }
@@ -654,8 +679,9 @@ static void* pcg_fn_co(int bs, int nxr, int xtail) {
     return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, 0, false, true>
                      : bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, 0, false, true> : nullptr;
   if (xtail)
-    return (nxr == PCG_NXR && bs == 512) ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR, true, true>
-                                          : nullptr;
+    return (xtail == 1 && nxr == PCG_NXR && bs == 512)
+               ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR, true, true>
+               : nullptr;
   if (nxr == PCG_NXR2) {
     if constexpr (std::is_same<T, float>::value)
       return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR2, false, true>
@@ -676,6 +702,10 @@ static void* pcg_fn_v(int vpt, int bs, int nxr, int xtail, bool co) {
   }
   if (nxr > 0) {  // register-resident X: one voxel per thread, 256- or 512-thread groups
     if (!LR || vpt != 1) return nullptr;
+    if (xtail == 2) {  // 64 register rows and the tail in LDS, 256-thread groups
+      if (nxr != PCG_NXR) return nullptr;
+      return bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR, true, false, true> : nullptr;
+    }
     if (xtail) {  // 64 register rows and a streamed tail, 512-thread groups
       if (nxr != PCG_NXR) return nullptr;
       return bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR, true> : nullptr;
@@ -708,6 +738,12 @@ static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr, int xtail, boo
   }
 }
 
+// dynamic LDS of a launch: the tail rows of the LDS-resident form
+template <typename T>
+static size_t pcg_dyn_lds(const PcgArgs<T>& a) {
+  return a.xtail == 2 ? sizeof(double) * (size_t)std::max(0, a.ninj - a.nxr) * (size_t)a.bs : 0;
+}
+
 template <typename T>
 int pcg_max_wg(const PcgArgs<T>& a) {
   void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail,
@@ -717,7 +753,8 @@ int pcg_max_wg(const PcgArgs<T>& a) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, a.bs, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, a.bs, pcg_dyn_lds(a)) != hipSuccess)
+    return 0;
   return per * ncu;
 }
 
@@ -744,10 +781,11 @@ cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
   PcgArgs<T> arg = a;
   if (arg.bar.mode == 1) CR_HIP(hipMemsetAsync(arg.bar.bar, 0, BAR_WORDS * sizeof(unsigned), st));
   void* params[] = {&arg};
+  const size_t dyn = pcg_dyn_lds(arg);
   if (arg.bar.coop || arg.bar.mode == 0)
-    CR_HIP(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(arg.bs), params, 0, st));
+    CR_HIP(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(arg.bs), params, dyn, st));
   else
-    CR_HIP(hipLaunchKernel(fn, dim3(nwg), dim3(arg.bs), params, 0, st));
+    CR_HIP(hipLaunchKernel(fn, dim3(nwg), dim3(arg.bs), params, dyn, st));
   return CR_OK;
 }
 
