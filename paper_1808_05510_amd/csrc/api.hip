@@ -3148,7 +3148,12 @@ static bool xreg_fits_share(cr_problem* P, int share) {
 // does every persistent PCG grid of problem P fit in `share` CUs?
 template <typename T>
 static bool fits_share_t(cr_problem* P, int share) {
-  if (!P->no_xreg && !xreg_fits_share<T>(P, 0)) {
+  // v-systems solved directly (SMW on a full source box) use their PCG only
+  // as a fallback, in whatever form fits: no register-form requirement
+  const bool v_direct = P->fcg_mode > 0 && P->boxx.valid && P->ninj <= SMW_MAX;
+  if (v_direct) {
+    // (the fallback grids are checked below)
+  } else if (!P->no_xreg && !xreg_fits_share<T>(P, 0)) {
     // (no register form even alone: the streamed form decides below)
   } else if (!P->no_xreg && !xreg_fits_share<T>(P, share)) {
     return false;
