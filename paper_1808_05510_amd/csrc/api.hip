@@ -475,7 +475,8 @@ struct Ctx {
   double* tmp = nullptr;
   int pcg_vpt_u = 1, pcg_vpt_v = 1, pcg_nwg_u = 1, pcg_nwg_v = 1, pcg_bs = NT;
   int64_t pcgpart_size = 0;
-  int pcg_xtail_v = 0;  // v-system: register rows plus a streamed tail of X
+  int pcg_xtail_v = 0;  // v-system: register rows plus a tail of X (1 streamed, 2 LDS first)
+  int pcg_xlds_v = 0;   // v-system tail rows held in LDS (pcg_xtail_v 2)
   int pcg_bs_v = NT, pcg_nxr_v = 0;  // v-system: X rows in registers when n_inj <= PCG_NXR
   // stats of the last ALS
   int it_u = 0, it_v = 0, notconv = 0;
@@ -554,6 +555,7 @@ struct Ctx {
     pcg_bs_v = pcg_bs;
     pcg_nxr_v = 0;
     pcg_xtail_v = 0;
+    pcg_xlds_v = 0;
     {
       const int tuned = P->tuned_vpt_v;
       const int want = vpt_opt > 0 ? vpt_opt : tuned;
@@ -589,27 +591,36 @@ struct Ctx {
         }
       }
       // more injections than register rows: 64 rows in registers and the
-      // rest in LDS, loaded once per solve (256-thread groups, one per CU:
-      // the LDS holds at most PCG_XLDS_MAX rows), when the grid fits
-      if (pcg_nxr_v == 0 && ninj > PCG_NXR && ninj - PCG_NXR <= PCG_XLDS_MAX && want <= 1 &&
-          !P->no_xreg && P->pcg_xlds) {
-        PcgArgs<T> probe{};
-        probe.g = P->gx;
-        probe.Xm = X();
-        probe.ninj = ninj;
-        probe.vpt = 1;
-        probe.bs = NT;
-        probe.nxr = PCG_NXR;
-        probe.xtail = 2;
-        int maxwg = pcg_max_wg<T>(probe);
-        if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
-        const int64_t w = std::max<int64_t>(1, (nx + NT - 1) / NT);
-        if (maxwg > 0 && w <= maxwg) {
-          pcg_vpt_v = 1;
-          pcg_nwg_v = (int)w;
-          pcg_bs_v = NT;
-          pcg_nxr_v = PCG_NXR;
-          pcg_xtail_v = 2;
+      // rest in LDS, loaded once per solve: all of them in 256-thread groups
+      // (one per CU; at most PCG_XLDS_MAX rows), else the first
+      // PCG_XLDS_MAX512 in 512-thread groups with the rest streamed, when
+      // the grid fits
+      if (pcg_nxr_v == 0 && ninj > PCG_NXR && want <= 1 && !P->no_xreg && P->pcg_xlds) {
+        const int tail = ninj - PCG_NXR;
+        for (int bs : {NT, 512}) {
+          const int rows = bs == NT ? tail : std::min(tail, PCG_XLDS_MAX512);
+          if (bs == NT && tail > PCG_XLDS_MAX) continue;
+          PcgArgs<T> probe{};
+          probe.g = P->gx;
+          probe.Xm = X();
+          probe.ninj = ninj;
+          probe.vpt = 1;
+          probe.bs = bs;
+          probe.nxr = PCG_NXR;
+          probe.xtail = 2;
+          probe.xlds = rows;
+          int maxwg = pcg_max_wg<T>(probe);
+          if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
+          const int64_t w = std::max<int64_t>(1, (nx + bs - 1) / bs);
+          if (maxwg > 0 && w <= maxwg) {
+            pcg_vpt_v = 1;
+            pcg_nwg_v = (int)w;
+            pcg_bs_v = bs;
+            pcg_nxr_v = PCG_NXR;
+            pcg_xtail_v = 2;
+            pcg_xlds_v = rows;
+            break;
+          }
         }
       }
       // else the rest streamed, in 512-thread groups (253 VGPRs, two waves per SIMD)
@@ -824,6 +835,7 @@ struct Ctx {
     a.bs = usys ? pcg_bs : pcg_bs_v;
     a.nxr = usys ? 0 : pcg_nxr_v;
     a.xtail = usys ? 0 : pcg_xtail_v;
+    a.xlds = usys ? 0 : pcg_xlds_v;
     a.bar.bar = P->bar;
     a.bar.mode = P->bar_mode;
     a.bar.coop = P->coop;
@@ -833,6 +845,7 @@ struct Ctx {
       PcgArgs<T> c = a;
       if (c.xtail == 2) {  // the two-level form streams the tail (512-thread groups)
         c.xtail = 1;
+        c.xlds = 0;
         c.bs = 512;
       }
       const CoarsePack& pk = P->cv.pack[c.bs == NT ? 0 : 1];

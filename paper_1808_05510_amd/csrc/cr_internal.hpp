@@ -249,14 +249,16 @@ struct PcgArgs {
   int vpt;              // voxels per thread
   int bs = NT;          // threads per workgroup (NT or 1024)
   int nxr = 0;          // PCG_NXR or PCG_NXR2: X rows in registers (low-rank term, vpt 1)
-  int xtail = 0;        // 1: more injections than nxr, the rest streamed; 2: the rest in LDS
+  int xtail = 0;        // 1: more injections than nxr, the rest streamed; 2: the first xlds
+                        // of the rest in LDS, any after them streamed
+  int xlds = 0;         // xtail 2: tail rows held in LDS
   BarrierArg bar;
 };
 constexpr int PCG_NXR = 64;  // injections held in registers by the X-resident PCG
 constexpr int PCG_NXR2 = 128;  // the same for FP32 data up to 128 injections
-// rows of X beyond the register rows that the LDS-resident form holds
-// (256 threads x 8 bytes each; with the kernel's static LDS, within 160 KB)
-constexpr int PCG_XLDS_MAX = 72;
+// rows of X beyond the register rows that the LDS-resident form holds, with
+// the kernel's static LDS within 160 KB: 72 rows at 256 threads, 35 at 512
+constexpr int PCG_XLDS_MAX = 72, PCG_XLDS_MAX512 = 35;
 template <typename T>
 cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st);
 template <typename T>

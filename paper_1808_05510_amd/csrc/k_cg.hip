@@ -214,8 +214,10 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // for FP32 data (rows held in FP32, 128 registers).  XTAIL: more injections than NXR; the
 // first NXR rows are in registers and the rest are streamed (z staged in LDS
 // for their partials), which halves the X traffic at 128 injections.
-// XLDS (with XTAIL): the tail rows are loaded once into LDS (dynamic shared
-// memory, (n_inj - NXR) * BS doubles) and read from there every iteration.
+// XLDS (with XTAIL): the first a.xlds tail rows are loaded once into LDS
+// (dynamic shared memory, a.xlds * BS doubles) and read from there every
+// iteration; the rows after them, if any, are streamed (512-thread groups
+// only: 256-thread groups hold the whole tail).
 // CO (two-level, one voxel per thread): thread slots hold the voxels of whole
 // aggregates (CoarseArg); z = D^-1 r + P Ainv P^T r needs the restricted
 // residual of every workgroup, so each z update takes one more grid barrier
@@ -224,7 +226,7 @@ template <typename T, int K, bool LR, int VPT, int BS, int NXR, bool XTAIL = fal
           bool CO = false, bool XLDS = false>
 __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   static_assert(!XTAIL || NXR > 0, "a streamed tail follows register rows");
-  static_assert(!XLDS || (XTAIL && !CO), "the LDS-resident tail replaces the streamed one");
+  static_assert(!XLDS || (XTAIL && !CO), "the LDS-resident rows are part of the tail");
   static_assert(NXR == 0 || (LR && VPT == 1), "register-resident X needs LR and VPT 1");
   static_assert(!CO || VPT == 1, "two-level launches hold one voxel per thread");
   cgrp::grid_group grid = cgrp::this_grid();
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       xr[al] = (i0 >= 0 && i0 < n && al < ninj) ? (XR)Xm[(int64_t)al * ldx + i0] : (XR)0;
     for (int al = threadIdx.x; al < NXR; al += BS) slr[al] = 0.0;
     if constexpr (XLDS) {
-      for (int al = NXR; al < ninj; ++al)
+      for (int al = NXR; al < NXR + a.xlds; ++al)
         xtl[(al - NXR) * BS + threadIdx.x] =
             (i0 >= 0 && i0 < n) ? (double)Xm[(int64_t)al * ldx + i0] : 0.0;
     }
@@ -339,8 +341,9 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         lrpart[(int64_t)al * nwg + blockIdx.x] = t;
       }
       if constexpr (XLDS) {
-        // tail partials from the LDS rows: one wave per injection
-        for (int al = NXR + wv; al < ninj; al += BS / WAVE) {
+        // tail partials from the LDS rows: one wave per injection; the
+        // rows after them streamed
+        for (int al = NXR + wv; al < NXR + a.xlds; al += BS / WAVE) {
           const double* xt = xtl + (al - NXR) * BS;
           double acc = 0.0;
 #pragma unroll
@@ -348,6 +351,9 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
           acc = wsum(acc);
           if (lane == 0) lrpart[(int64_t)al * nwg + blockIdx.x] = acc;
         }
+        // (256-thread groups hold the whole tail: no streamed rows)
+        if constexpr (BS != NT)
+          if (NXR + a.xlds < ninj) lr_partial<T, BS, CO>(a, zs, lo, n, nwg, lrpart, NXR + a.xlds);
       } else if constexpr (XTAIL) {
         lr_partial<T, BS, CO>(a, zs, lo, n, nwg, lrpart, NXR);
       }
@@ -470,8 +476,12 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
 #pragma unroll
               for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) s += xz(al, slr[al]);
               if constexpr (XLDS) {
-                for (int al = NXR; al < ninj; ++al)
+                const int al1 = BS == NT ? ninj : NXR + a.xlds;
+                for (int al = NXR; al < al1; ++al)
                   s += xtl[(al - NXR) * BS + threadIdx.x] * slr[al];
+                if constexpr (BS != NT)
+                  for (int al = al1; al < ninj; ++al)
+                    s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
               } else if constexpr (XTAIL) {
                 for (int al = NXR; al < ninj; ++al)
                   s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
@@ -702,9 +712,11 @@ static void* pcg_fn_v(int vpt, int bs, int nxr, int xtail, bool co) {
   }
   if (nxr > 0) {  // register-resident X: one voxel per thread, 256- or 512-thread groups
     if (!LR || vpt != 1) return nullptr;
-    if (xtail == 2) {  // 64 register rows and the tail in LDS, 256-thread groups
+    if (xtail == 2) {  // 64 register rows and the tail (or its first rows) in LDS
       if (nxr != PCG_NXR) return nullptr;
-      return bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR, true, false, true> : nullptr;
+      return bs == NT ? (void*)&k_pcg<T, K, true, 1, NT, PCG_NXR, true, false, true>
+                      : bs == 512 ? (void*)&k_pcg<T, K, true, 1, 512, PCG_NXR, true, false, true>
+                                  : nullptr;
     }
     if (xtail) {  // 64 register rows and a streamed tail, 512-thread groups
       if (nxr != PCG_NXR) return nullptr;
@@ -741,7 +753,7 @@ static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr, int xtail, boo
 // dynamic LDS of a launch: the tail rows of the LDS-resident form
 template <typename T>
 static size_t pcg_dyn_lds(const PcgArgs<T>& a) {
-  return a.xtail == 2 ? sizeof(double) * (size_t)std::max(0, a.ninj - a.nxr) * (size_t)a.bs : 0;
+  return a.xtail == 2 ? sizeof(double) * (size_t)std::max(0, a.xlds) * (size_t)a.bs : 0;
 }
 
 template <typename T>

@@ -1,7 +1,8 @@
 """v-system PCG with more injections than register rows (FP64: 64 rows of X
-in registers), in its two forms for the remaining rows: held in LDS for the
-whole solve (up to 72 more rows, 256-thread groups) and streamed from memory
-(512-thread groups, CONNREG_PCG_XLDS=0).  Both against the FP64 oracle in
+in registers), in its forms for the remaining rows: held in LDS for the
+whole solve (up to 72 more rows, 256-thread groups; 100 injections here),
+the first 35 in LDS and the rest streamed (512-thread groups; 150
+injections), and all streamed from memory (CONNREG_PCG_XLDS=0).  Both against the FP64 oracle in
 lockstep (same initial vectors, fixed ALS sweeps, inner solves to 1e-13):
 relative W difference <= 1e-6, per-rank relres within 1e-5 relative; and the
 two forms against each other (they differ only in summation order)."""
@@ -21,12 +22,13 @@ def np_(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.fixture(scope="module")
-def case():
-    # 990 / 504 voxels: two 256-voxel groups, the second partly empty;
-    # 100 injections: 36 rows beyond the register rows
-    d = synth.box_problem(box_y=(11, 10, 9), box_x=(8, 7, 9), offset=(1, 2, 0), n_inj=100,
-                          sigma=1.5, hole_r=1.5, wt_rank=4, wt_w=(2.0, 4.0), lam=30.0, seed=8)
+@pytest.fixture(scope="module", params=[100, 150])
+def case(request):
+    # 990 / 504 voxels: two 256-voxel groups (one 512-voxel group), the last
+    # partly empty; 100 or 150 injections: 36 or 86 rows beyond the register rows
+    d = synth.box_problem(box_y=(11, 10, 9), box_x=(8, 7, 9), offset=(1, 2, 0),
+                          n_inj=request.param, sigma=1.5, hole_r=1.5, wt_rank=4, wt_w=(2.0, 4.0),
+                          lam=30.0, seed=8)
     P = oop.problem_from_arrays(d)
     R = 8
     ores = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(
