@@ -3237,22 +3237,45 @@ extern "C" cr_status cr_greedy_solve_batch(int32_t count, cr_problem** probs,
   std::vector<std::string> errs(count);
   std::atomic<int> next{0};
   std::vector<std::thread> th;
+  // Each worker runs its problems on a pair of streams created here, one
+  // after another, so the K workers' streams spread over the device's
+  // hardware queues; the problems' own streams, created whenever their
+  // handles were, could share queues and serialise concurrent problems.
+  // The problems' pending work is finished first; their streams are restored
+  // after each solve (which ends with a wait on the stream it ran on).
+  std::vector<hipStream_t> wst(2 * K, nullptr);
+  for (int k = 0; k < count; ++k) CR_HIP(hipStreamSynchronize(probs[k]->st));
+  for (int w = 0; w < 2 * K && K > 1; ++w)
+    CR_HIP(hipStreamCreateWithFlags(&wst[w], hipStreamNonBlocking));
   for (int w = 0; w < K; ++w)
-    th.emplace_back([&]() {
+    th.emplace_back([&, w]() {
       (void)hipSetDevice(dev);
       for (int q = next++; q < count; q = next++) {
         const int k = order[q];
         cr_problem* P = probs[k];
+        hipStream_t own = P->st, own_aux = P->aux;
+        if (K > 1) {
+          P->st = wst[2 * w];
+          P->aux = wst[2 * w + 1];
+        }
         cr_status s = P->prec == CR_PREC_MIXED
                           ? greedy_impl<float>(P, opts[k], U[k], V[k], Z[k], &ranks[k],
                                                stats ? &stats[k] : nullptr, nullptr, nullptr)
                           : greedy_impl<double>(P, opts[k], U[k], V[k], Z[k], &ranks[k],
                                                 stats ? &stats[k] : nullptr, nullptr, nullptr);
+        if (K > 1) {
+          (void)hipStreamSynchronize(P->st);
+          (void)hipStreamSynchronize(P->aux);
+          P->st = own;
+          P->aux = own_aux;
+        }
         statuses[k] = s;
         if (s < 0) errs[k] = cr_last_error();
       }
     });
   for (auto& t : th) t.join();
+  for (hipStream_t sw : wst)
+    if (sw) (void)hipStreamDestroy(sw);
   cr_status worst = CR_OK;
   for (int k = 0; k < count; ++k) {
     probs[k]->cu_share = saved_cap[k];
