@@ -104,6 +104,8 @@ struct cr_problem {
                              // CONNREG_PCG_XBS=256 or 512)
   bool no_xreg = false;     // CONNREG_PCG_XREG=0: v-system PCG streams X (no register-resident rows)
   bool pcg_xlds = true;     // rows of X beyond the register rows held in LDS (CONNREG_PCG_XLDS=0: streamed)
+  bool batch_xreg = true;   // batches keep the register form of the v-system PCG
+                            // (CONNREG_BATCH_XREG=0: any form that fits a share)
   bool pcg_warm = true;     // FP64 ALS half-steps warm-started (CONNREG_PCG_WARM=0: from zero)
   int bar_mode = 1;
   unsigned bar_spin = 1u << 22;  // grid-barrier poll bound (CONNREG_BAR_SPIN, for tests)
@@ -1842,6 +1844,7 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   if (const char* e = std::getenv("CONNREG_PCG_XREG")) P->no_xreg = std::atoi(e) == 0;
   if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
   if (const char* e = std::getenv("CONNREG_PCG_XLDS")) P->pcg_xlds = std::atoi(e) != 0;
+  if (const char* e = std::getenv("CONNREG_BATCH_XREG")) P->batch_xreg = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_PCG_WARM")) P->pcg_warm = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_RESID_QR")) P->resid_qr = std::max(0, std::min(2, std::atoi(e)));
   if (const char* e = std::getenv("CONNREG_GAL_LOW")) P->gal_low = std::max(-1, std::min(1, std::atoi(e)));
@@ -3164,7 +3167,7 @@ static bool fits_share_t(cr_problem* P, int share) {
   // v-systems solved directly (SMW on a full source box) use their PCG only
   // as a fallback, in whatever form fits: no register-form requirement
   const bool v_direct = P->fcg_mode > 0 && P->boxx.valid && P->ninj <= SMW_MAX;
-  if (v_direct) {
+  if (v_direct || !P->batch_xreg) {
     // (the fallback grids are checked below)
   } else if (!P->no_xreg && !xreg_fits_share<T>(P, 0)) {
     // (no register form even alone: the streamed form decides below)
