@@ -104,6 +104,8 @@ struct cr_problem {
                              // CONNREG_PCG_XBS=256 or 512)
   bool no_xreg = false;     // CONNREG_PCG_XREG=0: v-system PCG streams X (no register-resident rows)
   bool pcg_xlds = true;     // rows of X beyond the register rows held in LDS (CONNREG_PCG_XLDS=0: streamed)
+  bool pcg_xlds_f32 = true; // FP32 data: 64 register rows and an LDS tail where 128 register
+                            // rows would need 512-thread groups (CONNREG_PCG_XLDS_F32=0: off)
   bool batch_xreg = true;   // batches keep the register form of the v-system PCG
                             // (CONNREG_BATCH_XREG=0: any form that fits a share)
   bool pcg_warm = true;     // FP64 ALS half-steps warm-started (CONNREG_PCG_WARM=0: from zero)
@@ -564,6 +566,11 @@ struct Ctx {
       // rows of X in registers: 64 for either type, 128 for FP32 data
       const int nxr_sel = ninj <= PCG_NXR ? PCG_NXR
                           : (std::is_same<T, float>::value && ninj <= PCG_NXR2) ? PCG_NXR2 : 0;
+      // FP32 data with more than 64 injections: when 128 register rows need
+      // 512-thread groups (their 256-thread form does not fit one group per
+      // CU), 64 rows in registers and the rest in LDS instead (below)
+      const bool f32_lds = std::is_same<T, float>::value && ninj > PCG_NXR && P->pcg_xlds &&
+                           P->pcg_xlds_f32;
       if (nxr_sel > 0 && want <= 1 && !P->no_xreg) {
         // 256-thread groups, whose kernel sums the X^T z partials with one
         // butterfly per wave (512-thread groups have no registers for it and
@@ -574,6 +581,7 @@ struct Ctx {
         // per injection, so a grid that does not fit at 256 tries 512)
         const int xbs = P->pcg_xbs > 0 ? P->pcg_xbs : NT;
         for (int bs : {xbs, NT, 512}) {
+          if (f32_lds && nxr_sel == PCG_NXR2 && bs == 512) break;
           PcgArgs<T> probe{};
           probe.g = P->gx;
           probe.Xm = X();
@@ -600,8 +608,9 @@ struct Ctx {
       if (pcg_nxr_v == 0 && ninj > PCG_NXR && want <= 1 && !P->no_xreg && P->pcg_xlds) {
         const int tail = ninj - PCG_NXR;
         for (int bs : {NT, 512}) {
-          const int rows = bs == NT ? tail : std::min(tail, PCG_XLDS_MAX512);
-          if (bs == NT && tail > PCG_XLDS_MAX) continue;
+          const int cap = pcg_xlds_cap(bs, (int)sizeof(T));
+          const int rows = bs == NT ? tail : std::min(tail, cap);
+          if (bs == NT && tail > cap) continue;
           PcgArgs<T> probe{};
           probe.g = P->gx;
           probe.Xm = X();
@@ -623,6 +632,25 @@ struct Ctx {
             pcg_xlds_v = rows;
             break;
           }
+        }
+      }
+      // FP32 data whose LDS form did not fit: back to 128 register rows in
+      // 512-thread groups
+      if (pcg_nxr_v == 0 && f32_lds && nxr_sel == PCG_NXR2 && want <= 1 && !P->no_xreg) {
+        PcgArgs<T> probe{};
+        probe.g = P->gx;
+        probe.Xm = X();
+        probe.vpt = 1;
+        probe.bs = 512;
+        probe.nxr = PCG_NXR2;
+        int maxwg = pcg_max_wg<T>(probe);
+        if (P->cu_share > 0) maxwg = share_cap(maxwg, P->cu_share);
+        const int64_t w = std::max<int64_t>(1, (nx + 511) / 512);
+        if (maxwg > 0 && w <= maxwg) {
+          pcg_vpt_v = 1;
+          pcg_nwg_v = (int)w;
+          pcg_bs_v = 512;
+          pcg_nxr_v = PCG_NXR2;
         }
       }
       // else the rest streamed, in 512-thread groups (253 VGPRs, two waves per SIMD)
@@ -1844,6 +1872,7 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   if (const char* e = std::getenv("CONNREG_PCG_XREG")) P->no_xreg = std::atoi(e) == 0;
   if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
   if (const char* e = std::getenv("CONNREG_PCG_XLDS")) P->pcg_xlds = std::atoi(e) != 0;
+  if (const char* e = std::getenv("CONNREG_PCG_XLDS_F32")) P->pcg_xlds_f32 = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_BATCH_XREG")) P->batch_xreg = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_PCG_WARM")) P->pcg_warm = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_RESID_QR")) P->resid_qr = std::max(0, std::min(2, std::atoi(e)));

@@ -256,9 +256,13 @@ struct PcgArgs {
 };
 constexpr int PCG_NXR = 64;  // injections held in registers by the X-resident PCG
 constexpr int PCG_NXR2 = 128;  // the same for FP32 data up to 128 injections
-// rows of X beyond the register rows that the LDS-resident form holds, with
-// the kernel's static LDS within 160 KB: 72 rows at 256 threads, 35 at 512
-constexpr int PCG_XLDS_MAX = 72, PCG_XLDS_MAX512 = 35;
+// rows of X beyond the register rows that the LDS-resident form can hold
+// beside the kernel's static LDS (12 KB at 256 threads, 16.5 KB at 512)
+// within 160 KB: 72 / 35 FP64 rows, 147 / 71 FP32 rows at 256 / 512 threads
+inline int pcg_xlds_cap(int bs, int bytes) {
+  const int stat = bs == 256 ? 12352 : 16512;
+  return (160 * 1024 - stat) / (bs * bytes);
+}
 template <typename T>
 cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st);
 template <typename T>

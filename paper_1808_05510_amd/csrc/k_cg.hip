@@ -215,7 +215,7 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // first NXR rows are in registers and the rest are streamed (z staged in LDS
 // for their partials), which halves the X traffic at 128 injections.
 // XLDS (with XTAIL): the first a.xlds tail rows are loaded once into LDS
-// (dynamic shared memory, a.xlds * BS doubles) and read from there every
+// (dynamic shared memory, a.xlds * BS values of type T) and read from there every
 // iteration; the rows after them, if any, are streamed (512-thread groups
 // only: 256-thread groups hold the whole tail).
 // CO (two-level, one voxel per thread): thread slots hold the voxels of whole
@@ -237,7 +237,8 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   __shared__ double lred[NXR > 0 ? BS / WAVE : 1][NXR > 0 ? NXR : 1];
   __shared__ double crs[CO ? BS : 1];         // w r of the workgroup's slots
   __shared__ double cys[CO ? CO_MAXLOC : 1];  // Ainv rc of the workgroup's aggregates
-  extern __shared__ double xtl[];             // XLDS: tail rows, xtl[(al - NXR) * BS + thread]
+  extern __shared__ double xtl_raw[];
+  T* const xtl = reinterpret_cast<T*>(xtl_raw);  // XLDS: tail rows (type T), xtl[(al - NXR) * BS + thread]
   const int64_t n = a.g.n;
   const int nwg = gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * BS * VPT;
@@ -310,8 +311,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
     for (int al = threadIdx.x; al < NXR; al += BS) slr[al] = 0.0;
     if constexpr (XLDS) {
       for (int al = NXR; al < NXR + a.xlds; ++al)
-        xtl[(al - NXR) * BS + threadIdx.x] =
-            (i0 >= 0 && i0 < n) ? (double)Xm[(int64_t)al * ldx + i0] : 0.0;
+        xtl[(al - NXR) * BS + threadIdx.x] = (i0 >= 0 && i0 < n) ? Xm[(int64_t)al * ldx + i0] : (T)0;
     }
   }
   // per-workgroup partials of X^T z into lrpart (z of this thread's voxels)
@@ -344,10 +344,11 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         // tail partials from the LDS rows: one wave per injection; the
         // rows after them streamed
         for (int al = NXR + wv; al < NXR + a.xlds; al += BS / WAVE) {
-          const double* xt = xtl + (al - NXR) * BS;
+          const T* xt = xtl + (al - NXR) * BS;
           double acc = 0.0;
 #pragma unroll
-          for (int k = 0; k < BS / WAVE; ++k) acc += xt[lane + WAVE * k] * zs[lane + WAVE * k];
+          for (int k = 0; k < BS / WAVE; ++k)
+            acc += (double)xt[lane + WAVE * k] * zs[lane + WAVE * k];
           acc = wsum(acc);
           if (lane == 0) lrpart[(int64_t)al * nwg + blockIdx.x] = acc;
         }
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
               if constexpr (XLDS) {
                 const int al1 = BS == NT ? ninj : NXR + a.xlds;
                 for (int al = NXR; al < al1; ++al)
-                  s += xtl[(al - NXR) * BS + threadIdx.x] * slr[al];
+                  s += (double)xtl[(al - NXR) * BS + threadIdx.x] * slr[al];
                 if constexpr (BS != NT)
                   for (int al = al1; al < ninj; ++al)
                     s += (double)Xm[(int64_t)al * ldx + i] * slr[al];
@@ -753,7 +754,7 @@ static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr, int xtail, boo
 // dynamic LDS of a launch: the tail rows of the LDS-resident form
 template <typename T>
 static size_t pcg_dyn_lds(const PcgArgs<T>& a) {
-  return a.xtail == 2 ? sizeof(double) * (size_t)std::max(0, a.xlds) * (size_t)a.bs : 0;
+  return a.xtail == 2 ? sizeof(T) * (size_t)std::max(0, a.xlds) * (size_t)a.bs : 0;
 }
 
 template <typename T>

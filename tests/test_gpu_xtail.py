@@ -37,9 +37,9 @@ def case(request):
     return d, P, R, ores
 
 
-def _solve(monkeypatch, d, R, xlds):
+def _solve(monkeypatch, d, R, xlds, prec="fp64"):
     monkeypatch.setenv("CONNREG_PCG_XLDS", "1" if xlds else "0")
-    g = connreg.Problem(d, "fp64", DEV)
+    g = connreg.Problem(d, prec, DEV)
     try:
         res = g.greedy_solve(max_rank=R, als_fixed_sweeps=3, pcg_rtol=1e-13, pcg_maxit=20000,
                              galerkin_rtol=1e-13, galerkin_maxit=20000, seed=5)
@@ -69,3 +69,16 @@ def test_tail_forms_agree(monkeypatch, case):
     Ub, Vb, Zb = np_(b["U"]), np_(b["V"]), np_(b["Z"])
     err = omet.diff_norm(Ua, Za, Va, Ub, Zb, Vb) / omet.low_rank_norm(Ub, Zb, Vb)
     assert err <= 1e-9, err
+
+
+@pytest.mark.parametrize("xlds", [True, False])
+def test_mixed_lockstep_tail_forms(monkeypatch, case, xlds):
+    """FP32 data: 100 injections keep 128 register rows; 150 take 64 register
+    rows and 86 FP32 rows in LDS (or streamed): W within the mixed bar 1e-4."""
+    d, P, R, ores = case
+    res = _solve(monkeypatch, d, R, xlds, prec="mixed")
+    assert res["rank"] == R
+    U, V, Z = (res[k].detach().to("cpu").double().numpy() for k in ("U", "V", "Z"))
+    err = omet.diff_norm(U, Z, V, ores.U, ores.Z, ores.V) / omet.low_rank_norm(ores.U, ores.Z,
+                                                                               ores.V)
+    assert err <= 1e-4, err
