@@ -104,8 +104,9 @@ struct cr_problem {
                              // CONNREG_PCG_XBS=256 or 512)
   bool no_xreg = false;     // CONNREG_PCG_XREG=0: v-system PCG streams X (no register-resident rows)
   bool pcg_xlds = true;     // rows of X beyond the register rows held in LDS (CONNREG_PCG_XLDS=0: streamed)
-  bool pcg_xlds_f32 = true; // FP32 data: 64 register rows and an LDS tail where 128 register
-                            // rows would need 512-thread groups (CONNREG_PCG_XLDS_F32=0: off)
+  int pcg_xlds_f32 = 1;     // FP32 data: 64 register rows and an LDS tail where 128 register
+                            // rows would need 512-thread groups (CONNREG_PCG_XLDS_F32=0: off,
+                            // 2: also where they fit 256-thread groups)
   bool batch_xreg = true;   // batches keep the register form of the v-system PCG
                             // (CONNREG_BATCH_XREG=0: any form that fits a share)
   bool pcg_warm = true;     // FP64 ALS half-steps warm-started (CONNREG_PCG_WARM=0: from zero)
@@ -570,7 +571,7 @@ struct Ctx {
       // 512-thread groups (their 256-thread form does not fit one group per
       // CU), 64 rows in registers and the rest in LDS instead (below)
       const bool f32_lds = std::is_same<T, float>::value && ninj > PCG_NXR && P->pcg_xlds &&
-                           P->pcg_xlds_f32;
+                           P->pcg_xlds_f32 > 0;
       if (nxr_sel > 0 && want <= 1 && !P->no_xreg) {
         // 256-thread groups, whose kernel sums the X^T z partials with one
         // butterfly per wave (512-thread groups have no registers for it and
@@ -581,7 +582,7 @@ struct Ctx {
         // per injection, so a grid that does not fit at 256 tries 512)
         const int xbs = P->pcg_xbs > 0 ? P->pcg_xbs : NT;
         for (int bs : {xbs, NT, 512}) {
-          if (f32_lds && nxr_sel == PCG_NXR2 && bs == 512) break;
+          if (f32_lds && nxr_sel == PCG_NXR2 && (bs == 512 || P->pcg_xlds_f32 == 2)) break;
           PcgArgs<T> probe{};
           probe.g = P->gx;
           probe.Xm = X();
@@ -1872,7 +1873,8 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   if (const char* e = std::getenv("CONNREG_PCG_XREG")) P->no_xreg = std::atoi(e) == 0;
   if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
   if (const char* e = std::getenv("CONNREG_PCG_XLDS")) P->pcg_xlds = std::atoi(e) != 0;
-  if (const char* e = std::getenv("CONNREG_PCG_XLDS_F32")) P->pcg_xlds_f32 = std::atoi(e) != 0;
+  if (const char* e = std::getenv("CONNREG_PCG_XLDS_F32"))
+    P->pcg_xlds_f32 = std::max(0, std::min(2, std::atoi(e)));
   if (const char* e = std::getenv("CONNREG_BATCH_XREG")) P->batch_xreg = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_PCG_WARM")) P->pcg_warm = std::atoi(e) != 0;
   if (const char* e = std::getenv("CONNREG_RESID_QR")) P->resid_qr = std::max(0, std::min(2, std::atoi(e)));
