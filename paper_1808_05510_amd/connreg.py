@@ -107,8 +107,8 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
-                           "(hipcc, gfx950); there is no CPU fallback")
+        raise RuntimeError(f"{path} is missing: build it with python -m "
+                           "paper_1808_05510_amd.build (hipcc, gfx950); there is no CPU fallback")
     L = ctypes.CDLL(path)
     P = c_void_p
     L.cr_problem_create.argtypes = [POINTER(ProblemDesc), ctypes.c_int, P, POINTER(P)]
