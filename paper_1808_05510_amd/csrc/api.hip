@@ -1192,16 +1192,14 @@ struct Ctx {
         CR_TRY(lpc_output(pc->net, pc->acts.in, pc->acts.y, z, st));
         zz = z;
       }
-      // [r.z, qq.z, r.w, qq.w]
-      Blocks<double> A, B;
+      // [r.z, qq.z, r.w, qq.w] (without the network z is w and only the
+      // first pair is read)
+      Blocks<double> A;
       A.clear();
       A.add(r, n, 1);
       A.add(qq, n, 1);
-      B.clear();
-      B.add(zz, n, 1);
-      B.add(w, n, 1);
-      CR_TRY(gemm_tn<double>(n, A, B, nullptr, nullptr, 0, S + FS_DZ, 2, gpart, gemm_part_cap(P),
-                             st));
+      CR_TRY(gemv_t<double>(n, A, zz, S + FS_DZ, part, st));
+      if (net) CR_TRY(gemv_t<double>(n, A, w, S + FS_DZ + 2, part, st));
       hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(1), 0, st, S, it == 0 ? 1 : 0, net ? 1 : 0);
       hipLaunchKernelGGL(k_fcg_dir, dim3(nblk(n)), dim3(256), 0, st, n, zz, w, S, pp, p);
       CR_HIP(hipGetLastError());
