@@ -199,30 +199,40 @@ __global__ __launch_bounds__(SMW_NT) void k_smw_factor(int n, const double* __re
   }
 }
 
-// kvec = -G^1/2 K^-1 G^1/2 h with K = L L^T (L from k_smw_factor)
+// kvec = -G^1/2 K^-1 G^1/2 h with K = L L^T (L from k_smw_factor): the
+// workgroup stages L in LDS, then one wave solves L y = z and L^T w = y with
+// rows i and i + 64 in lane i % 64 and the pivot broadcast by a shuffle.
 __global__ __launch_bounds__(NT) void k_smw_apply(int n, const double* __restrict__ g,
                                                   const double* __restrict__ L,
                                                   const double* __restrict__ h,
                                                   double* __restrict__ kvec) {
-  __shared__ double z[SMW_MAX];
+  __shared__ double Ls[SMW_MAX * SMW_MAX];
   const int tid = threadIdx.x;
-  for (int i = tid; i < n; i += NT) z[i] = sqrt(g[i]) * h[i];
+  for (int e = tid; e < n * n; e += NT) Ls[e] = L[e];
   __syncthreads();
-  for (int j = 0; j < n; ++j) {  // L y = z
-    if (tid == 0) z[j] /= L[(int64_t)j * n + j];
-    __syncthreads();
-    const double zj = z[j];
-    for (int i = j + 1 + tid; i < n; i += NT) z[i] -= L[(int64_t)j * n + i] * zj;
-    __syncthreads();
+  if (tid >= WAVE) return;
+  const int lane = tid;
+  const int i0 = lane, i1 = lane + WAVE;
+  double z0 = i0 < n ? sqrt(g[i0]) * h[i0] : 0.0;
+  double z1 = i1 < n ? sqrt(g[i1]) * h[i1] : 0.0;
+  for (int j = 0; j < n; ++j) {  // L y = z (column j: L(i, j) = Ls[j n + i])
+    const int src = j & (WAVE - 1);
+    const double zj = __shfl(j < WAVE ? z0 : z1, src, WAVE) / Ls[j * n + j];
+    if (i0 == j) z0 = zj;
+    if (i1 == j) z1 = zj;
+    if (i0 > j && i0 < n) z0 -= Ls[j * n + i0] * zj;
+    if (i1 > j && i1 < n) z1 -= Ls[j * n + i1] * zj;
   }
-  for (int j = n - 1; j >= 0; --j) {  // L^T w = y
-    if (tid == 0) z[j] /= L[(int64_t)j * n + j];
-    __syncthreads();
-    const double zj = z[j];
-    for (int i = tid; i < j; i += NT) z[i] -= L[(int64_t)i * n + j] * zj;
-    __syncthreads();
+  for (int j = n - 1; j >= 0; --j) {  // L^T w = y (row j of L^T: L(j, i) = Ls[i n + j])
+    const int src = j & (WAVE - 1);
+    const double zj = __shfl(j < WAVE ? z0 : z1, src, WAVE) / Ls[j * n + j];
+    if (i0 == j) z0 = zj;
+    if (i1 == j) z1 = zj;
+    if (i0 < j) z0 -= Ls[i0 * n + j] * zj;
+    if (i1 < j) z1 -= Ls[i1 * n + j] * zj;
   }
-  for (int i = tid; i < n; i += NT) kvec[i] = -sqrt(g[i]) * z[i];
+  if (i0 < n) kvec[i0] = -sqrt(g[i0]) * z0;
+  if (i1 < n) kvec[i1] = -sqrt(g[i1]) * z1;
 }
 
 cr_status smw_factor(int n, const double* g, double* K, hipStream_t st) {
