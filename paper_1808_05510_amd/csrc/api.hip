@@ -1457,9 +1457,10 @@ struct Ctx {
       return read_scalars(sc + 8, 4, scal4);
     }
     const int ldh = (r + 3) / 4 * 4;
+    __bf16* gb = WS(__bf16, "gGb", (int64_t)ninj * r * ldh);
+    CR_TRY(gram_to_bf16(r, (int)ldr, ldh, ninj, G, gb, st));
     a.ldh = ldh;
-    a.Gb = WS(__bf16, "gGb", (int64_t)ninj * r * ldh);
-    CR_TRY(gram_to_bf16(r, (int)ldr, ldh, ninj, G, const_cast<__bf16*>(a.Gb), st));
+    a.Gb = gb;
     a.inner_rel = GAL_LOW_INNER;
     double tot = 0.0, s5[5] = {0, 0, 0, 0, 0};
     int outer = 0;
@@ -3257,6 +3258,22 @@ extern "C" cr_status cr_greedy_solve_batch(int32_t count, cr_problem** probs,
   for (int k = 0; k < count; ++k) order[k] = k;
   std::sort(order.begin(), order.end(),
             [&](int a, int b) { return probs[a]->ny > probs[b]->ny; });
+  // Each worker runs its problems on a pair of streams created here, one
+  // after another, so the K workers' streams spread over the device's
+  // hardware queues; the problems' own streams, created whenever their
+  // handles were, could share queues and serialise concurrent problems.
+  // The problems' pending work is finished first; their streams are restored
+  // after each solve (which ends with a wait on the stream it ran on).
+  std::vector<hipStream_t> wst(2 * K, nullptr);
+  for (int k = 0; k < count; ++k) CR_HIP(hipStreamSynchronize(probs[k]->st));
+  for (int w = 0; w < 2 * K && K > 1; ++w) {
+    if (hipStreamCreateWithFlags(&wst[w], hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t sw : wst)
+        if (sw) (void)hipStreamDestroy(sw);
+      set_error("stream creation for the batch workers failed");
+      return CR_EHIP;
+    }
+  }
   std::vector<int> saved_cap(count), saved_coop(count), saved_mode(count);
   for (int k = 0; k < count; ++k) {
     saved_cap[k] = probs[k]->cu_share;
@@ -3269,16 +3286,6 @@ extern "C" cr_status cr_greedy_solve_batch(int32_t count, cr_problem** probs,
   std::vector<std::string> errs(count);
   std::atomic<int> next{0};
   std::vector<std::thread> th;
-  // Each worker runs its problems on a pair of streams created here, one
-  // after another, so the K workers' streams spread over the device's
-  // hardware queues; the problems' own streams, created whenever their
-  // handles were, could share queues and serialise concurrent problems.
-  // The problems' pending work is finished first; their streams are restored
-  // after each solve (which ends with a wait on the stream it ran on).
-  std::vector<hipStream_t> wst(2 * K, nullptr);
-  for (int k = 0; k < count; ++k) CR_HIP(hipStreamSynchronize(probs[k]->st));
-  for (int w = 0; w < 2 * K && K > 1; ++w)
-    CR_HIP(hipStreamCreateWithFlags(&wst[w], hipStreamNonBlocking));
   for (int w = 0; w < K; ++w)
     th.emplace_back([&, w]() {
       (void)hipSetDevice(dev);
