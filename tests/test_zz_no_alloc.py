@@ -68,3 +68,48 @@ def test_noalloc_rejects_sizes_beyond_its_scratch():
     with pytest.raises(connreg.ConnRegError, match="scratch"):
         g.op_apply(U, Z, V, noalloc=True)
     g.close()
+
+
+def test_noalloc_op_apply_replays_in_a_captured_graph():
+    """The callers the entry point is for: captured once into a graph (on the
+    handle's stream, its fork to the auxiliary stream and join included) and
+    replayed with new inputs copied into the captured buffers; every replay,
+    with eager work and a synchronisation between replays, equals the eager
+    call on the same inputs exactly (the same kernels in the same shapes)."""
+    d = synth.box_problem(box_y=(11, 10, 9), box_x=(8, 7, 9), offset=(1, 2, 0), n_inj=37,
+                          sigma=1.5, hole_r=1.5, wt_rank=4, wt_w=(2.0, 4.0), lam=30.0, seed=4)
+    s = torch.cuda.Stream(DEV)
+    g = connreg.Problem(d, "fp64", DEV, stream=s)
+    r = 24
+    gen = torch.Generator(device=DEV).manual_seed(7)
+
+    def colmajor_randn(n, k):
+        return torch.randn((k, n), device=DEV, dtype=torch.float64, generator=gen).T
+
+    U, Z, V = colmajor_randn(g.n_y, r), colmajor_randn(r, r), colmajor_randn(g.n_x, r)
+    F = connreg.empty_colmajor(g.n_y, 2 * r + g.n_inj, DEV)
+    G = connreg.empty_colmajor(g.n_x, 2 * r, DEV)
+    with torch.cuda.stream(s):
+        g.op_apply(U, Z, V, out=(F, G), noalloc=True)
+    s.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        g.op_apply(U, Z, V, out=(F, G), noalloc=True)
+    s.synchronize()
+    try:
+        for k in range(4):
+            with torch.cuda.stream(s):
+                U.copy_(colmajor_randn(g.n_y, r))
+                Z.copy_(colmajor_randn(r, r))
+                V.copy_(colmajor_randn(g.n_x, r))
+                graph.replay()
+            s.synchronize()
+            Fg, Gg = F.cpu().numpy(), G.cpu().numpy()
+            with torch.cuda.stream(s):
+                Fe, Ge = g.op_apply(U, Z, V, noalloc=True)
+            s.synchronize()
+            assert np.array_equal(Fg, Fe.cpu().numpy()), k
+            assert np.array_equal(Gg, Ge.cpu().numpy()), k
+    finally:
+        del graph
+        g.close()
