@@ -166,6 +166,7 @@ const float* cr_problem::OY<float>() const { return OY32; }
 // this relative residual; CholQR2 needs factor widths k = n_inj + 3r <= KMAX
 constexpr double RESID_QR_SWITCH = 1e-6;
 constexpr int RESID_QR_KMAX = 1024;
+constexpr int PCG_U_VPT2_WG = 96;
 // with neither factor (both have more columns than rows, or dependent ones)
 // the residual's entries are formed when n_y n_x k is at most this
 constexpr double RESID_DENSE_MAX = 2e11;
@@ -526,10 +527,18 @@ struct Ctx {
     // voxels per thread, whose per-phase latency grows faster than the grid
     // barrier (3 us at 64, 8 us at 256 groups) shrinks; wider workgroups
     // (pcg_bs) cut the group count without adding work per thread.
+    // u-systems whose one-voxel grid exceeds PCG_U_VPT2_WG workgroups take two
+    // voxels per thread, halving the arrivals at the grid barrier (1024-thread
+    // groups: the cortex shells 5.77 -> 5.55 s and the flatmap-sized map
+    // 11.86 -> 11.35 s, both FP64; the 40^3 grid's 63 groups stay at one,
+    // where two measured slower)
     pcg_bs = P->cu_share > 0 ? NT : P->pcg_bs;
     auto pick = [&](const Geom& g, const T* Xm, int& vpt, int& nwg) -> bool {
       const int tuned = Xm ? P->tuned_vpt_v : P->tuned_vpt_u;
-      const int want = vpt_opt > 0 ? vpt_opt : tuned;
+      int want = vpt_opt > 0 ? vpt_opt : tuned;
+      if (want <= 0 && !Xm && P->cu_share <= 0 &&
+          (g.n + (int64_t)pcg_bs - 1) / pcg_bs > PCG_U_VPT2_WG)
+        want = 2;
       for (int v = 1; v <= 8; v *= 2) {
         if (want > 0 && v < want) continue;
         PcgArgs<T> probe{};
