@@ -63,6 +63,12 @@ struct cr_problem {
   hipStream_t aux = nullptr;  // library-owned second stream (default priority) for fork/join
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool op_fork = true;  // op_apply's data term on the auxiliary stream (CONNREG_OP_FORK=0: serial)
+  // op_apply in fused ring-2 window sweeps where the geometry has the tables
+  // (CONNREG_OP_FUSED: 0 off, 1 FP64 only, 2 FP64 and FP32).  Off by default:
+  // on the cortex shells at r = 100 the fused call measured 912 against
+  // 770 us (FP64) and 703 against 500 us (FP32); its window loop is latency
+  // bound at two workgroups per CU, and each ring-2 window is 11 times its tile
+  int op_fused = 0;
   cr_precision prec = CR_PREC_FP64;
   int64_t ny = 0, nx = 0;
   int ninj = 0;
@@ -1710,6 +1716,130 @@ struct Ctx {
 };
 
 // ===================================================================== create / destroy
+// Ring-2 window tables of the fused operator sweep (left null when some row
+// of L^2 or some tile's window does not fit; the sweep then falls back to two
+// stencil passes).  Row i of L = K I - N (N: the self-padded neighbour
+// table) has the diagonal K - #self slots and -1 per present neighbour; row
+// i of L^2 is the sum over the entries (m, a) of row i of L of a times row m.
+static cr_status build_win2(Geom& g, const std::vector<int32_t>& nbr, hipStream_t st) {
+  const int64_t n = g.n;
+  const int K = g.K;
+  if (K > W2_NL - 1 || n == 0) return CR_OK;
+  std::vector<uint32_t> ent((size_t)W2_NE * n);
+  // row i of L as (column, coefficient), the diagonal first
+  auto lrow = [&](int64_t i, int32_t* col, int* cf) {
+    int m = 1, self = 0;
+    col[0] = (int32_t)i;
+    for (int k = 0; k < K; ++k) {
+      const int32_t j = nbr[(size_t)k * n + i];
+      if (j == (int32_t)i) {
+        ++self;
+      } else {
+        col[m] = j;
+        cf[m] = -1;
+        ++m;
+      }
+    }
+    cf[0] = K - self;
+    return m;
+  };
+  auto pack = [](int pos, int c2, int c1) {
+    return (uint32_t)pos | ((uint32_t)(uint8_t)(int8_t)c2 << 16) |
+           ((uint32_t)(uint8_t)(int8_t)c1 << 24);
+  };
+  const int64_t nt2 = (n + W2_TILE - 1) / W2_TILE;
+  std::vector<int32_t> tab((size_t)nt2 * W2_TAB, 0);
+  std::vector<int32_t> idx;
+  int32_t scol[W2_NE];
+  int sc2[W2_NE], sc1[W2_NE];
+  // the tile's entries as (voxel, c2, c1), before window positions exist
+  std::vector<int32_t> tcol((size_t)W2_TILE * W2_NE);
+  std::vector<int> tc2((size_t)W2_TILE * W2_NE), tc1((size_t)W2_TILE * W2_NE);
+  int32_t ci[W2_NL], cm[W2_NL];
+  int fi[W2_NL], fm[W2_NL];
+  for (int64_t t = 0; t < nt2; ++t) {
+    const int64_t t0 = t * W2_TILE, t1 = std::min(n, t0 + W2_TILE);
+    idx.clear();
+    for (int64_t i = t0; i < t1; ++i) {
+      const int mi = lrow(i, ci, fi);
+      // entries 0..W2_NL-1: the support of row i of L (with c1), padded with
+      // the voxel itself; the rest of row i of L^2 follows
+      int ne = W2_NL;
+      for (int a = 0; a < W2_NL; ++a) {
+        scol[a] = a < mi ? ci[a] : (int32_t)i;
+        sc1[a] = a < mi ? fi[a] : 0;
+        sc2[a] = 0;
+      }
+      for (int a = 0; a < mi; ++a) {
+        const int mm = lrow(ci[a], cm, fm);
+        for (int b = 0; b < mm; ++b) {
+          const int32_t j = cm[b];
+          int q = -1;
+          for (int e = 0; e < ne && q < 0; ++e)
+            if (scol[e] == j && (e < mi || e >= W2_NL)) q = e;
+          if (q < 0) {
+            if (ne == W2_NE) return CR_OK;  // row of L^2 too wide: no tables
+            q = ne++;
+            scol[q] = j;
+            sc1[q] = 0;
+            sc2[q] = 0;
+          }
+          sc2[q] += fi[a] * fm[b];
+        }
+      }
+      for (int e = ne; e < W2_NE; ++e) {
+        scol[e] = (int32_t)i;
+        sc1[e] = 0;
+        sc2[e] = 0;
+      }
+      const size_t o = (size_t)(i - t0) * W2_NE;
+      for (int e = 0; e < W2_NE; ++e) {
+        if (sc2[e] < -128 || sc2[e] > 127) return CR_OK;
+        tcol[o + e] = scol[e];
+        tc2[o + e] = sc2[e];
+        tc1[o + e] = sc1[e];
+        idx.push_back(scol[e]);
+      }
+    }
+    std::sort(idx.begin(), idx.end());
+    idx.erase(std::unique(idx.begin(), idx.end()), idx.end());
+    int32_t* it = tab.data() + t * W2_TAB;
+    int nint = 0, tot = 0;
+    size_t a = 0;
+    while (a < idx.size()) {
+      size_t b = a;
+      while (b + 1 < idx.size() && idx[b + 1] - idx[b] <= W2_GAP) ++b;
+      if (nint == W2_NI) return CR_OK;
+      it[2 + nint] = idx[a];
+      it[2 + W2_NI + nint] = tot;
+      tot += idx[b] - idx[a] + 1;
+      ++nint;
+      a = b + 1;
+    }
+    if (tot > W2_MAX) return CR_OK;
+    it[0] = nint;
+    it[1] = tot;
+    auto pos = [&](int32_t j) {
+      int q = 0;
+      while (q + 1 < nint && it[2 + q + 1] <= j) ++q;
+      return it[2 + W2_NI + q] + (j - it[2 + q]);
+    };
+    for (int64_t i = t0; i < t1; ++i) {
+      const size_t o = (size_t)(i - t0) * W2_NE;
+      for (int e = 0; e < W2_NE; ++e)
+        ent[(size_t)e * n + i] = pack(pos(tcol[o + e]), tc2[o + e], tc1[o + e]);
+    }
+  }
+  if (hipMalloc(&g.w2tab, sizeof(int32_t) * tab.size()) != hipSuccess ||
+      hipMalloc(&g.w2ent, sizeof(uint32_t) * ent.size()) != hipSuccess) {
+    set_error("device allocation of the ring-2 window tables failed");
+    return CR_ENOMEM;
+  }
+  CR_HIP(stage_to_device(g.w2tab, tab.data(), sizeof(int32_t) * tab.size(), st));
+  CR_HIP(stage_to_device(g.w2ent, ent.data(), sizeof(uint32_t) * ent.size(), st));
+  return CR_OK;
+}
+
 static cr_status build_geom(const cr_csr& L, Geom& g, const char* which, hipStream_t st) {
   const int64_t n = L.n;
   if (n <= 0 || !L.rowptr || !L.colidx || !L.val) {
@@ -1852,7 +1982,7 @@ static cr_status build_geom(const cr_csr& L, Geom& g, const char* which, hipStre
     CR_HIP(stage_to_device(g.witab, itab.data(), sizeof(int32_t) * itab.size(), st));
     CR_HIP(stage_to_device(g.wpos, wpos.data(), sizeof(uint16_t) * wpos.size(), st));
   }
-  return CR_OK;
+  return build_win2(g, nbr, st);
 }
 
 template <typename T>
@@ -1877,6 +2007,7 @@ static cr_status create_impl(const cr_problem_desc* d, cr_precision prec, void* 
   CR_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
   CR_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
   if (const char* e = std::getenv("CONNREG_OP_FORK")) P->op_fork = std::atoi(e) != 0;
+  if (const char* e = std::getenv("CONNREG_OP_FUSED")) P->op_fused = std::atoi(e);
   if (const char* e = std::getenv("CONNREG_PCG_BS")) P->pcg_bs = std::atoi(e) == NT ? NT : 1024;
   if (const char* e = std::getenv("CONNREG_PCG_XREG")) P->no_xreg = std::atoi(e) == 0;
   if (const char* e = std::getenv("CONNREG_PCG_XBS")) P->pcg_xbs = std::atoi(e) == NT ? NT : 512;
@@ -2033,6 +2164,8 @@ extern "C" void cr_problem_destroy(cr_problem* P) {
     if (g->deg) (void)hipFree(g->deg);
     if (g->witab) (void)hipFree(g->witab);
     if (g->wpos) (void)hipFree(g->wpos);
+    if (g->w2tab) (void)hipFree(g->w2tab);
+    if (g->w2ent) (void)hipFree(g->w2ent);
   }
   if (P->hscal) (void)hipHostFree(P->hscal);
   if (P->aux) {
@@ -2109,6 +2242,11 @@ static cr_status op_apply_run(cr_problem* P, int64_t r, const T* U, int64_t ldu,
   // for both.
   CR_HIP(hipEventRecord(P->ev_fork, st));
   CR_HIP(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
+  // fused form: T = Z H on the auxiliary stream while the source-side sweep
+  // (L_x V, L_x^2 V in one pass) runs on the caller's stream; then one
+  // target-side pass writes L_y U, L_y^2 U and Omega o (U T)
+  const bool fused = rr >= 1 && P->op_fused >= (sizeof(T) == 8 ? 1 : 2) &&
+                     op_win2_ok<T>(P->gy, rr, ninj) && op_win2_ok<T>(P->gx, rr, 0);
   auto data_term = [&]() -> cr_status {
     hipStream_t as = P->op_fork ? P->aux : st;
     if (r > 0) {
@@ -2129,11 +2267,22 @@ static cr_status op_apply_run(cr_problem* P, int64_t r, const T* U, int64_t ldu,
         CR_TRY(small_gemm(rr, ninj, rr, Zd, r, false, Ht, ninj, true, 1.0, Tm, r, as));
       }
     }
+    if (fused) return CR_OK;
     return masked_tall_gemm<T>(ny, rr, ninj, U, ldu, Tm, std::max<int64_t>(r, 1), P->bits,
                                (const T*)nullptr, 0, F + 2 * r * ldf, ldf, as);
   };
   const cr_status sd = data_term();
   cr_status ss = CR_OK;
+  if (sd == CR_OK && fused) {
+    ss = op_win2<T>(P->gx, rr, V, ldv, G, G + r * ldg, ldg, 0, nullptr, 0, nullptr, nullptr, 0,
+                    st);
+    CR_HIP(hipEventRecord(P->ev_join, P->aux));
+    CR_HIP(hipStreamWaitEvent(st, P->ev_join, 0));
+    if (ss == CR_OK)
+      ss = op_win2<T>(P->gy, rr, U, ldu, F, F + r * ldf, ldf, ninj, Tm, r, P->bits,
+                      F + 2 * r * ldf, ldf, st);
+    return ss;
+  }
   if (sd == CR_OK) {
     ss = stencil<T>(P->gy, rr, U, ldu, F, ldf, st);
     if (ss == CR_OK) ss = stencil<T>(P->gy, rr, F, ldf, F + r * ldf, ldf, st);

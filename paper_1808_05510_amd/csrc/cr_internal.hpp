@@ -80,6 +80,17 @@ constexpr int NT = 256;  // threads per workgroup for streaming kernels
 constexpr int WIN_NI = 16, WIN_MAX = 2048, WIN_GAP = 32;
 constexpr int WIN_TAB = 2 + 2 * WIN_NI;  // count, total, starts, LDS prefixes
 
+// Ring-2 window form (the fused sweep writing L w and L^2 w together): per
+// tile of W2_TILE consecutive voxels, the voxels that its rows of L^2 read, as
+// at most W2_NI intervals of total length at most W2_MAX; per voxel, W2_NE
+// packed entries (window position in bits 0-15, the L^2 coefficient in bits
+// 16-23 and the L coefficient in bits 24-31, both signed 8-bit): entries
+// 0..6 are the voxel and its present neighbours (the support of its row of
+// L, padded with the voxel and zero coefficients), entries 7..24 the rest of
+// its row of L^2 (padded the same way).  Built for stencil widths K <= 6.
+constexpr int W2_TILE = 64, W2_NI = 12, W2_MAX = 1024, W2_GAP = 32, W2_NE = 25, W2_NL = 7;
+constexpr int W2_TAB = 2 + 2 * W2_NI;  // count, total, starts, LDS prefixes
+
 struct Geom {
   int64_t n = 0;
   int K = 0;
@@ -88,6 +99,9 @@ struct Geom {
   // window tables (null when some tile's window does not fit):
   int32_t* witab = nullptr;  // device, ntile * WIN_TAB
   uint16_t* wpos = nullptr;  // device, (K + 1) * n: window position of i, then of nbr_k(i)
+  // ring-2 window tables (null when some tile's window or row does not fit):
+  int32_t* w2tab = nullptr;   // device, ceil(n / W2_TILE) * W2_TAB
+  uint32_t* w2ent = nullptr;  // device, W2_NE * n (entry e of voxel i at e * n + i)
 };
 
 // A column-block list: columns [col0, col0+ncols) of the logical matrix live
@@ -162,6 +176,17 @@ template <typename T>
 cr_status masked_tall_gemm(int64_t n, int r, int ninj, const T* U, int64_t ldu,
                            const double* Tm, int64_t ldt, const uint32_t* bits,
                            const T* OY, int64_t ldoy, T* N, int64_t ldn, hipStream_t st);
+
+// Fused operator sweep (ring-2 window form): out1 = L w, out2 = L^2 w for the
+// r columns of w (ldw; outputs ldo), and with N != nullptr also
+// N = Omega o (w T) (n x ninj, ldn; T: r x ninj double, ldt).  Needs the
+// geometry's ring-2 tables and ninj <= 128 (op_win2_ok).
+template <typename T>
+bool op_win2_ok(const Geom& g, int r, int ninj);
+template <typename T>
+cr_status op_win2(const Geom& g, int r, const T* w, int64_t ldw, T* out1, T* out2, int64_t ldo,
+                  int ninj, const double* Tm, int64_t ldt, const uint32_t* bits, T* N,
+                  int64_t ldn, hipStream_t st);
 
 // d_i = sum_a omega_ia h_a^2 (h: device double, ninj); tmp: 1 device double
 template <typename T>

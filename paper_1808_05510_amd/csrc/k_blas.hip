@@ -1031,6 +1031,189 @@ cr_status masked_tall_gemm(int64_t n, int r, int ninj, const T* U, int64_t ldu, 
   return CR_OK;
 }
 
+// ============================================================== fused operator sweep
+// One pass over a tile of W2_TILE consecutive voxels that writes L w and
+// L^2 w for every column of w and, with DATA, N = Omega o (w T) (the masked
+// data term of eq. multitermSylv) from the same staged values.  Columns go in
+// groups of four: the tile's ring-2 window of the group (the voxels its rows
+// of L^2 read) is staged into LDS with coalesced loads, double-buffered so
+// that the next group's loads are in flight while the current group is
+// computed.  Stencil role: thread (wave c, lane v) forms rows v of L and L^2
+// for column c of the group from 25 packed entries held in registers.
+// Product role: wave q owns injections 32q .. 32q + 31 and accumulates
+// (w T)^T over the groups on FP64 (or FP32) MFMA tiles, reading the w
+// fragments from the same LDS window (the tile's own voxels); the masked
+// result is stored once at the end.  w is read from memory once per call
+// (up to L2 re-use of window overlaps between neighbouring tiles) and L w is
+// never re-read, unlike two stencil passes followed by a separate product.
+constexpr int W2_EPT = W2_MAX / NT;  // window elements staged per thread
+
+template <typename T, bool DATA>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_op_win2(
+    int64_t n, unsigned nt_log, const int32_t* __restrict__ itab,
+    const uint32_t* __restrict__ ent, int r, const T* __restrict__ w, int64_t ldw,
+    T* __restrict__ out1, T* __restrict__ out2, int64_t ldo, int ninj,
+    const double* __restrict__ Tm, int64_t ldt, const uint32_t* __restrict__ bits,
+    T* __restrict__ N, int64_t ldn) {
+  typedef typename Mfma16<T>::acc_t acc_t;
+  __shared__ T buf[2][4][W2_MAX];
+  const int64_t tile = xcd_block(blockIdx.x, nt_log);
+  if (tile >= nt_log) return;  // uniform per workgroup
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  const int32_t* it = itab + tile * W2_TAB;
+  const int nint = it[0], tot = it[1];
+  // staging map: window element e = tid + NT m comes from voxel src[m]
+  int src[W2_EPT];
+#pragma unroll
+  for (int m = 0; m < W2_EPT; ++m) {
+    const int e = tid + NT * m;
+    int sv = -1;
+    if (e < tot) {
+      int q = 0;
+      for (int k = 1; k < nint; ++k)
+        if (it[2 + W2_NI + k] <= e) q = k;
+      sv = it[2 + q] + (e - it[2 + W2_NI + q]);
+    }
+    src[m] = sv;
+  }
+  const int64_t v0 = tile * W2_TILE;
+  const int64_t i = v0 + lane;  // stencil row of this thread
+  const bool valid = i < n;
+  uint32_t en[W2_NE];
+#pragma unroll
+  for (int e = 0; e < W2_NE; ++e) en[e] = valid ? ent[(int64_t)e * n + i] : 0u;
+  const int ngr = (r + 3) / 4;
+  T rg[4][W2_EPT];
+  auto load = [&](int g) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * g + q;
+      const T* wc = w + (int64_t)min(c, r - 1) * ldw;
+#pragma unroll
+      for (int m = 0; m < W2_EPT; ++m) rg[q][m] = (src[m] >= 0 && c < r) ? wc[src[m]] : (T)0;
+    }
+  };
+  auto stage = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int m = 0; m < W2_EPT; ++m)
+        if (tid + NT * m < tot) buf[b][q][tid + NT * m] = rg[q][m];
+  };
+  // product role: window positions of the tile's voxels 16 vb + fr, the
+  // wave's first injection, and its accumulators (injection x voxel tiles)
+  const int a0 = 32 * wv;
+  const bool prod = DATA && a0 < ninj;  // uniform per wave
+  int cpos[4];
+  acc_t acc[4][2];
+#pragma unroll
+  for (int vb = 0; vb < 4; ++vb) {
+    const int64_t v = v0 + 16 * vb + fr;
+    cpos[vb] = (prod && v < n) ? (int)(ent[v] & 0xffffu) : 0;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) acc[vb][cb] = acc_t{0, 0, 0, 0};
+  }
+  // T^T fragments of a group (rows: the wave's injections; k: the group's
+  // columns), fetched one group ahead like the window
+  T ta[2], tn[2];
+  auto loadT = [&](int g, T* x) {
+    const int k = 4 * g + fk;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int al = a0 + 16 * cb + fr;
+      x[cb] = (k < r && al < ninj) ? (T)Tm[(int64_t)al * ldt + k] : (T)0;
+    }
+  };
+  if (prod) loadT(0, tn);
+  load(0);
+  stage(0);
+  __syncthreads();
+  for (int g = 0; g < ngr; ++g) {
+    const int b = g & 1;
+    if (prod) {
+      ta[0] = tn[0];
+      ta[1] = tn[1];
+      if (g + 1 < ngr) loadT(g + 1, tn);
+    }
+    if (g + 1 < ngr) load(g + 1);
+    const int c = 4 * g + wv;
+    if (valid && c < r) {
+      const T* B = buf[b][wv];
+      T s1 = (T)0, s2 = (T)0;
+#pragma unroll
+      for (int e = 0; e < W2_NL; ++e) {
+        const T x = B[en[e] & 0xffffu];
+        s1 += (T)((int32_t)en[e] >> 24) * x;
+        s2 += (T)((int32_t)(en[e] << 8) >> 24) * x;
+      }
+#pragma unroll
+      for (int e = W2_NL; e < W2_NE; ++e)
+        s2 += (T)((int32_t)(en[e] << 8) >> 24) * B[en[e] & 0xffffu];
+      out1[(int64_t)c * ldo + i] = s1;
+      out2[(int64_t)c * ldo + i] = s2;
+    }
+    if (prod) {
+      const T* B = buf[b][fk];
+#pragma unroll
+      for (int vb = 0; vb < 4; ++vb) {
+        const T x = B[cpos[vb]];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[vb][cb] = Mfma16<T>::mma(ta[cb], x, acc[vb][cb]);
+      }
+    }
+    if (g + 1 < ngr) stage(b ^ 1);
+    __syncthreads();
+  }
+  if (prod) {
+    const uint32_t* wb = bits + (int64_t)(a0 >> 5) * n;
+#pragma unroll
+    for (int vb = 0; vb < 4; ++vb) {
+      const int64_t v = v0 + 16 * vb + fr;
+      if (v < n) {
+        const uint32_t wd = wb[v];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int al_loc = 16 * cb + Mfma16<T>::row(fk, e);  // < 32
+            const int al = a0 + al_loc;
+            if (al < ninj) N[(int64_t)al * ldn + v] = (T)((wd >> al_loc) & 1u) * acc[vb][cb][e];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+bool op_win2_ok(const Geom& g, int r, int ninj) {
+  return g.w2tab && g.w2ent && r >= 1 && ninj <= 4 * 32 && g.n <= INT32_MAX;
+}
+
+template <typename T>
+cr_status op_win2(const Geom& g, int r, const T* w, int64_t ldw, T* out1, T* out2, int64_t ldo,
+                  int ninj, const double* Tm, int64_t ldt, const uint32_t* bits, T* N,
+                  int64_t ldn, hipStream_t st) {
+  if (g.n == 0 || r <= 0) return CR_OK;
+  if (!op_win2_ok<T>(g, r, N ? ninj : 0)) {
+    set_error("fused operator sweep: no ring-2 tables for this geometry or sizes out of range");
+    return CR_EINVAL;
+  }
+  const unsigned nt_log = (unsigned)((g.n + W2_TILE - 1) / W2_TILE);
+  const unsigned nb_phys = (nt_log + NXCD - 1) / NXCD * NXCD;
+  if (N)
+    hipLaunchKernelGGL((k_op_win2<T, true>), dim3(nb_phys), dim3(NT), 0, st, g.n, nt_log,
+                       g.w2tab, g.w2ent, r, w, ldw, out1, out2, ldo, ninj, Tm, ldt, bits, N,
+                       ldn);
+  else
+    hipLaunchKernelGGL((k_op_win2<T, false>), dim3(nb_phys), dim3(NT), 0, st, g.n, nt_log,
+                       g.w2tab, g.w2ent, r, w, ldw, out1, out2, ldo, 0, (const double*)nullptr,
+                       0, (const uint32_t*)nullptr, (T*)nullptr, 0);
+  CR_HIP(hipGetLastError());
+  return CR_OK;
+}
+
 // ============================================================== masked reductions
 // d_i = sum_a omega_ia h_a^2 = sum_a h_a^2 - sum_{a: omega_ia = 0} h_a^2
 __global__ __launch_bounds__(NT) void k_hsq(int ninj, const double* __restrict__ h,
@@ -1349,6 +1532,10 @@ cr_status hole_gram_col(int ninj, const int32_t* hptr, const int32_t* hidx, int 
   template cr_status masked_tall_gemm<T>(int64_t, int, int, const T*, int64_t, const double*,   \
                                          int64_t, const uint32_t*, const T*, int64_t, T*,       \
                                          int64_t, hipStream_t);                                 \
+  template bool op_win2_ok<T>(const Geom&, int, int);                                           \
+  template cr_status op_win2<T>(const Geom&, int, const T*, int64_t, T*, T*, int64_t, int,      \
+                                const double*, int64_t, const uint32_t*, T*, int64_t,          \
+                                hipStream_t);                                                   \
   template cr_status masked_quad_ws<T>(int64_t, int, const uint32_t*, const double*, T*,        \
                                        double*, hipStream_t);                                   \
   template cr_status masked_colsq<T>(int64_t, int, const uint32_t*, const T*, double*,          \

@@ -44,8 +44,11 @@ def shells():
     return d, oop.problem_from_arrays(d)
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_op_apply_full_shells_r100(shells, fp32):
+def test_op_apply_full_shells_r100(shells, fp32, fused, monkeypatch):
+    """Default path, and the fused ring-2 window sweeps (CONNREG_OP_FUSED=2)."""
+    monkeypatch.setenv("CONNREG_OP_FUSED", "2" if fused else "0")
     d, P = shells
     r = 100
     rng = np.random.default_rng(21)

@@ -166,6 +166,37 @@ def test_op_apply_fp32(case, r):
     assert rel(F[:, 2 * r:], f.M) < 2e-6
 
 
+@pytest.mark.parametrize("r", [1, 7, 67, 100, 150])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_op_apply_fused_sweep(case, r, fp32, monkeypatch):
+    """The fused ring-2 window sweeps (CONNREG_OP_FUSED=2: L w and L^2 w in
+    one pass per side, the masked product from the target pass's staged
+    values) against the oracle at the same bars as the default path.  The
+    scrambled geometry has no ring-2 tables and 150 injections exceed the
+    fused product's 128: both take the default path."""
+    monkeypatch.setenv("CONNREG_OP_FUSED", "2")
+    name, d, P = case
+    r = min(r, P.n_x)
+    rng = np.random.default_rng(r + 31)
+    U = rng.standard_normal((P.n_y, r))
+    V = rng.standard_normal((P.n_x, r))
+    Z = rng.standard_normal((r, r))
+    if fp32:
+        U, V, Z = (a.astype(np.float32).astype(np.float64) for a in (U, V, Z))
+    g = connreg.Problem(d, "mixed" if fp32 else "fp64", DEV)
+    F, G = g.op_apply(U, Z, V, fp32=fp32)
+    g.close()
+    f = oop.op_apply(P, U, Z, V)
+    F, G = np_(F).astype(np.float64), np_(G).astype(np.float64)
+    tol, tol_m = (2e-6, 2e-6) if fp32 else (1e-13, 1e-12)
+    for a, b in ((F[:, :r], f.LyU), (F[:, r:2 * r], f.Ly2U), (G[:, :r], f.LxV),
+                 (G[:, r:], f.Lx2V)):
+        assert rel(a, b) < tol
+        assert max_rel(a, b) < tol
+    assert rel(F[:, 2 * r:], f.M) < tol_m
+    assert max_rel(F[:, 2 * r:], f.M) < tol_m
+
+
 # ------------------------------------------------------------------ residual norm
 def test_residual_norm(case):
     name, d, P = case
