@@ -533,16 +533,18 @@ struct Ctx {
     // voxels per thread, whose per-phase latency grows faster than the grid
     // barrier (3 us at 64, 8 us at 256 groups) shrinks; wider workgroups
     // (pcg_bs) cut the group count without adding work per thread.
-    // u-systems whose one-voxel grid exceeds PCG_U_VPT2_WG workgroups take two
-    // voxels per thread, halving the arrivals at the grid barrier (1024-thread
-    // groups: the cortex shells 5.77 -> 5.55 s and the flatmap-sized map
-    // 11.86 -> 11.35 s, both FP64; the 40^3 grid's 63 groups stay at one,
-    // where two measured slower)
+    // u-systems without the two-barrier form (no rows of L^2 for it) whose
+    // one-voxel grid exceeds PCG_U_VPT2_WG workgroups take two voxels per
+    // thread, halving the arrivals at the grid barrier (1024-thread groups,
+    // three barriers: the cortex shells 5.77 -> 5.55 s and the flatmap-sized
+    // map 11.86 -> 11.35 s, both FP64).  The two-barrier form holds one voxel
+    // per thread and beats both on the shells (FP64 5.38 s, mixed 2.45
+    // against 2.80 s).
     pcg_bs = P->cu_share > 0 ? NT : P->pcg_bs;
     auto pick = [&](const Geom& g, const T* Xm, int& vpt, int& nwg) -> bool {
       const int tuned = Xm ? P->tuned_vpt_v : P->tuned_vpt_u;
       int want = vpt_opt > 0 ? vpt_opt : tuned;
-      if (want <= 0 && !Xm && P->cu_share <= 0 &&
+      if (want <= 0 && !Xm && P->cu_share <= 0 && !g.r2idx &&
           (g.n + (int64_t)pcg_bs - 1) / pcg_bs > PCG_U_VPT2_WG)
         want = 2;
       for (int v = 1; v <= 8; v *= 2) {
@@ -1716,16 +1718,17 @@ struct Ctx {
 };
 
 // ===================================================================== create / destroy
-// Ring-2 window tables of the fused operator sweep (left null when some row
-// of L^2 or some tile's window does not fit; the sweep then falls back to two
-// stencil passes).  Row i of L = K I - N (N: the self-padded neighbour
+// Rows of L^2: the two-barrier PCG's tables, and the ring-2 window tables of
+// the fused operator sweep (each left null when some row of L^2 or some
+// tile's window does not fit; the PCG then takes three barriers per
+// iteration, the operator application two stencil passes).  Row i of L = K I - N (N: the self-padded neighbour
 // table) has the diagonal K - #self slots and -1 per present neighbour; row
 // i of L^2 is the sum over the entries (m, a) of row i of L of a times row m.
-static cr_status build_win2(Geom& g, const std::vector<int32_t>& nbr, hipStream_t st) {
+static cr_status build_win2(Geom& g, const std::vector<int32_t>& nbr, bool target,
+                            hipStream_t st) {
   const int64_t n = g.n;
   const int K = g.K;
   if (K > W2_NL - 1 || n == 0) return CR_OK;
-  std::vector<uint32_t> ent((size_t)W2_NE * n);
   // row i of L as (column, coefficient), the diagonal first
   auto lrow = [&](int64_t i, int32_t* col, int* cf) {
     int m = 1, self = 0;
@@ -1743,64 +1746,102 @@ static cr_status build_win2(Geom& g, const std::vector<int32_t>& nbr, hipStream_
     cf[0] = K - self;
     return m;
   };
+  // every voxel's entries as (voxel, c2, c1): 0..W2_NL-1 the support of its
+  // row of L (with c1), padded with the voxel itself; the rest of its row of
+  // L^2 after them, padded the same way
+  std::vector<int32_t> ecol((size_t)W2_NE * n);
+  std::vector<int8_t> ec2((size_t)W2_NE * n), ec1((size_t)W2_NE * n);
+  int32_t scol[W2_NE];
+  int sc2[W2_NE], sc1[W2_NE];
+  int32_t ci[W2_NL], cm[W2_NL];
+  int fi[W2_NL], fm[W2_NL];
+  for (int64_t i = 0; i < n; ++i) {
+    const int mi = lrow(i, ci, fi);
+    int ne = W2_NL;
+    for (int a = 0; a < W2_NL; ++a) {
+      scol[a] = a < mi ? ci[a] : (int32_t)i;
+      sc1[a] = a < mi ? fi[a] : 0;
+      sc2[a] = 0;
+    }
+    for (int a = 0; a < mi; ++a) {
+      const int mm = lrow(ci[a], cm, fm);
+      for (int b = 0; b < mm; ++b) {
+        const int32_t j = cm[b];
+        int q = -1;
+        for (int e = 0; e < ne && q < 0; ++e)
+          if (scol[e] == j && (e < mi || e >= W2_NL)) q = e;
+        if (q < 0) {
+          if (ne == W2_NE) return CR_OK;  // row of L^2 too wide: no tables
+          q = ne++;
+          scol[q] = j;
+          sc1[q] = 0;
+          sc2[q] = 0;
+        }
+        sc2[q] += fi[a] * fm[b];
+      }
+    }
+    for (int e = ne; e < W2_NE; ++e) {
+      scol[e] = (int32_t)i;
+      sc1[e] = 0;
+      sc2[e] = 0;
+    }
+    for (int e = 0; e < W2_NE; ++e) {
+      if (sc2[e] < -128 || sc2[e] > 127) return CR_OK;
+      ecol[(size_t)i * W2_NE + e] = scol[e];
+      ec2[(size_t)i * W2_NE + e] = (int8_t)sc2[e];
+      ec1[(size_t)i * W2_NE + e] = (int8_t)sc1[e];
+    }
+  }
+  // the two-barrier PCG's tables, by default for the target geometry (the
+  // u-systems) only.  The v-systems' low-rank term needs the sums of all
+  // workgroups' X^T z partials in every workgroup, which read more than the
+  // third barrier costs (40^3 / 30^3 FP64 solve: 2.39 s with three barriers,
+  // 2.34 s with the two-barrier u-systems, 3.01 s with both).
+  // CONNREG_PCG_R2: 0 none, u (default) target, v source, 1 both
+  const char* r2env = std::getenv("CONNREG_PCG_R2");
+  const char* r2sel = r2env ? r2env : "u";
+  const bool r2want = std::strcmp(r2sel, "1") == 0 ||
+                      (std::strcmp(r2sel, "u") == 0 && target) ||
+                      (std::strcmp(r2sel, "v") == 0 && !target);
+  if (r2want) {
+    std::vector<int32_t> ridx((size_t)R2_NX * n);
+    std::vector<int8_t> rcf((size_t)R2_NC * n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      const size_t o = (size_t)i * W2_NE;
+      rcf[(size_t)i] = ec2[o];
+      for (int k = 0; k < K; ++k) {
+        const int32_t j = nbr[(size_t)k * n + i];
+        int8_t c = 0;
+        if (j != (int32_t)i)
+          for (int e = 1; e < W2_NL; ++e)
+            if (ecol[o + e] == j && ec1[o + e] != 0) c = ec2[o + e];
+        rcf[(size_t)(1 + k) * n + i] = c;
+      }
+      for (int e = 0; e < R2_NX; ++e) {
+        ridx[(size_t)e * n + i] = ecol[o + W2_NL + e];
+        rcf[(size_t)(R2_C0 + e) * n + i] = ec2[o + W2_NL + e];
+      }
+    }
+    if (hipMalloc(&g.r2idx, sizeof(int32_t) * ridx.size()) != hipSuccess ||
+        hipMalloc(&g.r2cf, rcf.size()) != hipSuccess) {
+      set_error("device allocation of the L^2 row tables failed");
+      return CR_ENOMEM;
+    }
+    CR_HIP(stage_to_device(g.r2idx, ridx.data(), sizeof(int32_t) * ridx.size(), st));
+    CR_HIP(stage_to_device(g.r2cf, rcf.data(), rcf.size(), st));
+  }
+  // window tables of the fused operator sweep
   auto pack = [](int pos, int c2, int c1) {
     return (uint32_t)pos | ((uint32_t)(uint8_t)(int8_t)c2 << 16) |
            ((uint32_t)(uint8_t)(int8_t)c1 << 24);
   };
   const int64_t nt2 = (n + W2_TILE - 1) / W2_TILE;
+  std::vector<uint32_t> ent((size_t)W2_NE * n);
   std::vector<int32_t> tab((size_t)nt2 * W2_TAB, 0);
   std::vector<int32_t> idx;
-  int32_t scol[W2_NE];
-  int sc2[W2_NE], sc1[W2_NE];
-  // the tile's entries as (voxel, c2, c1), before window positions exist
-  std::vector<int32_t> tcol((size_t)W2_TILE * W2_NE);
-  std::vector<int> tc2((size_t)W2_TILE * W2_NE), tc1((size_t)W2_TILE * W2_NE);
-  int32_t ci[W2_NL], cm[W2_NL];
-  int fi[W2_NL], fm[W2_NL];
   for (int64_t t = 0; t < nt2; ++t) {
     const int64_t t0 = t * W2_TILE, t1 = std::min(n, t0 + W2_TILE);
-    idx.clear();
-    for (int64_t i = t0; i < t1; ++i) {
-      const int mi = lrow(i, ci, fi);
-      // entries 0..W2_NL-1: the support of row i of L (with c1), padded with
-      // the voxel itself; the rest of row i of L^2 follows
-      int ne = W2_NL;
-      for (int a = 0; a < W2_NL; ++a) {
-        scol[a] = a < mi ? ci[a] : (int32_t)i;
-        sc1[a] = a < mi ? fi[a] : 0;
-        sc2[a] = 0;
-      }
-      for (int a = 0; a < mi; ++a) {
-        const int mm = lrow(ci[a], cm, fm);
-        for (int b = 0; b < mm; ++b) {
-          const int32_t j = cm[b];
-          int q = -1;
-          for (int e = 0; e < ne && q < 0; ++e)
-            if (scol[e] == j && (e < mi || e >= W2_NL)) q = e;
-          if (q < 0) {
-            if (ne == W2_NE) return CR_OK;  // row of L^2 too wide: no tables
-            q = ne++;
-            scol[q] = j;
-            sc1[q] = 0;
-            sc2[q] = 0;
-          }
-          sc2[q] += fi[a] * fm[b];
-        }
-      }
-      for (int e = ne; e < W2_NE; ++e) {
-        scol[e] = (int32_t)i;
-        sc1[e] = 0;
-        sc2[e] = 0;
-      }
-      const size_t o = (size_t)(i - t0) * W2_NE;
-      for (int e = 0; e < W2_NE; ++e) {
-        if (sc2[e] < -128 || sc2[e] > 127) return CR_OK;
-        tcol[o + e] = scol[e];
-        tc2[o + e] = sc2[e];
-        tc1[o + e] = sc1[e];
-        idx.push_back(scol[e]);
-      }
-    }
+    idx.assign(ecol.begin() + (size_t)t0 * W2_NE, ecol.begin() + (size_t)t1 * W2_NE);
     std::sort(idx.begin(), idx.end());
     idx.erase(std::unique(idx.begin(), idx.end()), idx.end());
     int32_t* it = tab.data() + t * W2_TAB;
@@ -1825,9 +1866,9 @@ static cr_status build_win2(Geom& g, const std::vector<int32_t>& nbr, hipStream_
       return it[2 + W2_NI + q] + (j - it[2 + q]);
     };
     for (int64_t i = t0; i < t1; ++i) {
-      const size_t o = (size_t)(i - t0) * W2_NE;
+      const size_t o = (size_t)i * W2_NE;
       for (int e = 0; e < W2_NE; ++e)
-        ent[(size_t)e * n + i] = pack(pos(tcol[o + e]), tc2[o + e], tc1[o + e]);
+        ent[(size_t)e * n + i] = pack(pos(ecol[o + e]), ec2[o + e], ec1[o + e]);
     }
   }
   if (hipMalloc(&g.w2tab, sizeof(int32_t) * tab.size()) != hipSuccess ||
@@ -1982,7 +2023,7 @@ static cr_status build_geom(const cr_csr& L, Geom& g, const char* which, hipStre
     CR_HIP(stage_to_device(g.witab, itab.data(), sizeof(int32_t) * itab.size(), st));
     CR_HIP(stage_to_device(g.wpos, wpos.data(), sizeof(uint16_t) * wpos.size(), st));
   }
-  return build_win2(g, nbr, st);
+  return build_win2(g, nbr, which[2] == 'y', st);
 }
 
 template <typename T>
@@ -2166,6 +2207,8 @@ extern "C" void cr_problem_destroy(cr_problem* P) {
     if (g->wpos) (void)hipFree(g->wpos);
     if (g->w2tab) (void)hipFree(g->w2tab);
     if (g->w2ent) (void)hipFree(g->w2ent);
+    if (g->r2idx) (void)hipFree(g->r2idx);
+    if (g->r2cf) (void)hipFree(g->r2cf);
   }
   if (P->hscal) (void)hipHostFree(P->hscal);
   if (P->aux) {

@@ -102,7 +102,15 @@ struct Geom {
   // ring-2 window tables (null when some tile's window or row does not fit):
   int32_t* w2tab = nullptr;   // device, ceil(n / W2_TILE) * W2_TAB
   uint32_t* w2ent = nullptr;  // device, W2_NE * n (entry e of voxel i at e * n + i)
+  // rows of L^2 for the two-barrier PCG (null when some row does not fit):
+  // r2idx[e * n + i] (e < R2_NX): the voxels of row i of L^2 outside the
+  // support of row i of L (padded with i); r2cf[e * n + i]: the L^2
+  // coefficients, e = 0 the diagonal, 1 + k the neighbour in slot k of the
+  // ELL table (0 for a self-padded slot), R2_C0 + e that of r2idx entry e
+  int32_t* r2idx = nullptr;  // device, R2_NX * n
+  int8_t* r2cf = nullptr;    // device, R2_NC * n
 };
+constexpr int R2_NX = W2_NE - W2_NL, R2_C0 = W2_NL, R2_NC = W2_NE;
 
 // A column-block list: columns [col0, col0+ncols) of the logical matrix live
 // at p + (c-col0)*ld.  Up to 6 blocks, passed by value to kernels.

@@ -223,8 +223,10 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // residual of every workgroup, so each z update takes one more grid barrier
 // (four per iteration).
 template <typename T, int K, bool LR, int VPT, int BS, int NXR, bool XTAIL = false,
-          bool CO = false, bool XLDS = false>
+          bool CO = false, bool XLDS = false, bool R2 = false>
 __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
+  static_assert(!R2 || (VPT == 1 && !XTAIL && !CO && !XLDS && (!LR || NXR > 0)),
+                "the two-barrier form: one voxel per thread, no tail of X, no coarse level");
   static_assert(!XTAIL || NXR > 0, "a streamed tail follows register rows");
   static_assert(!XLDS || (XTAIL && !CO), "the LDS-resident rows are part of the tail");
   static_assert(NXR == 0 || (LR && VPT == 1), "register-resident X needs LR and VPT 1");
@@ -239,6 +241,12 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   __shared__ double cys[CO ? CO_MAXLOC : 1];  // Ainv rc of the workgroup's aggregates
   extern __shared__ double xtl_raw[];
   T* const xtl = reinterpret_cast<T*>(xtl_raw);  // XLDS: tail rows (type T), xtl[(al - NXR) * BS + thread]
+  // R2: this thread's row of L^2 (ring-2 voxels and all coefficients), and
+  // the workgroup's own copy of s = X^T p with its reduction slots
+  __shared__ int32_t r2x[R2 ? R2_NX : 1][R2 ? BS : 1];
+  __shared__ int8_t r2k[R2 ? R2_NC : 1][R2 ? BS : 1];
+  __shared__ double s2[R2 && LR ? NXR : 1];
+  __shared__ double s2n[R2 && LR ? NXR : 1];
   const int64_t n = a.g.n;
   const int nwg = gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * BS * VPT;
@@ -313,6 +321,15 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       for (int al = NXR; al < NXR + a.xlds; ++al)
         xtl[(al - NXR) * BS + threadIdx.x] = (i0 >= 0 && i0 < n) ? Xm[(int64_t)al * ldx + i0] : (T)0;
     }
+  }
+  if constexpr (R2) {
+    const int64_t i0 = vox(0);
+    const bool in = i0 >= 0 && i0 < n;
+#pragma unroll
+    for (int e = 0; e < R2_NX; ++e) r2x[e][threadIdx.x] = in ? a.g.r2idx[(int64_t)e * n + i0] : 0;
+#pragma unroll
+    for (int e = 0; e < R2_NC; ++e)
+      r2k[e][threadIdx.x] = in ? a.g.r2cf[(int64_t)e * n + i0] : (int8_t)0;
   }
   // per-workgroup partials of X^T z into lrpart (z of this thread's voxels)
   auto lr_part = [&](const double* zv) {
@@ -416,34 +433,128 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   const double tol2 = a.rtol * a.rtol * bnorm2;
   if (!(bnorm2 > 0.0)) status = 2;  // zero or non-finite right-hand side
 
+  constexpr int KP = VPT <= 2 ? K : 1;
+  double q[VPT];
+#pragma unroll
+  for (int m = 0; m < VPT; ++m) q[m] = 0.0;
+  // R2 (one voxel per thread): u = L^2 p kept by its own recurrence from
+  // L^2 z, formed from z at the ring-2 voxels of the thread's row of L^2,
+  // so that q = A p needs no neighbour values of t and no third barrier.
+  // Every workgroup also sums all workgroups' X^T z partials itself (in the
+  // same order, so the copies of s = X^T p agree bit for bit).
+  double u2 = 0.0;
+  double zn1[R2 ? K : 1], z2[R2 ? R2_NX : 1];
+  auto r2_load = [&]() {
+    if constexpr (R2) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) zn1[k] = ok[0] ? (double)zg[nb[0][k]] : 0.0;
+#pragma unroll
+      for (int e = 0; e < R2_NX; ++e) z2[e] = ok[0] ? (double)zg[r2x[e][threadIdx.x]] : 0.0;
+      if constexpr (LR) {
+        // wave w sums injections w, w + BS/WAVE, ...: every partial load of
+        // a lane is issued before the first wave sum
+        constexpr int NJ = (NXR > 0 ? NXR : 1) / (BS / WAVE);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        double acc[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = 0.0;
+        for (int b = lane; b < nwg; b += WAVE) {
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            const int al = wv + (BS / WAVE) * j;
+            if (al < ninj) acc[j] += lrpart[(int64_t)al * nwg + b];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int al = wv + (BS / WAVE) * j;
+          const double v = wsum(acc[j]);
+          if (lane == 0 && al < ninj) s2n[al] = v;
+        }
+      }
+    }
+  };
+  auto r2_update = [&](double beta, bool first) {
+    if constexpr (R2) {
+      if (ok[0]) {
+        double lz = (double)K * z[0];
+        double l2 = (double)r2k[0][threadIdx.x] * z[0];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          lz -= zn1[k];
+          l2 += (double)r2k[1 + k][threadIdx.x] * zn1[k];
+        }
+#pragma unroll
+        for (int e = 0; e < R2_NX; ++e) l2 += (double)r2k[R2_C0 + e][threadIdx.x] * z2[e];
+        p[0] = (double)(T)(z[0] + beta * p[0]);
+        t[0] = (double)(T)(lz + beta * t[0]);
+        u2 = (double)(T)(l2 + beta * u2);
+      }
+      if constexpr (LR) {
+        __syncthreads();
+        for (int al = threadIdx.x; al < ninj; al += BS) {
+          s2[al] = first ? s2n[al] : s2n[al] + beta * s2[al];
+          slr[al] = a.gw[al] * s2[al];
+        }
+        __syncthreads();
+      }
+      double pq = 0.0;
+      q[0] = 0.0;
+      if (ok[0]) {
+        double qi = lam * (u2 + c1 * t[0] + c0 * p[0]) + dd[0] * p[0];
+        if constexpr (LR) {
+          double sacc = 0.0;
+#pragma unroll
+          for (int al = 0; al < (NXR > 0 ? NXR : 1); ++al) sacc += xz(al, slr[al]);
+          qi += sacc;
+        }
+        q[0] = (double)(T)qi;
+        pq = p[0] * q[0];
+      }
+      // (with the low-rank term the workgroup barriers above already
+      // separate this write of red from the grid total's reads of it)
+      pq = block_sum<BS, !LR>(pq, red);
+      if (threadIdx.x == 0) part[0 * nwg + blockIdx.x] = pq;
+    }
+  };
+
   if (status == 0 && !(rr <= tol2)) {
-    // ---- p = z, t = L z, s = X^T z
+    if constexpr (R2) {
+      // ---- p = z, t = L z, u = L^2 z, s = X^T z (reduced in every
+      // workgroup), q = A p and its partial p.q: the loop then starts with
+      // phase C and ends with phase D, two grid barriers per iteration
+      r2_load();
+      r2_update(0.0, true);
+      grid_barrier(a.bar, grid);
+    } else {
+      // ---- p = z, t = L z, s = X^T z
 #pragma unroll
-    for (int m = 0; m < VPT; ++m) {
-      if (ok[m]) {
-        double s = (double)K * z[m];
+      for (int m = 0; m < VPT; ++m) {
+        if (ok[m]) {
+          double s = (double)K * z[m];
 #pragma unroll
-        for (int k = 0; k < K; ++k) s -= (double)zg[nb[m][k]];
-        p[m] = z[m];
-        t[m] = (double)(T)s;
-        tg[vox(m)] = (T)t[m];
+          for (int k = 0; k < K; ++k) s -= (double)zg[nb[m][k]];
+          p[m] = z[m];
+          t[m] = (double)(T)s;
+          tg[vox(m)] = (T)t[m];
+        }
       }
-    }
-    if (LR) {
-      for (int al = blockIdx.x; al < ninj; al += nwg) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nwg; b += BS) s += lrpart[(int64_t)al * nwg + b];
-        s = block_sum<BS>(s, red);
-        if (threadIdx.x == 0) a.sbuf[al] = s;
+      if (LR) {
+        for (int al = blockIdx.x; al < ninj; al += nwg) {
+          double s = 0.0;
+          for (int b = threadIdx.x; b < nwg; b += BS) s += lrpart[(int64_t)al * nwg + b];
+          s = block_sum<BS>(s, red);
+          if (threadIdx.x == 0) a.sbuf[al] = s;
+        }
       }
+      grid_barrier(a.bar, grid);
     }
-    grid_barrier(a.bar, grid);
 
     for (it = 0; it < a.maxit; ++it) {
+      if constexpr (!R2) {
       // ---- phase B: q = A p, partial p.q
       // (the neighbour t values are loaded before the low-rank set-up's
       // workgroup barrier, so the two latencies overlap)
-      constexpr int KP = VPT <= 2 ? K : 1;
       double tn[VPT <= 2 ? VPT : 1][KP];
       if constexpr (VPT <= 2) {
 #pragma unroll
@@ -455,7 +566,6 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         for (int al = threadIdx.x; al < ninj; al += BS) slr[al] = a.gw[al] * a.sbuf[al];
         __syncthreads();
       }
-      double q[VPT];
       double pq = 0.0;
 #pragma unroll
       for (int m = 0; m < VPT; ++m) {
@@ -499,6 +609,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       pq = block_sum<BS, false>(pq, red);
       if (threadIdx.x == 0) part[0 * nwg + blockIdx.x] = pq;
       grid_barrier(a.bar, grid);
+      }
 
       // ---- phase C: x += alpha p, r -= alpha q, z = M^-1 r
       const double pq_tot = grid_total<BS, false>(part, 0, nwg, red);
@@ -592,6 +703,20 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
       // ---- phase D: beta, convergence, p = z + beta p, t = L z + beta t
       // (the neighbour z values and this workgroup's first low-rank partial
       // sum are loaded before the reduction, so their latency overlaps it)
+      if constexpr (R2) {
+        // two-barrier form: also u = L^2 z + beta u and s = X^T z + beta s,
+        // then q = A p and its partial p.q (phase B folded in)
+        r2_load();
+        double rz_new;
+        grid_total2<BS, false>(part, 1, 2, nwg, red, rz_new, rr);
+        if (rr <= tol2) {
+          ++it;
+          break;
+        }
+        const double beta = rz_new / rz_cur;
+        rz_cur = rz_new;
+        r2_update(beta, false);
+      } else {
       double zn[VPT <= 2 ? VPT : 1][KP];
       if constexpr (VPT <= 2) {
 #pragma unroll
@@ -637,6 +762,7 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
           s = block_sum<BS>(s, red);
           if (threadIdx.x == 0) a.sbuf[al] = s + beta * a.sbuf[al];
         }
+      }
       }
       grid_barrier(a.bar, grid);
     }
@@ -751,6 +877,40 @@ static void* pcg_select(int K, bool lr, int vpt, int bs, int nxr, int xtail, boo
   }
 }
 
+// The two-barrier form (R2) where the geometry has its rows of L^2 and the
+// launch holds one voxel per thread with no tail of X and no coarse level.
+template <typename T>
+static void* pcg_select_r2(const PcgArgs<T>& a, bool co) {
+  if (!a.g.r2idx || !a.g.r2cf || co || a.vpt != 1 || a.xtail != 0) return nullptr;
+  const bool lr = a.Xm != nullptr;
+  switch (a.g.K) {
+#define R2CASE(KK)                                                                          \
+  case KK:                                                                                  \
+    if (!lr)                                                                                \
+      return a.bs == 1024 ? (void*)&k_pcg<T, KK, false, 1, 1024, 0, false, false, false, true> \
+             : a.bs == NT ? (void*)&k_pcg<T, KK, false, 1, NT, 0, false, false, false, true>   \
+                          : nullptr;                                                        \
+    if (a.nxr == PCG_NXR)                                                                   \
+      return a.bs == NT ? (void*)&k_pcg<T, KK, true, 1, NT, PCG_NXR, false, false, false, true> \
+             : a.bs == 512                                                                  \
+                 ? (void*)&k_pcg<T, KK, true, 1, 512, PCG_NXR, false, false, false, true>   \
+                 : nullptr;                                                                 \
+    if constexpr (std::is_same<T, float>::value) {                                         \
+      if (a.nxr == PCG_NXR2)                                                                \
+        return a.bs == NT                                                                   \
+                   ? (void*)&k_pcg<T, KK, true, 1, NT, PCG_NXR2, false, false, false, true> \
+                   : a.bs == 512                                                            \
+                         ? (void*)&k_pcg<T, KK, true, 1, 512, PCG_NXR2, false, false, false, true> \
+                         : nullptr;                                                         \
+    }                                                                                       \
+    return nullptr;
+    R2CASE(4) R2CASE(6)
+#undef R2CASE
+    default:
+      return nullptr;
+  }
+}
+
 // dynamic LDS of a launch: the tail rows of the LDS-resident form
 template <typename T>
 static size_t pcg_dyn_lds(const PcgArgs<T>& a) {
@@ -759,8 +919,10 @@ static size_t pcg_dyn_lds(const PcgArgs<T>& a) {
 
 template <typename T>
 int pcg_max_wg(const PcgArgs<T>& a) {
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail,
-                           a.co.slot_vox != nullptr);
+  void* fn = pcg_select_r2<T>(a, a.co.slot_vox != nullptr);
+  if (!fn)
+    fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail,
+                       a.co.slot_vox != nullptr);
   if (!fn) return 0;
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -785,8 +947,10 @@ cr_status pcg_solve(const PcgArgs<T>& a, int nwg, hipStream_t st) {
     set_error("pcg: grid does not cover the voxels");
     return CR_EINVAL;
   }
-  void* fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail,
-                           a.co.slot_vox != nullptr);
+  void* fn = pcg_select_r2<T>(a, a.co.slot_vox != nullptr);
+  if (!fn)
+    fn = pcg_select<T>(a.g.K, a.Xm != nullptr, a.vpt, a.bs, a.nxr, a.xtail,
+                       a.co.slot_vox != nullptr);
   if (!fn) {
     set_error("pcg: unsupported stencil width or voxels per thread");
     return CR_EINVAL;

@@ -276,6 +276,32 @@ def test_greedy_lockstep(case, prec, tol):
         assert abs(hg["relres"] - ho["relres"]) <= (1e-5 if prec == "fp64" else 1e-3) * ho["relres"]
 
 
+@pytest.mark.parametrize("r2", ["0", "1"])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-6), ("mixed", 1e-4)])
+def test_greedy_lockstep_pcg_barrier_forms(monkeypatch, r2, prec, tol):
+    """The PCG with three grid barriers per iteration everywhere
+    (CONNREG_PCG_R2=0) and with two in every eligible system, the v-systems'
+    low-rank term included (=1; the default takes two in the u-systems only),
+    in lockstep with the oracle on the ragged box at the default bars."""
+    monkeypatch.setenv("CONNREG_PCG_R2", r2)
+    d = mid_box()
+    P = oop.problem_from_arrays(d)
+    R = 8
+    ores = ogreedy.greedy_solve(P, ogreedy.GreedyOptions(
+        max_rank=R, als_fixed_sweeps=3, galerkin="dense", seed=5, u_method="dense",
+        v_method="dense"))
+    g = connreg.Problem(d, prec, DEV)
+    res = g.greedy_solve(max_rank=R, als_fixed_sweeps=3, pcg_rtol=1e-13, pcg_maxit=20000,
+                         galerkin_rtol=1e-13, galerkin_maxit=20000, seed=5)
+    g.close()
+    assert res["rank"] == R
+    U, V, Z = np_(res["U"]), np_(res["V"]), np_(res["Z"])
+    err = _wdiff(U, Z, V, ores.U, ores.Z, ores.V)
+    assert err <= tol, err
+    for hg, ho in zip(res["history"], ores.history):
+        assert abs(hg["relres"] - ho["relres"]) <= (1e-5 if prec == "fp64" else 1e-3) * ho["relres"]
+
+
 def test_greedy_full_rank_exact():
     d = synth.box_problem(box_y=(4, 3, 3), box_x=(4, 3, 3), offset=(0, 0, 0), n_inj=5, sigma=1.0,
                           hole_r=1.0, wt_rank=3, wt_w=(1.5, 3.0), lam=5.0, seed=2)
