@@ -1718,80 +1718,11 @@ struct Ctx {
 };
 
 // ===================================================================== create / destroy
-// Rows of L^2: the two-barrier PCG's tables, and the ring-2 window tables of
-// the fused operator sweep (each left null when some row of L^2 or some
-// tile's window does not fit; the PCG then takes three barriers per
-// iteration, the operator application two stencil passes).  Row i of L = K I - N (N: the self-padded neighbour
-// table) has the diagonal K - #self slots and -1 per present neighbour; row
-// i of L^2 is the sum over the entries (m, a) of row i of L of a times row m.
+// Rows of L^2 for the two-barrier PCG and the fused operator sweep
+// (ring2_tables); each set is uploaded only when every row or tile fits.
 static cr_status build_win2(Geom& g, const std::vector<int32_t>& nbr, bool target,
                             hipStream_t st) {
-  const int64_t n = g.n;
   const int K = g.K;
-  if (K > W2_NL - 1 || n == 0) return CR_OK;
-  // row i of L as (column, coefficient), the diagonal first
-  auto lrow = [&](int64_t i, int32_t* col, int* cf) {
-    int m = 1, self = 0;
-    col[0] = (int32_t)i;
-    for (int k = 0; k < K; ++k) {
-      const int32_t j = nbr[(size_t)k * n + i];
-      if (j == (int32_t)i) {
-        ++self;
-      } else {
-        col[m] = j;
-        cf[m] = -1;
-        ++m;
-      }
-    }
-    cf[0] = K - self;
-    return m;
-  };
-  // every voxel's entries as (voxel, c2, c1): 0..W2_NL-1 the support of its
-  // row of L (with c1), padded with the voxel itself; the rest of its row of
-  // L^2 after them, padded the same way
-  std::vector<int32_t> ecol((size_t)W2_NE * n);
-  std::vector<int8_t> ec2((size_t)W2_NE * n), ec1((size_t)W2_NE * n);
-  int32_t scol[W2_NE];
-  int sc2[W2_NE], sc1[W2_NE];
-  int32_t ci[W2_NL], cm[W2_NL];
-  int fi[W2_NL], fm[W2_NL];
-  for (int64_t i = 0; i < n; ++i) {
-    const int mi = lrow(i, ci, fi);
-    int ne = W2_NL;
-    for (int a = 0; a < W2_NL; ++a) {
-      scol[a] = a < mi ? ci[a] : (int32_t)i;
-      sc1[a] = a < mi ? fi[a] : 0;
-      sc2[a] = 0;
-    }
-    for (int a = 0; a < mi; ++a) {
-      const int mm = lrow(ci[a], cm, fm);
-      for (int b = 0; b < mm; ++b) {
-        const int32_t j = cm[b];
-        int q = -1;
-        for (int e = 0; e < ne && q < 0; ++e)
-          if (scol[e] == j && (e < mi || e >= W2_NL)) q = e;
-        if (q < 0) {
-          if (ne == W2_NE) return CR_OK;  // row of L^2 too wide: no tables
-          q = ne++;
-          scol[q] = j;
-          sc1[q] = 0;
-          sc2[q] = 0;
-        }
-        sc2[q] += fi[a] * fm[b];
-      }
-    }
-    for (int e = ne; e < W2_NE; ++e) {
-      scol[e] = (int32_t)i;
-      sc1[e] = 0;
-      sc2[e] = 0;
-    }
-    for (int e = 0; e < W2_NE; ++e) {
-      if (sc2[e] < -128 || sc2[e] > 127) return CR_OK;
-      ecol[(size_t)i * W2_NE + e] = scol[e];
-      ec2[(size_t)i * W2_NE + e] = (int8_t)sc2[e];
-      ec1[(size_t)i * W2_NE + e] = (int8_t)sc1[e];
-    }
-  }
   // the two-barrier PCG's tables, by default for the target geometry (the
   // u-systems) only.  The v-systems' low-rank term needs the sums of all
   // workgroups' X^T z partials in every workgroup, which read more than the
@@ -1808,81 +1739,26 @@ static cr_status build_win2(Geom& g, const std::vector<int32_t>& nbr, bool targe
                                (std::strcmp(r2env, "u") == 0 && target) ||
                                (std::strcmp(r2env, "v") == 0 && !target))
                             : (target && K == 6);
+  const Ring2Host h = ring2_tables(g.n, K, nbr.data(), r2want);
+  if (!h.rows) return CR_OK;
   if (r2want) {
-    std::vector<int32_t> ridx((size_t)R2_NX * n);
-    std::vector<int8_t> rcf((size_t)R2_NC * n, 0);
-    for (int64_t i = 0; i < n; ++i) {
-      const size_t o = (size_t)i * W2_NE;
-      rcf[(size_t)i] = ec2[o];
-      for (int k = 0; k < K; ++k) {
-        const int32_t j = nbr[(size_t)k * n + i];
-        int8_t c = 0;
-        if (j != (int32_t)i)
-          for (int e = 1; e < W2_NL; ++e)
-            if (ecol[o + e] == j && ec1[o + e] != 0) c = ec2[o + e];
-        rcf[(size_t)(1 + k) * n + i] = c;
-      }
-      for (int e = 0; e < R2_NX; ++e) {
-        ridx[(size_t)e * n + i] = ecol[o + W2_NL + e];
-        rcf[(size_t)(R2_C0 + e) * n + i] = ec2[o + W2_NL + e];
-      }
-    }
-    if (hipMalloc(&g.r2idx, sizeof(int32_t) * ridx.size()) != hipSuccess ||
-        hipMalloc(&g.r2cf, rcf.size()) != hipSuccess) {
+    if (hipMalloc(&g.r2idx, sizeof(int32_t) * h.r2idx.size()) != hipSuccess ||
+        hipMalloc(&g.r2cf, h.r2cf.size()) != hipSuccess) {
       set_error("device allocation of the L^2 row tables failed");
       return CR_ENOMEM;
     }
-    CR_HIP(stage_to_device(g.r2idx, ridx.data(), sizeof(int32_t) * ridx.size(), st));
-    CR_HIP(stage_to_device(g.r2cf, rcf.data(), rcf.size(), st));
+    CR_HIP(stage_to_device(g.r2idx, h.r2idx.data(), sizeof(int32_t) * h.r2idx.size(), st));
+    CR_HIP(stage_to_device(g.r2cf, h.r2cf.data(), h.r2cf.size(), st));
   }
-  // window tables of the fused operator sweep
-  auto pack = [](int pos, int c2, int c1) {
-    return (uint32_t)pos | ((uint32_t)(uint8_t)(int8_t)c2 << 16) |
-           ((uint32_t)(uint8_t)(int8_t)c1 << 24);
-  };
-  const int64_t nt2 = (n + W2_TILE - 1) / W2_TILE;
-  std::vector<uint32_t> ent((size_t)W2_NE * n);
-  std::vector<int32_t> tab((size_t)nt2 * W2_TAB, 0);
-  std::vector<int32_t> idx;
-  for (int64_t t = 0; t < nt2; ++t) {
-    const int64_t t0 = t * W2_TILE, t1 = std::min(n, t0 + W2_TILE);
-    idx.assign(ecol.begin() + (size_t)t0 * W2_NE, ecol.begin() + (size_t)t1 * W2_NE);
-    std::sort(idx.begin(), idx.end());
-    idx.erase(std::unique(idx.begin(), idx.end()), idx.end());
-    int32_t* it = tab.data() + t * W2_TAB;
-    int nint = 0, tot = 0;
-    size_t a = 0;
-    while (a < idx.size()) {
-      size_t b = a;
-      while (b + 1 < idx.size() && idx[b + 1] - idx[b] <= W2_GAP) ++b;
-      if (nint == W2_NI) return CR_OK;
-      it[2 + nint] = idx[a];
-      it[2 + W2_NI + nint] = tot;
-      tot += idx[b] - idx[a] + 1;
-      ++nint;
-      a = b + 1;
+  if (h.windows) {
+    if (hipMalloc(&g.w2tab, sizeof(int32_t) * h.w2tab.size()) != hipSuccess ||
+        hipMalloc(&g.w2ent, sizeof(uint32_t) * h.w2ent.size()) != hipSuccess) {
+      set_error("device allocation of the ring-2 window tables failed");
+      return CR_ENOMEM;
     }
-    if (tot > W2_MAX) return CR_OK;
-    it[0] = nint;
-    it[1] = tot;
-    auto pos = [&](int32_t j) {
-      int q = 0;
-      while (q + 1 < nint && it[2 + q + 1] <= j) ++q;
-      return it[2 + W2_NI + q] + (j - it[2 + q]);
-    };
-    for (int64_t i = t0; i < t1; ++i) {
-      const size_t o = (size_t)i * W2_NE;
-      for (int e = 0; e < W2_NE; ++e)
-        ent[(size_t)e * n + i] = pack(pos(ecol[o + e]), ec2[o + e], ec1[o + e]);
-    }
+    CR_HIP(stage_to_device(g.w2tab, h.w2tab.data(), sizeof(int32_t) * h.w2tab.size(), st));
+    CR_HIP(stage_to_device(g.w2ent, h.w2ent.data(), sizeof(uint32_t) * h.w2ent.size(), st));
   }
-  if (hipMalloc(&g.w2tab, sizeof(int32_t) * tab.size()) != hipSuccess ||
-      hipMalloc(&g.w2ent, sizeof(uint32_t) * ent.size()) != hipSuccess) {
-    set_error("device allocation of the ring-2 window tables failed");
-    return CR_ENOMEM;
-  }
-  CR_HIP(stage_to_device(g.w2tab, tab.data(), sizeof(int32_t) * tab.size(), st));
-  CR_HIP(stage_to_device(g.w2ent, ent.data(), sizeof(uint32_t) * ent.size(), st));
   return CR_OK;
 }
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/connreg.h"
+#include "ring2.hpp"
 
 namespace cr {
 
@@ -80,16 +81,7 @@ constexpr int NT = 256;  // threads per workgroup for streaming kernels
 constexpr int WIN_NI = 16, WIN_MAX = 2048, WIN_GAP = 32;
 constexpr int WIN_TAB = 2 + 2 * WIN_NI;  // count, total, starts, LDS prefixes
 
-// Ring-2 window form (the fused sweep writing L w and L^2 w together): per
-// tile of W2_TILE consecutive voxels, the voxels that its rows of L^2 read, as
-// at most W2_NI intervals of total length at most W2_MAX; per voxel, W2_NE
-// packed entries (window position in bits 0-15, the L^2 coefficient in bits
-// 16-23 and the L coefficient in bits 24-31, both signed 8-bit): entries
-// 0..6 are the voxel and its present neighbours (the support of its row of
-// L, padded with the voxel and zero coefficients), entries 7..24 the rest of
-// its row of L^2 (padded the same way).  Built for stencil widths K <= 6.
-constexpr int W2_TILE = 64, W2_NI = 12, W2_MAX = 1024, W2_GAP = 32, W2_NE = 25, W2_NL = 7;
-constexpr int W2_TAB = 2 + 2 * W2_NI;  // count, total, starts, LDS prefixes
+// (the ring-2 forms of L^2, W2_* and R2_*, are defined in ring2.hpp)
 
 struct Geom {
   int64_t n = 0;
@@ -102,15 +94,11 @@ struct Geom {
   // ring-2 window tables (null when some tile's window or row does not fit):
   int32_t* w2tab = nullptr;   // device, ceil(n / W2_TILE) * W2_TAB
   uint32_t* w2ent = nullptr;  // device, W2_NE * n (entry e of voxel i at e * n + i)
-  // rows of L^2 for the two-barrier PCG (null when some row does not fit):
-  // r2idx[e * n + i] (e < R2_NX): the voxels of row i of L^2 outside the
-  // support of row i of L (padded with i); r2cf[e * n + i]: the L^2
-  // coefficients, e = 0 the diagonal, 1 + k the neighbour in slot k of the
-  // ELL table (0 for a self-padded slot), R2_C0 + e that of r2idx entry e
+  // rows of L^2 for the two-barrier PCG (null when not built or some row
+  // does not fit)
   int32_t* r2idx = nullptr;  // device, R2_NX * n
   int8_t* r2cf = nullptr;    // device, R2_NC * n
 };
-constexpr int R2_NX = W2_NE - W2_NL, R2_C0 = W2_NL, R2_NC = W2_NE;
 
 // A column-block list: columns [col0, col0+ncols) of the logical matrix live
 // at p + (c-col0)*ld.  Up to 6 blocks, passed by value to kernels.
