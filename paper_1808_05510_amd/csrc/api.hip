@@ -1728,17 +1728,12 @@ static cr_status build_win2(Geom& g, const std::vector<int32_t>& nbr, bool targe
   // workgroups' X^T z partials in every workgroup, which read more than the
   // third barrier costs (40^3 / 30^3 FP64 solve: 2.39 s with three barriers,
   // 2.34 s with the two-barrier u-systems, 3.01 s with both).
-  // The default also leaves out 2-D maps (K = 4): on the top view to rank
-  // 1000 the two-barrier u-systems were faster per iteration (14.4 against
-  // 14.7 s to rank 250) but the late ranks took 8.6% more PCG iterations in
-  // all (4.30 against 3.96 million; 88.8 against 84.0 s in FP64), while the
-  // 3-D workloads' counts agree to within 0.1%.
-  // CONNREG_PCG_R2: 0 none, u target, v source, 1 both (default: target, K 6)
+  // CONNREG_PCG_R2: 0 none, u (default) target, v source, 1 both
   const char* r2env = std::getenv("CONNREG_PCG_R2");
-  const bool r2want = r2env ? (std::strcmp(r2env, "1") == 0 ||
-                               (std::strcmp(r2env, "u") == 0 && target) ||
-                               (std::strcmp(r2env, "v") == 0 && !target))
-                            : (target && K == 6);
+  const char* r2sel = r2env ? r2env : "u";
+  const bool r2want = std::strcmp(r2sel, "1") == 0 ||
+                      (std::strcmp(r2sel, "u") == 0 && target) ||
+                      (std::strcmp(r2sel, "v") == 0 && !target);
   const Ring2Host h = ring2_tables(g.n, K, nbr.data(), r2want);
   if (!h.rows) return CR_OK;
   if (r2want) {
