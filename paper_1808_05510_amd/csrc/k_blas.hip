@@ -1043,9 +1043,11 @@ cr_status masked_tall_gemm(int64_t n, int r, int ninj, const T* U, int64_t ldu, 
 // Product role: wave q owns injections 32q .. 32q + 31 and accumulates
 // (w T)^T over the groups on FP64 (or FP32) MFMA tiles, reading the w
 // fragments from the same LDS window (the tile's own voxels); the masked
-// result is stored once at the end.  w is read from memory once per call
-// (up to L2 re-use of window overlaps between neighbouring tiles) and L w is
-// never re-read, unlike two stencil passes followed by a separate product.
+// result is stored once at the end.  L w is never written and re-read, and
+// the product reads no w of its own; but the windows of neighbouring tiles
+// overlap, and what of them has left L2 is fetched again (on the cortex
+// shells the target pass fetched 4.2 times w and ran slower than the two
+// stencil passes and the product it replaces, so the form is opt-in).
 constexpr int W2_EPT = W2_MAX / NT;  // window elements staged per thread
 
 template <typename T, bool DATA>
