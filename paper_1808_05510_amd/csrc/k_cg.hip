@@ -443,13 +443,15 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
   // Every workgroup also sums all workgroups' X^T z partials itself (in the
   // same order, so the copies of s = X^T p agree bit for bit).
   double u2 = 0.0;
-  double zn1[R2 ? K : 1], z2[R2 ? R2_NX : 1];
+  // gathered in the storage type (FP32 data: half the registers), widened
+  // where they are used
+  T zn1[R2 ? K : 1], z2[R2 ? R2_NX : 1];
   auto r2_load = [&]() {
     if constexpr (R2) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) zn1[k] = ok[0] ? (double)zg[nb[0][k]] : 0.0;
+      for (int k = 0; k < K; ++k) zn1[k] = ok[0] ? zg[nb[0][k]] : (T)0;
 #pragma unroll
-      for (int e = 0; e < R2_NX; ++e) z2[e] = ok[0] ? (double)zg[r2x[e][threadIdx.x]] : 0.0;
+      for (int e = 0; e < R2_NX; ++e) z2[e] = ok[0] ? zg[r2x[e][threadIdx.x]] : (T)0;
       if constexpr (LR) {
         // wave w sums injections w, w + BS/WAVE, ...: every partial load of
         // a lane is issued before the first wave sum
@@ -481,11 +483,12 @@ __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
         double l2 = (double)r2k[0][threadIdx.x] * z[0];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          lz -= zn1[k];
-          l2 += (double)r2k[1 + k][threadIdx.x] * zn1[k];
+          lz -= (double)zn1[k];
+          l2 += (double)r2k[1 + k][threadIdx.x] * (double)zn1[k];
         }
 #pragma unroll
-        for (int e = 0; e < R2_NX; ++e) l2 += (double)r2k[R2_C0 + e][threadIdx.x] * z2[e];
+        for (int e = 0; e < R2_NX; ++e)
+          l2 += (double)r2k[R2_C0 + e][threadIdx.x] * (double)z2[e];
         p[0] = (double)(T)(z[0] + beta * p[0]);
         t[0] = (double)(T)(lz + beta * t[0]);
         u2 = (double)(T)(l2 + beta * u2);
