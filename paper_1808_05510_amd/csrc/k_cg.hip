@@ -222,6 +222,11 @@ __device__ void lr_partial(const PcgArgs<T>& a, const double* zs, int64_t lo, in
 // aggregates (CoarseArg); z = D^-1 r + P Ainv P^T r needs the restricted
 // residual of every workgroup, so each z update takes one more grid barrier
 // (four per iteration).
+// R2 (one voxel per thread, no tail, no coarse level): phase B is folded into
+// phase D, which also carries u = L^2 p by its own recurrence u = L^2 z +
+// beta u from z at the voxels of the thread's row of L^2 (tables in LDS), and
+// every workgroup sums all X^T z partials itself; two grid barriers per
+// iteration.
 template <typename T, int K, bool LR, int VPT, int BS, int NXR, bool XTAIL = false,
           bool CO = false, bool XLDS = false, bool R2 = false>
 __global__ __launch_bounds__(BS) void k_pcg(PcgArgs<T> a) {
