@@ -27,3 +27,15 @@ def test_struct_sizes_match_header(root):
     o = connreg.default_opts()
     assert o.max_rank == 20 and o.als_delta == 0.1 and o.als_max_sweeps == 10
     assert lib.cr_version().startswith(b"libconnreg")
+
+
+def test_missing_library_fails_loudly(root, tmp_path):
+    """Without the built library the binding raises at load (no CPU path)."""
+    import subprocess
+    import sys
+    code = ("from paper_1808_05510_amd import connreg\n"
+            f"connreg.load({str(tmp_path / 'libconnreg.so')!r})\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0
+    assert "is missing" in r.stderr and "no CPU fallback" in r.stderr
